@@ -1,0 +1,286 @@
+"""The oracle's BPMF chain, posterior-propagation stages, aggregation, prediction.
+
+TEST INFRASTRUCTURE ONLY (FP64).  Sweep order and readings:
+
+* r_nd = y_nd - y_bar with y_bar the sequential FP64 mean of the training
+  values; predictions add y_bar back (centering is a reading: the paper does
+  not state it).
+* Stages (Sec. 3.2, eq. stage1, stage2a, stage2b, stage3; Algorithm 1), 0-based
+  block (i, j): stage 1 is (0, 0); stage 2 the blocks with exactly one zero
+  index; stage 3 the rest.  The X side of (i, j) is propagated iff j > 0, from
+  the moment-matched X of block (i, 0); the W side iff i > 0, from the W of
+  block (0, j).  A propagated side takes no Normal-Wishart draw (Sec. 5.1).
+* Initialisation (reading): a propagated side starts at the propagated means;
+  other factors at K^(-1/4) z; hyperparameters (mu, Lambda) = (0, I);
+  tau = tau_fixed, or a0 / b0 when tau is sampled.
+* Sweep t of a block: (a) every row given W, (b) every column given the new X,
+  (c) NW draw for X if not propagated, (d) NW draw for W if not propagated,
+  (e) tau ~ Gamma if sampled, (f) keep the sample if t >= burnin and
+  (t - burnin) % thin == 0.
+* Moment matching at the end of a stage (Sec. 4.1): per-row mean and inverse
+  sample covariance (1/(S-1) normaliser, ridge when S <= K or not SPD).
+* Aggregation (Sec. 4.2, eq. post_marg_aggregation and Algorithm 2): for the
+  rows of row block i the base is block (i, 0) and the siblings are (i, j),
+  j >= 1; for a column block j the base is (0, j) and the siblings (i, j),
+  i >= 1.  A sibling whose difference to the base is not SPD is corrected by
+  (|lambda_min| + eps) I with eps = 1e-6 tr(Lambda_base) / K (the "small
+  constant" is a reading).  With no siblings, mu* is the base mean itself.
+* Prediction (Sec. 5.2): y_hat = y_bar + mu*_x^T mu*_w with posterior means.
+"""
+import numpy as np
+
+from . import native
+from .native import ptr
+from .plan import Plan, counter_c2, stage_of
+
+
+def nw_scale_inverse(W0):
+    L = native.cholesky(W0)
+    if L is None:
+        raise ValueError("W0 must be SPD")
+    Li = np.linalg.solve(L, np.eye(W0.shape[0]))
+    return np.ascontiguousarray(Li.T @ Li)
+
+
+class Oracle:
+    def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
+                 nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
+                 seed=0, burnin=0, thin=1, nthreads=0):
+        self.N, self.D, self.K = int(N), int(D), int(K)
+        self.I, self.J = int(I), int(J)
+        self.seed = int(seed)
+        self.mu0 = np.zeros(K) if mu0 is None else np.asarray(mu0, dtype=np.float64).copy()
+        self.beta0 = float(beta0)
+        self.nu0 = float(K if nu0 is None else nu0)
+        W0 = np.eye(K) if W0 is None else np.asarray(W0, dtype=np.float64)
+        self.W0inv = nw_scale_inverse(W0)
+        self.sample_tau = bool(sample_tau)
+        self.a0, self.b0, self.tau_fixed = float(tau_a0), float(tau_b0), float(tau_fixed)
+        self.burnin, self.thin = int(burnin), int(thin)
+        self.nthreads = int(nthreads)
+        val = np.asarray(val, dtype=np.float32)
+        self.ybar = native.seq_mean(val)
+        self.plan = Plan(N, D, row, col, I, J, order, seed)
+        r = val.astype(np.float64) - self.ybar
+        self.blocks = []
+        for b, pb in enumerate(self.plan.blocks):
+            blk = dict(pb)
+            blk["b"] = b
+            blk["stage"] = stage_of(pb["i"], pb["j"])
+            blk["csr_val"] = np.ascontiguousarray(r[pb["csr_entry"]])
+            blk["csc_val"] = np.ascontiguousarray(r[pb["csc_entry"]])
+            blk["x_prop"] = pb["j"] > 0
+            blk["w_prop"] = pb["i"] > 0
+            self.blocks.append(blk)
+        self.stage = 0
+        self.mm = {}          # block -> dict(x_mu, x_Lam, w_mu, w_Lam, ridged)
+
+    # ------------------------------------------------------------------ stages
+    def stage_blocks(self, s):
+        return [blk for blk in self.blocks if blk["stage"] == s]
+
+    def begin_stage(self, s):
+        K = self.K
+        for blk in self.stage_blocks(s):
+            b, i, j = blk["b"], blk["i"], blk["j"]
+            if blk["x_prop"]:
+                src = self.mm[i * self.J + 0]
+                blk["x_prior"] = (src["x_Lam"], src["x_mu"])
+                blk["X"] = src["x_mu"].copy()
+            else:
+                blk["x_prior"] = None
+                X = np.zeros((blk["R"], K))
+                native.lib().orc_init_side(blk["R"], K, self.seed, counter_c2(b, "INIT_X"), ptr(X))
+                blk["X"] = X
+            if blk["w_prop"]:
+                src = self.mm[0 * self.J + j]
+                blk["w_prior"] = (src["w_Lam"], src["w_mu"])
+                blk["W"] = src["w_mu"].copy()
+            else:
+                blk["w_prior"] = None
+                W = np.zeros((blk["C"], K))
+                native.lib().orc_init_side(blk["C"], K, self.seed, counter_c2(b, "INIT_W"), ptr(W))
+                blk["W"] = W
+            blk["hx"] = (np.eye(K), np.zeros(K))      # (Lambda_X, mu_X)
+            blk["hw"] = (np.eye(K), np.zeros(K))
+            blk["tau"] = self.a0 / self.b0 if self.sample_tau else self.tau_fixed
+            blk["t"] = 0
+            blk["samples_x"] = []
+            blk["samples_w"] = []
+        self.stage = s
+
+    # -------------------------------------------------------------- sub-steps
+    def update_rows(self, blk, t=None):
+        t = blk["t"] if t is None else t
+        self._update(blk, "rows", t)
+
+    def update_cols(self, blk, t=None):
+        t = blk["t"] if t is None else t
+        self._update(blk, "cols", t)
+
+    def _update(self, blk, which, t):
+        K = self.K
+        if which == "rows":
+            n, ptr_, idx, val = blk["R"], blk["csr_ptr"], blk["csr_idx"], blk["csr_val"]
+            other, prop, hyp, purpose, key = blk["W"], blk["x_prior"], blk["hx"], "ROW", "X"
+        else:
+            n, ptr_, idx, val = blk["C"], blk["csc_ptr"], blk["csc_idx"], blk["csc_val"]
+            other, prop, hyp, purpose, key = blk["X"], blk["w_prior"], blk["hw"], "COL", "W"
+        if prop is not None:
+            P = np.ascontiguousarray(prop[0])
+            m = np.ascontiguousarray(prop[1])
+            per_row = 1
+        else:
+            P = np.ascontiguousarray(hyp[0])
+            m = np.ascontiguousarray(hyp[1])
+            per_row = 0
+        out = blk[key].copy()
+        other = np.ascontiguousarray(other)
+        fails = native.lib().orc_update_side(
+            n, K, ptr(ptr_), ptr(idx), ptr(val), ptr(other), per_row, ptr(P), ptr(m),
+            float(blk["tau"]), self.seed, t & 0xFFFFFFFF, counter_c2(blk["b"], purpose),
+            ptr(out), self.nthreads)
+        if fails:
+            raise FloatingPointError("oracle: %d non-SPD conditional precisions" % fails)
+        blk[key] = out
+
+    def hyper_draw(self, blk, side, t=None):
+        t = blk["t"] if t is None else t
+        K = self.K
+        X = np.ascontiguousarray(blk["X"] if side == "x" else blk["W"])
+        Lam = np.zeros((K, K))
+        mu = np.zeros(K)
+        purpose = "HYPER_X" if side == "x" else "HYPER_W"
+        rc = native.lib().orc_nw_draw(X.shape[0], K, ptr(X), ptr(self.mu0), self.beta0, self.nu0,
+                                      ptr(self.W0inv), self.seed, t & 0xFFFFFFFF,
+                                      counter_c2(blk["b"], purpose), ptr(Lam), ptr(mu))
+        if rc != 0:
+            raise FloatingPointError("oracle: NW draw failed")
+        blk["hx" if side == "x" else "hw"] = (Lam, mu)
+
+    def sse(self, blk):
+        return native.lib().orc_sse(blk["R"], self.K, ptr(blk["csr_ptr"]), ptr(blk["csr_idx"]),
+                                    ptr(blk["csr_val"]), ptr(np.ascontiguousarray(blk["X"])),
+                                    ptr(np.ascontiguousarray(blk["W"])))
+
+    def tau_draw(self, blk, t=None):
+        t = blk["t"] if t is None else t
+        s = self.sse(blk)
+        blk["tau"] = native.lib().orc_tau_draw(s, blk["M"], self.a0, self.b0, self.seed,
+                                               t & 0xFFFFFFFF, counter_c2(blk["b"], "TAU"))
+
+    def sweep_block(self, blk):
+        t = blk["t"]
+        self.update_rows(blk, t)
+        self.update_cols(blk, t)
+        if not blk["x_prop"]:
+            self.hyper_draw(blk, "x", t)
+        if not blk["w_prop"]:
+            self.hyper_draw(blk, "w", t)
+        if self.sample_tau:
+            self.tau_draw(blk, t)
+        if t >= self.burnin and (t - self.burnin) % self.thin == 0:
+            blk["samples_x"].append(blk["X"].copy())
+            blk["samples_w"].append(blk["W"].copy())
+        blk["t"] = t + 1
+
+    def sweep(self, n=1):
+        for _ in range(n):
+            for blk in self.stage_blocks(self.stage):
+                self.sweep_block(blk)
+
+    # ------------------------------------------------------------ moment match
+    def finalize_stage(self):
+        for blk in self.stage_blocks(self.stage):
+            self.mm[blk["b"]] = self.moment_match(blk)
+
+    def moment_match(self, blk):
+        out = {}
+        ridged = 0
+        for side in ("x", "w"):
+            S = len(blk["samples_" + side])
+            if S < 1:
+                raise RuntimeError("no kept samples in block %d" % blk["b"])
+            smp = np.ascontiguousarray(np.stack(blk["samples_" + side]))
+            R = smp.shape[1]
+            mu = np.zeros((R, self.K))
+            Lam = np.zeros((R, self.K, self.K))
+            if S >= 2:
+                ridged += native.lib().orc_mm(R, self.K, S, ptr(smp), ptr(mu), ptr(Lam))
+            else:
+                mu[:] = smp[0]
+                Lam[:] = np.nan
+            out[side + "_mu"] = mu
+            out[side + "_Lam"] = Lam
+        out["ridged"] = ridged
+        return out
+
+    def run_stage(self, s, nsweeps):
+        self.begin_stage(s)
+        self.sweep(nsweeps)
+        self.finalize_stage()
+
+    def run_pp(self, nsweeps):
+        for s in (1, 2, 3):
+            if self.stage_blocks(s):
+                self.run_stage(s, nsweeps)
+
+    # -------------------------------------------------------------- aggregate
+    def aggregate(self):
+        """Per-row aggregated means (Algorithm 2) for every row and column block."""
+        I, J, K = self.I, self.J, self.K
+        self.mu_x = []
+        self.mu_w = []
+        self.corrections = 0
+        for i in range(I):
+            base = self.mm[i * J + 0]
+            sib = [self.mm[i * J + j] for j in range(1, J)]
+            mu, ncor = aggregate_side(base["x_mu"], base["x_Lam"],
+                                      [s["x_mu"] for s in sib], [s["x_Lam"] for s in sib], K)
+            self.corrections += ncor
+            self.mu_x.append(mu)
+        for j in range(J):
+            base = self.mm[0 * J + j]
+            sib = [self.mm[i * J + j] for i in range(1, I)]
+            mu, ncor = aggregate_side(base["w_mu"], base["w_Lam"],
+                                      [s["w_mu"] for s in sib], [s["w_Lam"] for s in sib], K)
+            self.corrections += ncor
+            self.mu_w.append(mu)
+
+    def predict(self, row, col):
+        p = self.plan
+        row = np.asarray(row, dtype=np.int64)
+        col = np.asarray(col, dtype=np.int64)
+        out = np.empty(row.size, dtype=np.float64)
+        for q in range(row.size):
+            i, n = p.row_block[row[q]], p.row_local[row[q]]
+            j, d = p.col_block[col[q]], p.col_local[col[q]]
+            out[q] = self.ybar + float(np.dot(self.mu_x[i][n], self.mu_w[j][d]))
+        return out
+
+
+def aggregate_side(mu_b, Lam_b, mus, Lams, K):
+    """Algorithm 2 for every row of one side: returns (mu*, #corrections)."""
+    if not mus:
+        return mu_b.copy(), 0
+    R = mu_b.shape[0]
+    Jn = len(mus) + 1
+    out = np.zeros_like(mu_b)
+    ncor = 0
+    for n in range(R):
+        Lb = Lam_b[n]
+        eps = 1e-6 * np.trace(Lb) / K
+        Lstar = (2 - Jn) * Lb
+        rhs = (2 - Jn) * (Lb @ mu_b[n])
+        for mj, Lj in zip(mus, Lams):
+            Dj = Lj[n] - Lb
+            if native.cholesky(Dj) is not None:
+                Lsj = Lj[n]
+            else:
+                lam_min = np.linalg.eigvalsh(Dj)[0]
+                Lsj = Dj + (abs(lam_min) + eps) * np.eye(K) + Lb
+                ncor += 1
+            Lstar = Lstar + Lsj
+            rhs = rhs + Lsj @ mj[n]
+        out[n] = np.linalg.solve(Lstar, rhs)
+    return out, ncor

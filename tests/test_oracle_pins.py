@@ -1,0 +1,501 @@
+"""Pins of the FP64 oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle against a published value, a closed form, a
+library routine or a statistical law, so that a dropped term, a wrong sign or a
+transposed operand in the oracle fails at least one of them.
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import native
+from oracle.bpmf import Oracle, aggregate_side
+from oracle.native import ptr
+from oracle.plan import Plan, counter_c2, part_sizes
+
+import synth
+
+L = native.lib
+
+
+# --------------------------------------------------------------------- Philox
+def test_philox_known_answers(golden_dir):
+    rows = [l.split() for l in open(os.path.join(golden_dir, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = native.philox4x32_10(v[0:4], v[4:6])
+        assert [int(x) for x in out] == v[6:10]
+
+
+def test_philox_batch_matches_single():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(17, 4), dtype=np.uint64).astype(np.uint32)
+    seed = 0x1234_5678_9ABC_DEF0
+    out = native.philox_batch(ctr, seed)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for q in range(17):
+        assert np.array_equal(out[q], native.philox4x32_10(ctr[q], key))
+
+
+def test_u23_exact_and_open_interval():
+    u = L()
+    assert u.orc_u23(0) == 0.5 / 2**23
+    assert u.orc_u23(0x1FF) == 0.5 / 2**23
+    assert u.orc_u23(0xFFFFFFFF) == (2**23 - 0.5) / 2**23
+    # exactly representable in FP32
+    for x in (0, 255, 256, 0x80000000, 0xFFFFFFFF, 123456789):
+        v = u.orc_u23(x)
+        assert float(np.float32(v)) == v
+
+
+# ------------------------------------------------------------------- Normals
+def test_normals_ks_and_moments():
+    z = np.concatenate([native.normals(7, c0, 3, 99, 64) for c0 in range(1000)])
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 5 * np.sqrt(2.0 / z.size)
+
+
+def test_normals_box_muller_layout():
+    # z[4g], z[4g+1] come from (u0, u1); z[4g+2], z[4g+3] from (u2, u3).
+    seed, c0, c1, c2 = 11, 5, 6, 7
+    z = native.normals(seed, c0, c1, c2, 8)
+    for g in range(2):
+        o = native.philox4x32_10([c0, c1, c2, g], [seed, 0])
+        u = [L().orc_u23(int(x)) for x in o]
+        r1, r2 = np.sqrt(-2 * np.log(u[0])), np.sqrt(-2 * np.log(u[2]))
+        assert z[4 * g] ** 2 + z[4 * g + 1] ** 2 == pytest.approx(r1 ** 2, rel=1e-13)
+        assert z[4 * g + 2] ** 2 + z[4 * g + 3] ** 2 == pytest.approx(r2 ** 2, rel=1e-13)
+        assert np.arctan2(z[4 * g + 1], z[4 * g]) % (2 * np.pi) == pytest.approx(
+            2 * np.pi * u[1], rel=1e-12)
+
+
+# --------------------------------------------------------------------- Gamma
+@pytest.mark.parametrize("shape", [0.3, 1.0, 2.5, 17.0, 5000.5])
+def test_gamma_ks(shape):
+    g = np.array([native.gamma(3, c0, 1, 2, shape) for c0 in range(4000)])
+    assert stats.kstest(g, "gamma", args=(shape,)).pvalue > 1e-3
+    assert abs(g.mean() - shape) < 5 * np.sqrt(shape / g.size)
+
+
+def test_chi2_from_gamma():
+    nu = 7.0
+    x = np.array([2.0 * native.gamma(9, c0, 4, 5, nu / 2) for c0 in range(4000)])
+    assert stats.kstest(x, "chi2", args=(nu,)).pvalue > 1e-3
+
+
+# ------------------------------------------------------------- Linear algebra
+def test_cholesky_matches_numpy():
+    rng = np.random.default_rng(1)
+    for K in (1, 2, 5, 16, 33):
+        B = rng.standard_normal((K, K + 3))
+        A = B @ B.T + 0.1 * np.eye(K)
+        np.testing.assert_allclose(native.cholesky(A), np.linalg.cholesky(A), rtol=1e-12,
+                                   atol=1e-12)
+    assert native.cholesky(np.array([[1.0, 2.0], [2.0, 1.0]])) is None
+
+
+# ------------------------------------------------ conditional update (rows)
+def _one_row_update(K, w, r, P, m, tau, seed=5, t=3, c2=77, nrep=1):
+    """nrep identical rows with the same observed set: draws differ only by z."""
+    deg = w.shape[0]
+    ptr_ = np.arange(nrep + 1, dtype=np.int64) * deg
+    idx = np.tile(np.arange(deg, dtype=np.int32), nrep)
+    val = np.tile(np.asarray(r, dtype=np.float64), nrep)
+    out = np.zeros((nrep, K))
+    f = L().orc_update_side(nrep, K, ptr(ptr_), ptr(idx), ptr(val),
+                            ptr(np.ascontiguousarray(w, dtype=np.float64)), 0,
+                            ptr(np.ascontiguousarray(P)), ptr(np.ascontiguousarray(m)),
+                            tau, seed, t, c2, ptr(out), 1)
+    assert f == 0
+    return out
+
+
+def test_update_k1_closed_form():
+    rng = np.random.default_rng(2)
+    w = rng.standard_normal((6, 1))
+    r = rng.standard_normal(6)
+    lam_p, m, tau = 1.7, 0.3, 2.2
+    x = _one_row_update(1, w, r, np.array([[lam_p]]), np.array([m]), tau)[0, 0]
+    Lam = lam_p + tau * np.sum(w[:, 0] ** 2)
+    mu = (lam_p * m + tau * np.sum(r * w[:, 0])) / Lam
+    z = native.normals(5, 0, 3, 77, 1)[0]
+    assert x == pytest.approx(mu + z / np.sqrt(Lam), rel=1e-12, abs=1e-14)
+
+
+def test_update_k2_closed_form():
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal((9, 2))
+    r = rng.standard_normal(9)
+    P = np.array([[2.0, 0.4], [0.4, 1.5]])
+    m = np.array([0.2, -0.7])
+    tau = 1.3
+    x = _one_row_update(2, w, r, P, m, tau)[0]
+    # explicit 2x2 algebra
+    a = P[0, 0] + tau * np.sum(w[:, 0] ** 2)
+    b = P[0, 1] + tau * np.sum(w[:, 0] * w[:, 1])
+    d = P[1, 1] + tau * np.sum(w[:, 1] ** 2)
+    h0 = P[0, 0] * m[0] + P[0, 1] * m[1] + tau * np.sum(r * w[:, 0])
+    h1 = P[1, 0] * m[0] + P[1, 1] * m[1] + tau * np.sum(r * w[:, 1])
+    det = a * d - b * b
+    mu = np.array([d * h0 - b * h1, a * h1 - b * h0]) / det
+    # lower Cholesky factor of [[a, b], [b, d]] and x = mu + L^-T z
+    l11 = np.sqrt(a)
+    l21 = b / l11
+    l22 = np.sqrt(d - l21 ** 2)
+    z = native.normals(5, 0, 3, 77, 2)
+    v1 = z[1] / l22
+    v0 = (z[0] - l21 * v1) / l11
+    np.testing.assert_allclose(x, mu + np.array([v0, v1]), rtol=1e-12, atol=1e-14)
+
+
+def test_update_monte_carlo_moments():
+    rng = np.random.default_rng(4)
+    K, deg, n = 4, 12, 100_000
+    w = rng.standard_normal((deg, K))
+    r = rng.standard_normal(deg)
+    B = rng.standard_normal((K, K))
+    P = B @ B.T + np.eye(K)
+    m = rng.standard_normal(K)
+    tau = 0.8
+    X = _one_row_update(K, w, r, P, m, tau, nrep=n)
+    A = P + tau * w.T @ w
+    Ainv = np.linalg.inv(A)
+    mu = Ainv @ (P @ m + tau * w.T @ r)
+    se = np.sqrt(np.diag(Ainv) / n)
+    assert np.all(np.abs(X.mean(0) - mu) < 5 * se)
+    C = np.cov(X.T)
+    assert np.linalg.norm(C - Ainv) / np.linalg.norm(Ainv) < 0.02
+
+
+def test_update_per_row_prior_equals_shared_when_identical():
+    rng = np.random.default_rng(5)
+    K, R, C = 3, 20, 7
+    ptr_ = np.sort(rng.integers(0, 40, size=R + 1)).astype(np.int64)
+    ptr_[0] = 0
+    idx = rng.integers(0, C, size=ptr_[-1]).astype(np.int32)
+    val = rng.standard_normal(ptr_[-1])
+    W = rng.standard_normal((C, K))
+    B = rng.standard_normal((K, K))
+    P = B @ B.T + np.eye(K)
+    m = rng.standard_normal(K)
+    o1 = np.zeros((R, K))
+    o2 = np.zeros((R, K))
+    L().orc_update_side(R, K, ptr(ptr_), ptr(idx), ptr(val), ptr(W), 0, ptr(P), ptr(m), 1.1, 9, 2,
+                        5, ptr(o1), 2)
+    Pr = np.ascontiguousarray(np.broadcast_to(P, (R, K, K)))
+    mr = np.ascontiguousarray(np.broadcast_to(m, (R, K)))
+    L().orc_update_side(R, K, ptr(ptr_), ptr(idx), ptr(val), ptr(W), 1, ptr(Pr), ptr(mr), 1.1, 9,
+                        2, 5, ptr(o2), 3)
+    assert np.array_equal(o1, o2)
+
+
+# ---------------------------------------------------------- Normal-Wishart
+def test_nw_draw_moments_against_uncentred_footnote_formula():
+    """E[Lambda] = nu* W*, Var[Lambda_ij] = nu* (W*_ij^2 + W*_ii W*_jj), E[mu] = mu*,
+    with W*^-1 written in the footnote's third (uncentred) form."""
+    rng = np.random.default_rng(6)
+    K, Nb = 3, 40
+    X = rng.standard_normal((Nb, K)) * 0.7 + 0.4
+    mu0 = np.array([0.1, -0.2, 0.3])
+    beta0, nu0 = 2.0, 5.0
+    W0 = np.array([[1.0, 0.2, 0.0], [0.2, 2.0, 0.1], [0.0, 0.1, 0.5]])
+    W0inv = np.linalg.inv(W0)
+    ndraw = 20000
+    Lams = np.zeros((ndraw, K, K))
+    mus = np.zeros((ndraw, K))
+    Lm = np.zeros((K, K))
+    mm = np.zeros(K)
+    for t in range(ndraw):
+        rc = L().orc_nw_draw(Nb, K, ptr(X), ptr(mu0), beta0, nu0, ptr(W0inv), 21, t, 1028,
+                             ptr(Lm), ptr(mm))
+        assert rc == 0
+        Lams[t] = Lm
+        mus[t] = mm
+    xbar = X.mean(0)
+    Sunc = X.T @ X / Nb
+    bs = beta0 + Nb
+    mus_ = (beta0 * mu0 + Nb * xbar) / bs
+    Winv = W0inv + Nb * Sunc + beta0 * np.outer(mu0, mu0) - bs * np.outer(mus_, mus_)
+    Ws = np.linalg.inv(Winv)
+    nus = nu0 + Nb
+    mean = nus * Ws
+    var = nus * (Ws ** 2 + np.outer(np.diag(Ws), np.diag(Ws)))
+    se = np.sqrt(var / ndraw)
+    assert np.all(np.abs(Lams.mean(0) - mean) < 5 * se)
+    assert np.allclose(Lams.var(0), var, rtol=0.1)
+    # mu | Lambda ~ N(mu*, (beta* Lambda)^-1): E[mu] = mu*, Cov = E[Lambda^-1] / beta*
+    #   with E[Lambda^-1] = W*^-1 / (nu* - K - 1)
+    cov_mu = Winv / (nus - K - 1) / bs
+    assert np.all(np.abs(mus.mean(0) - mus_) < 5 * np.sqrt(np.diag(cov_mu) / ndraw))
+    assert np.allclose(np.cov(mus.T), cov_mu, rtol=0.08, atol=1e-5)
+
+
+def test_nw_three_footnote_forms_agree_numerically():
+    """The oracle's centred form and the two alternatives of the footnote give the
+    same W*^-1 (checked through the same Bartlett draw, which depends on W*^-1 only)."""
+    rng = np.random.default_rng(7)
+    K, Nb = 4, 25
+    X = rng.standard_normal((Nb, K)) + 1.5
+    mu0 = rng.standard_normal(K)
+    W0inv = np.eye(K) * 0.7
+    beta0, nu0 = 2.0, K
+    Lm = np.zeros((K, K))
+    mm = np.zeros(K)
+    assert L().orc_nw_draw(Nb, K, ptr(X), ptr(mu0), beta0, nu0, ptr(W0inv), 1, 0, 4, ptr(Lm),
+                           ptr(mm)) == 0
+    # Re-derive the same draw from the second footnote form: Bartlett factors are a
+    # deterministic function of the counters, so Lambda = T A A^T T^T must match.
+    xbar = X.mean(0)
+    Sunc = X.T @ X / Nb
+    bs = beta0 + Nb
+    Winv2 = W0inv + Nb * Sunc + beta0 * Nb / bs * np.outer(mu0 - xbar, mu0 - xbar) \
+        - Nb * np.outer(xbar, xbar)
+    R = np.linalg.cholesky(Winv2)
+    T = np.linalg.inv(R).T
+    A = np.zeros((K, K))
+    nus = nu0 + Nb
+    for k in range(1, K + 1):
+        A[k - 1, k - 1] = np.sqrt(2.0 * native.gamma(1, k, 0, 4, 0.5 * (nus - k + 1)))
+    zoff = native.normals(1, 0, 0, 4, K * (K - 1) // 2)
+    q = 0
+    for a in range(1, K):
+        for b in range(a):
+            A[a, b] = zoff[q]
+            q += 1
+    Lam2 = T @ A @ A.T @ T.T
+    np.testing.assert_allclose(Lm, Lam2, rtol=1e-9)
+
+
+# ---------------------------------------------------------------------- tau
+def test_tau_draw_gamma_mean():
+    sse, M, a0, b0 = 37.5, 120, 1.0, 1.0
+    d = np.array([L().orc_tau_draw(sse, M, a0, b0, 5, t, 6) for t in range(20000)])
+    shape, rate = a0 + M / 2, b0 + sse / 2
+    assert abs(d.mean() - shape / rate) < 5 * np.sqrt(shape) / rate / np.sqrt(d.size)
+    assert stats.kstest(d * rate, "gamma", args=(shape,)).pvalue > 1e-3
+
+
+def test_sse_matches_dense_algebra():
+    rng = np.random.default_rng(8)
+    R, C, K = 30, 12, 3
+    Y = rng.standard_normal((R, C))
+    mask = rng.random((R, C)) < 0.4
+    X = rng.standard_normal((R, K))
+    W = rng.standard_normal((C, K))
+    rows, cols = np.nonzero(mask)
+    ptr_ = np.zeros(R + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=R), out=ptr_[1:])
+    s = L().orc_sse(R, K, ptr(ptr_), ptr(cols.astype(np.int32)), ptr(Y[mask].copy()), ptr(X),
+                    ptr(W))
+    assert s == pytest.approx(np.sum(((Y - X @ W.T) ** 2)[mask]), rel=1e-12)
+
+
+# ------------------------------------------------------------ moment matching
+def test_mm_matches_numpy_cov_and_ridge():
+    rng = np.random.default_rng(9)
+    S, R, K = 30, 5, 4
+    smp = rng.standard_normal((S, R, K)) * np.array([1.0, 2.0, 0.5, 1.5]) + 3.0
+    mu = np.zeros((R, K))
+    Lam = np.zeros((R, K, K))
+    assert L().orc_mm(R, K, S, ptr(smp), ptr(mu), ptr(Lam)) == 0
+    for n in range(R):
+        np.testing.assert_allclose(mu[n], smp[:, n].mean(0), rtol=1e-13)
+        np.testing.assert_allclose(Lam[n], np.linalg.inv(np.cov(smp[:, n].T)), rtol=1e-10)
+    # S <= K: ridge with delta = 1e-6 tr / K
+    S2 = 3
+    smp2 = np.ascontiguousarray(smp[:S2])
+    assert L().orc_mm(R, K, S2, ptr(smp2), ptr(mu), ptr(Lam)) == R
+    for n in range(R):
+        C = np.cov(smp2[:, n].T)
+        C = C + (1e-6 * np.trace(C) / K + 1e-300) * np.eye(K)
+        np.testing.assert_allclose(Lam[n], np.linalg.inv(C), rtol=1e-6)
+
+
+# --------------------------------------------------------------- partition
+def test_partition_sizes_pinned_by_paper(golden_dir):
+    for l in open(os.path.join(golden_dir, "partition_ml1m_5x5.txt")):
+        if l.startswith("#") or not l.strip():
+            continue
+        N, D, r, c, rp, cp = map(int, l.split())
+        bs, sizes = part_sizes(N, r)
+        assert bs == rp and sizes[0] == rp and sum(sizes) == N
+        bs, sizes = part_sizes(D, c)
+        assert bs == cp and sizes[0] == cp and sum(sizes) == D
+    with pytest.raises(ValueError):
+        part_sizes(10, 6)          # ceil(10/6)=2 leaves the 6th part empty
+
+
+@pytest.mark.parametrize("order", ["given", "random", "decreasing"])
+def test_plan_brute_force(order):
+    rng = np.random.default_rng(10)
+    N, D, I, J = 23, 17, 3, 2
+    cells = rng.choice(N * D, size=120, replace=False)
+    row, col = cells // D, cells % D
+    p = Plan(N, D, row, col, I, J, order, seed=44)
+    # positions are permutations
+    assert sorted(p.row_pos.tolist()) == list(range(N))
+    assert sorted(p.col_pos.tolist()) == list(range(D))
+    if order == "decreasing":
+        cnt = np.bincount(row, minlength=N)
+        by_pos = cnt[np.argsort(p.row_pos)]
+        assert np.all(np.diff(by_pos) <= 0)
+    if order == "given":
+        assert np.array_equal(p.row_pos, np.arange(N))
+    # brute force: every entry in exactly one block, CSR and CSC transposes
+    tot = 0
+    for blk in p.blocks:
+        i, j = blk["i"], blk["j"]
+        dense = np.zeros((blk["R"], blk["C"]), dtype=int)
+        for e in range(row.size):
+            if p.row_block[row[e]] == i and p.col_block[col[e]] == j:
+                dense[p.row_local[row[e]], p.col_local[col[e]]] += 1
+        assert dense.max(initial=0) <= 1
+        csr = np.zeros_like(dense)
+        for n in range(blk["R"]):
+            cols_n = blk["csr_idx"][blk["csr_ptr"][n]:blk["csr_ptr"][n + 1]]
+            assert np.all(np.diff(cols_n) > 0)
+            csr[n, cols_n] = 1
+        csc = np.zeros_like(dense)
+        for d in range(blk["C"]):
+            rows_d = blk["csc_idx"][blk["csc_ptr"][d]:blk["csc_ptr"][d + 1]]
+            assert np.all(np.diff(rows_d) > 0)
+            csc[rows_d, d] = 1
+        assert np.array_equal(dense, csr) and np.array_equal(dense, csc)
+        tot += blk["M"]
+    assert tot == row.size
+
+
+def test_random_order_uses_philox_keys():
+    N = 50
+    p = Plan(N, 3, np.arange(N) % N, np.zeros(N, dtype=int), 1, 1, "random", seed=99)
+    keys = [int(native.philox4x32_10([n, 0, counter_c2(0xFFFFFF, "PERM_ROW"), 0],
+                                     [99, 0])[0]) for n in range(N)]
+    expected = sorted(range(N), key=lambda n: (keys[n], n))
+    assert [int(x) for x in np.argsort(p.row_pos)] == expected
+
+
+# ----------------------------------------------------------------- aggregation
+def _spd(rng, K, scale=1.0):
+    B = rng.standard_normal((K, K))
+    return scale * (B @ B.T + K * np.eye(K))
+
+
+def test_aggregation_linear_gaussian_exactness():
+    """Theorem 1 with X fixed and Gaussian W: base precision Lambda_W + tau G_0 and
+    sibling precisions Lambda_base + tau G_i aggregate to the full-data posterior."""
+    rng = np.random.default_rng(11)
+    K, R, I, tau = 3, 6, 4, 1.7
+    LamW = _spd(rng, K)
+    m = rng.standard_normal(K)
+    G = [[_spd(rng, K, 0.3) for _ in range(R)] for _ in range(I)]
+    h = [[rng.standard_normal(K) for _ in range(R)] for _ in range(I)]
+    Lb = np.array([LamW + tau * G[0][n] for n in range(R)])
+    eb = [LamW @ m + tau * h[0][n] for n in range(R)]
+    mub = np.array([np.linalg.solve(Lb[n], eb[n]) for n in range(R)])
+    Ls, mus = [], []
+    for i in range(1, I):
+        Li = np.array([Lb[n] + tau * G[i][n] for n in range(R)])
+        mi = np.array([np.linalg.solve(Li[n], Lb[n] @ mub[n] + tau * h[i][n]) for n in range(R)])
+        Ls.append(Li)
+        mus.append(mi)
+    mu_star, ncor = aggregate_side(mub, Lb, mus, Ls, K)
+    assert ncor == 0
+    for n in range(R):
+        Lfull = LamW + tau * sum(G[i][n] for i in range(I))
+        mfull = np.linalg.solve(Lfull, LamW @ m + tau * sum(h[i][n] for i in range(I)))
+        np.testing.assert_allclose(mu_star[n], mfull, rtol=1e-10, atol=1e-12)
+
+
+def test_aggregation_eigen_correction_gives_spd():
+    rng = np.random.default_rng(12)
+    K, R = 4, 5
+    Lb = np.array([_spd(rng, K, 2.0) for _ in range(R)])
+    mub = rng.standard_normal((R, K))
+    # siblings less precise than the base: differences are not PD
+    Ls = [np.array([0.5 * Lb[n] for n in range(R)]) for _ in range(3)]
+    mus = [rng.standard_normal((R, K)) for _ in range(3)]
+    mu, ncor = aggregate_side(mub, Lb, mus, Ls, K)
+    assert ncor == 3 * R
+    for n in range(R):
+        eps = 1e-6 * np.trace(Lb[n]) / K
+        Lstar = -2 * Lb[n]
+        rhs = -2 * Lb[n] @ mub[n]
+        for Lj, mj in zip(Ls, mus):
+            Dj = Lj[n] - Lb[n]
+            Lsj = Dj + (abs(np.linalg.eigvalsh(Dj)[0]) + eps) * np.eye(K) + Lb[n]
+            Lstar += Lsj
+            rhs += Lsj @ mj[n]
+        assert np.linalg.eigvalsh(Lstar)[0] > 0
+        np.testing.assert_allclose(mu[n], np.linalg.solve(Lstar, rhs), rtol=1e-10)
+
+
+def test_aggregation_two_forms_equal_without_correction():
+    """Algorithm 2's (2 - J) form equals eq. post_marg_aggregation when no
+    correction fires."""
+    rng = np.random.default_rng(13)
+    K, R, J = 3, 4, 5
+    Lb = np.array([_spd(rng, K) for _ in range(R)])
+    mub = rng.standard_normal((R, K))
+    Ls = [np.array([Lb[n] + _spd(rng, K, 0.2) for n in range(R)]) for _ in range(J - 1)]
+    mus = [rng.standard_normal((R, K)) for _ in range(J - 1)]
+    mu, ncor = aggregate_side(mub, Lb, mus, Ls, K)
+    assert ncor == 0
+    for n in range(R):
+        Lstar = Lb[n] + sum(Ls[j][n] - Lb[n] for j in range(J - 1))
+        rhs = Lb[n] @ mub[n] + sum(Ls[j][n] @ mus[j][n] - Lb[n] @ mub[n] for j in range(J - 1))
+        np.testing.assert_allclose(mu[n], np.linalg.solve(Lstar, rhs), rtol=1e-10)
+
+
+# ------------------------------------------------------- chain-level checks
+def test_chain_config1_rmse_between_noise_floor_and_column_means():
+    d = synth.config(1, seed=1)
+    o = Oracle(d["N"], d["D"], d["K"], d["row"], d["col"], d["val"], seed=101, burnin=20)
+    o.run_stage(1, 50)
+    o.aggregate()
+    p = o.predict(d["test_row"], d["test_col"])
+    rmse = np.sqrt(np.mean((p - d["test_val"]) ** 2))
+    cnt = np.maximum(np.bincount(d["col"], minlength=d["D"]), 1)
+    cm = np.bincount(d["col"], weights=d["val"], minlength=d["D"]) / cnt
+    rmse_cm = np.sqrt(np.mean((cm[d["test_col"]] - d["test_val"]) ** 2))
+    assert 0.5 < rmse < 0.6 * rmse_cm
+    # tau should approach the true noise precision 1/0.5^2 = 4
+    assert 2.5 < o.blocks[0]["tau"] < 6.0
+
+
+def test_pp_linear_gaussian_monte_carlo():
+    """PP with X frozen at the truth, fixed hyperparameters and tau, partition
+    I x 1: the moment-matched and aggregated W means approach the exact
+    full-data conditional means (Theorem 1) within Monte Carlo error."""
+    rng = np.random.default_rng(14)
+    N, D, K, I = 60, 8, 2, 3
+    X = rng.standard_normal((N, K))
+    Wt = rng.standard_normal((D, K))
+    mask = rng.random((N, D)) < 0.5
+    row, col = np.nonzero(mask)
+    val = (np.sum(X[row] * Wt[col], 1) + 0.5 * rng.standard_normal(row.size)).astype(np.float32)
+    o = Oracle(N, D, K, row, col, val, I=I, J=1, sample_tau=False, tau_fixed=4.0, seed=3,
+               burnin=0, thin=1)
+    nsw = 3000
+    for s in (1, 2):
+        o.begin_stage(s)
+        for blk in o.stage_blocks(s):
+            blk["X"] = np.ascontiguousarray(X[o.plan.row_ids[blk["i"]]])
+            for t in range(nsw):
+                o.update_cols(blk, t)
+                blk["samples_w"].append(blk["W"].copy())
+                blk["samples_x"].append(blk["X"].copy())
+        o.finalize_stage()
+    o.aggregate()
+    r = val.astype(np.float64) - o.ybar
+    for d in range(D):
+        sel = col == d
+        A = np.eye(K) + 4.0 * X[row[sel]].T @ X[row[sel]]
+        mu = np.linalg.solve(A, 4.0 * X[row[sel]].T @ r[sel])
+        got = o.mu_w[0][o.plan.col_local[d]]
+        sd = np.sqrt(np.diag(np.linalg.inv(A)))
+        assert np.all(np.abs(got - mu) < 6 * sd / np.sqrt(nsw) + 0.05 * sd)
