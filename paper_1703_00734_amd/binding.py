@@ -1,0 +1,311 @@
+"""ctypes binding of libbmf.so (argument marshalling only).
+
+Every step of the sweep runs in the HIP library; this module only converts
+numpy/torch arguments to the C ABI declared in include/bmf.h and raises on a
+non-OK status.  There is no Python or CPU fallback: when the library is
+missing, loading fails loudly.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbmf.so")
+
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+ORDER = {"given": 0, "random": 1, "decreasing": 2}
+STEP = {"rows": 0, "cols": 1, "hyper_x": 2, "hyper_w": 3, "tau": 4}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+
+
+class bmf_config(ctypes.Structure):
+    _fields_ = [
+        ("N", _i64), ("D", _i64), ("K", _i32),
+        ("nnz", _i64), ("row", _vp), ("col", _vp), ("val", _vp),
+        ("I", _i32), ("J", _i32), ("order", _i32),
+        ("mu0", _vp), ("beta0", _d), ("nu0", _d), ("W0", _vp),
+        ("sample_tau", _i32), ("tau_a0", _d), ("tau_b0", _d), ("tau_fixed", _d),
+        ("seed", ctypes.c_uint64),
+        ("burnin", _i32), ("thin", _i32), ("max_kept", _i32),
+        ("precision", _i32), ("pivot_theta", _d),
+        ("batched", _i32),
+        ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
+        ("stream", _vp),
+    ]
+
+
+class BMFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+_P = ctypes.POINTER
+
+
+def load():
+    """Load libbmf.so (built by paper_1703_00734_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbmf.so is not built (run paper_1703_00734_amd/build.py); "
+                          "there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    pc = _P(bmf_config)
+    pctx = _P(_vp)
+    sig = {
+        "bmf_config_defaults": [pc],
+        "bmf_workspace_size": [pc, _P(ctypes.c_size_t)],
+        "bmf_init": [pc, pctx],
+        "bmf_init_host": [pc, pctx],
+        "bmf_gibbs_sweep": [_vp, _i32],
+        "bmf_pp_stage": [_vp, _i32, _i32],
+        "bmf_predict": [_vp, _i64, _vp, _vp, _vp],
+        "bmf_free": [_vp],
+        "bmf_block_info": [_vp, _i32, _P(_i64), _P(_i64), _P(_i64), _P(_i32)],
+        "bmf_global_mean": [_vp, _P(_d)],
+        "bmf_get_positions": [_vp, _vp, _vp],
+        "bmf_get_block_csr": [_vp, _i32, _i32, _vp, _vp, _vp],
+        "bmf_get_state": [_vp, _i32, _vp, _vp, _vp, _vp],
+        "bmf_set_state": [_vp, _i32, _vp, _vp, _vp, _vp],
+        "bmf_step": [_vp, _i32, _i32, _i64],
+        "bmf_get_mm": [_vp, _i32, _i32, _vp, _vp],
+        "bmf_get_draw": [_vp, _i32, _i32, _vp],
+        "bmf_aggregate": [_vp],
+        "bmf_get_aggregate": [_vp, _i32, _vp],
+        "bmf_get_stats": [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)],
+        "bmf_enable_timing": [_vp, _i32],
+        "bmf_kernel_times": [_vp, _i32, _vp, _vp, _vp, _P(_i32)],
+        "bmf_stage_work": [_vp, _P(_i64), _P(_i64)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.bmf_last_error.argtypes = [_vp]
+    L.bmf_last_error.restype = ctypes.c_char_p
+    L.bmf_status_string.argtypes = [ctypes.c_int]
+    L.bmf_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_vp) if a is not None else None
+
+
+def exported_symbols():
+    """Names the header declares (checked against the shared object by tests)."""
+    return ["bmf_config_defaults", "bmf_workspace_size", "bmf_init", "bmf_init_host",
+            "bmf_gibbs_sweep", "bmf_pp_stage", "bmf_predict", "bmf_free", "bmf_last_error",
+            "bmf_status_string", "bmf_block_info", "bmf_global_mean", "bmf_get_positions",
+            "bmf_get_block_csr", "bmf_get_state", "bmf_set_state", "bmf_step", "bmf_get_draw", "bmf_get_mm",
+            "bmf_aggregate", "bmf_get_aggregate", "bmf_get_stats", "bmf_enable_timing",
+            "bmf_kernel_times", "bmf_stage_work"]
+
+
+class BMF:
+    """One library context: a COO training set, a partition and its device state.
+
+    device=False builds the host half only (planning and integer work).  On a
+    GPU the workspace is a torch uint8 tensor and work is ordered on torch's
+    current stream (PyTorch supplies memory and the stream, nothing else).
+    """
+
+    def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
+                 nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
+                 seed=0, burnin=0, thin=1, max_kept=1, precision="fp32", pivot_theta=0.0,
+                 batched=True, device=True, stream=None):
+        self.L = load()
+        self.K = int(K)
+        self.N, self.D = int(N), int(D)
+        self._row = np.ascontiguousarray(row, dtype=np.int32)
+        self._col = np.ascontiguousarray(col, dtype=np.int32)
+        self._val = np.ascontiguousarray(val, dtype=np.float32)
+        self._mu0 = None if mu0 is None else np.ascontiguousarray(mu0, dtype=np.float64)
+        self._W0 = None if W0 is None else np.ascontiguousarray(W0, dtype=np.float64)
+        c = bmf_config()
+        self.L.bmf_config_defaults(ctypes.byref(c))
+        c.N, c.D, c.K = self.N, self.D, self.K
+        c.nnz = self._row.size
+        c.row, c.col, c.val = _ptr(self._row), _ptr(self._col), _ptr(self._val)
+        c.I, c.J = int(I), int(J)
+        c.order = ORDER[order] if isinstance(order, str) else int(order)
+        c.mu0 = _ptr(self._mu0)
+        c.beta0 = float(beta0)
+        c.nu0 = float(self.K if nu0 is None else nu0)
+        c.W0 = _ptr(self._W0)
+        c.sample_tau = 1 if sample_tau else 0
+        c.tau_a0, c.tau_b0, c.tau_fixed = float(tau_a0), float(tau_b0), float(tau_fixed)
+        c.seed = int(seed)
+        c.burnin, c.thin, c.max_kept = int(burnin), int(thin), int(max_kept)
+        c.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+        c.pivot_theta = float(pivot_theta)
+        c.batched = 1 if batched else 0
+        self.cfg = c
+        self.ctx = _vp()
+        self.workspace = None
+        if device:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
+            size = ctypes.c_size_t()
+            self._check(self.L.bmf_workspace_size(ctypes.byref(c), ctypes.byref(size)), None)
+            self.workspace = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device="cuda")
+            c.workspace = self.workspace.data_ptr()
+            c.workspace_bytes = int(size.value)
+            s = torch.cuda.current_stream() if stream is None else stream
+            c.stream = s.cuda_stream
+            st = self.L.bmf_init(ctypes.byref(c), ctypes.byref(self.ctx))
+        else:
+            st = self.L.bmf_init_host(ctypes.byref(c), ctypes.byref(self.ctx))
+        self._check(st)
+
+    # ---------------------------------------------------------------- helpers
+    def _check(self, st, ctx=True):
+        if st != 0:
+            msg = self.L.bmf_last_error(self.ctx).decode() if ctx and self.ctx else ""
+            name = self.L.bmf_status_string(st).decode()
+            raise BMFError(name, msg)
+
+    def close(self):
+        if self.ctx:
+            self.L.bmf_free(self.ctx)
+            self.ctx = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ calls
+    def gibbs_sweep(self, n=1):
+        self._check(self.L.bmf_gibbs_sweep(self.ctx, int(n)))
+
+    def pp_stage(self, stage, nsweeps):
+        self._check(self.L.bmf_pp_stage(self.ctx, int(stage), int(nsweeps)))
+
+    def predict(self, row, col):
+        r = np.ascontiguousarray(row, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        out = np.empty(r.size, dtype=np.float32)
+        self._check(self.L.bmf_predict(self.ctx, r.size, _ptr(r), _ptr(c), _ptr(out)))
+        return out
+
+    def nblocks(self):
+        return self.cfg.I * self.cfg.J
+
+    def block_info(self, b):
+        R, C, M = _i64(), _i64(), _i64()
+        s = _i32()
+        self._check(self.L.bmf_block_info(self.ctx, b, ctypes.byref(R), ctypes.byref(C),
+                                          ctypes.byref(M), ctypes.byref(s)))
+        return dict(R=R.value, C=C.value, M=M.value, stage=s.value)
+
+    def global_mean(self):
+        y = _d()
+        self._check(self.L.bmf_global_mean(self.ctx, ctypes.byref(y)))
+        return y.value
+
+    def positions(self):
+        pr = np.empty(self.N, dtype=np.int64)
+        pc = np.empty(self.D, dtype=np.int64)
+        self._check(self.L.bmf_get_positions(self.ctx, _ptr(pr), _ptr(pc)))
+        return pr, pc
+
+    def block_csr(self, b, which):
+        info = self.block_info(b)
+        n = info["R"] if which == 0 else info["C"]
+        ptr = np.empty(n + 1, dtype=np.int64)
+        idx = np.empty(max(info["M"], 1), dtype=np.int32)
+        ent = np.empty(max(info["M"], 1), dtype=np.int64)
+        self._check(self.L.bmf_get_block_csr(self.ctx, b, which, _ptr(ptr), _ptr(idx), _ptr(ent)))
+        return ptr, idx[:info["M"]], ent[:info["M"]]
+
+    def get_state(self, b):
+        info = self.block_info(b)
+        K = self.K
+        X = np.empty((info["R"], K))
+        W = np.empty((info["C"], K))
+        hyp = np.empty(2 * (K * K + K))
+        tau = _d()
+        self._check(self.L.bmf_get_state(self.ctx, b, _ptr(X), _ptr(W), _ptr(hyp),
+                                         ctypes.byref(tau)))
+        hx = (hyp[:K * K].reshape(K, K), hyp[K * K:K * K + K])
+        o = K * K + K
+        hw = (hyp[o:o + K * K].reshape(K, K), hyp[o + K * K:o + K * K + K])
+        return dict(X=X, W=W, hx=hx, hw=hw, tau=tau.value)
+
+    def set_state(self, b, X=None, W=None, hx=None, hw=None, tau=None):
+        K = self.K
+        Xa = None if X is None else np.ascontiguousarray(X, dtype=np.float64)
+        Wa = None if W is None else np.ascontiguousarray(W, dtype=np.float64)
+        hyp = None
+        if hx is not None or hw is not None:
+            cur = self.get_state(b)
+            hx = cur["hx"] if hx is None else hx
+            hw = cur["hw"] if hw is None else hw
+            hyp = np.concatenate([np.ravel(hx[0]), np.ravel(hx[1]), np.ravel(hw[0]),
+                                  np.ravel(hw[1])]).astype(np.float64)
+        t = None if tau is None else ctypes.byref(_d(float(tau)))
+        self._check(self.L.bmf_set_state(self.ctx, b, _ptr(Xa), _ptr(Wa), _ptr(hyp), t))
+
+    def step(self, b, which, t):
+        w = STEP[which] if isinstance(which, str) else int(which)
+        self._check(self.L.bmf_step(self.ctx, int(b), w, int(t)))
+
+    def get_draw(self, b, side):
+        info = self.block_info(b)
+        n = info["R"] if side == 0 else info["C"]
+        x = np.empty((n, self.K))
+        self._check(self.L.bmf_get_draw(self.ctx, b, side, _ptr(x)))
+        return x
+
+    def get_mm(self, b, side):
+        info = self.block_info(b)
+        n = info["R"] if side == 0 else info["C"]
+        mu = np.empty((n, self.K))
+        Lam = np.empty((n, self.K, self.K))
+        self._check(self.L.bmf_get_mm(self.ctx, b, side, _ptr(mu), _ptr(Lam)))
+        return mu, Lam
+
+    def aggregate(self):
+        self._check(self.L.bmf_aggregate(self.ctx))
+
+    def get_aggregate(self, side):
+        n = self.N if side == 0 else self.D
+        mu = np.empty((n, self.K))
+        self._check(self.L.bmf_get_aggregate(self.ctx, side, _ptr(mu)))
+        return mu
+
+    def stats(self):
+        v = [_i64() for _ in range(4)]
+        self._check(self.L.bmf_get_stats(self.ctx, *[ctypes.byref(x) for x in v]))
+        return dict(fallback_rows=v[0].value, nonpd_rows=v[1].value, mm_ridged=v[2].value,
+                    agg_corrections=v[3].value)
+
+    def enable_timing(self, on=True):
+        self._check(self.L.bmf_enable_timing(self.ctx, 1 if on else 0))
+
+    def kernel_times(self):
+        n = 32
+        names = (ctypes.c_char_p * n)()
+        launches = np.zeros(n, dtype=np.int64)
+        ms = np.zeros(n, dtype=np.float64)
+        cnt = _i32()
+        self._check(self.L.bmf_kernel_times(self.ctx, n, ctypes.cast(names, _vp), _ptr(launches),
+                                            _ptr(ms), ctypes.byref(cnt)))
+        return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(cnt.value)}
+
+    def stage_work(self):
+        r, m = _i64(), _i64()
+        self._check(self.L.bmf_stage_work(self.ctx, ctypes.byref(r), ctypes.byref(m)))
+        return r.value, m.value

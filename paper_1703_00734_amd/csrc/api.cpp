@@ -1,0 +1,1443 @@
+// C ABI of the BMF library: context, device layout, stage logic and launches.
+//
+// The host side validates the problem, centres the values, builds the integer
+// plan (ordering, partition, CSR/CSC), the degree-sorted schedules and the
+// per-stage work lists, and drives the kernels on one HIP stream.  Every step
+// of the sweep runs on the device; the host only enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bmf.h"
+#include "common.hpp"
+#include "kernels.hpp"
+#include "planner.hpp"
+
+using namespace bmf;
+
+namespace {
+
+constexpr int32_t kStatsRowsPerJob = 512;   // entities per NW statistics job (about)
+constexpr int32_t kStatsJobsMax = 256;      // jobs per side at most
+constexpr int64_t kPredictChunk = 1 << 20;  // prediction pairs per launch
+constexpr int32_t kFallbackGrid = 512;      // workgroups of the FP64 redo pass
+constexpr int32_t kWaveGridCap = 1 << 20;
+
+enum Counter { kFbRow = 0, kFbCol = 1, kFbTotal = 2, kNonPD = 3, kRidged = 4, kCorr = 5, kNumCounters = 16 };
+
+// Kernel classes for the optional per-launch timing.
+enum KClass { kKRows = 0, kKCols, kKFallback, kKSse, kKStats, kKReduce, kKHyper, kKInit, kKMM, kKAgg, kKPredict, kKFill, kNumK };
+const char *kKNames[kNumK] = {"update_rows", "update_cols", "update_fallback_fp64", "sse", "nw_stats", "reduce",
+                              "hyper_draws", "init", "moment_match", "aggregate", "predict", "fill"};
+
+int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Sizes of everything the device holds, computable from the configuration.
+struct Layout {
+    int32_t K = 0, kc = 0, prec = 0, ks_m = 0, ks_p = 0, prow = 0, hy = 0, npair = 0;
+    int64_t nb = 0, E_r = 0, E_c = 0, Emax = 0, Pmax = 0;
+    int64_t vs = 0, ss = 0, sp = 0;  // value / state / sample element bytes
+    // byte offsets
+    int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, ord, X, W, hyper, tau, mu0,
+        W0inv, mm, agg_x, agg_w, sample, probe, sse_part, sse_final, stats_part, stats_final,
+        counters, fb_list, m_sides, m_tiles, m_reduce,
+        m_items, m_items2, m_stats, m_hyper, m_mmout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
+        p_out, total;
+    int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap;
+};
+
+bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
+    L = Layout();
+    L.K = c.K;
+    L.kc = capacity_for(c.K);
+    L.prec = c.precision;
+    const bool fp64 = c.precision == BMF_PREC_FP64;
+    L.vs = fp64 ? 8 : 4;
+    L.ss = fp64 ? 8 : (c.precision == BMF_PREC_BF16 ? 2 : 4);
+    L.sp = fp64 ? 8 : 4;
+    L.ks_m = stride_for(L.kc, (int32_t)L.ss);
+    L.ks_p = stride_for(L.kc, (int32_t)L.sp);
+    L.prow = c.K * (c.K + 1) / 2 + 2 * c.K;
+    L.hy = c.K * c.K + 2 * c.K;
+    L.npair = c.K + c.K * (c.K + 1) / 2;
+    L.nb = (int64_t)c.I * c.J;
+    L.E_r = (int64_t)c.J * c.N;
+    L.E_c = (int64_t)c.I * c.D;
+    const int64_t bs_r = (c.N + c.I - 1) / c.I, bs_c = (c.D + c.J - 1) / c.J;
+    std::vector<int64_t> R(c.I), C(c.J);
+    for (int32_t i = 0; i < c.I; ++i) R[i] = std::min(bs_r, c.N - i * bs_r);
+    for (int32_t j = 0; j < c.J; ++j) C[j] = std::min(bs_c, c.D - j * bs_c);
+    if (R.back() <= 0 || C.back() <= 0) {
+        err = "partition leaves an empty part";
+        return false;
+    }
+    int64_t er[4] = {0, 0, 0, 0}, ec[4] = {0, 0, 0, 0};
+    for (int32_t i = 0; i < c.I; ++i)
+        for (int32_t j = 0; j < c.J; ++j) {
+            const int s = stage_of(i, j);
+            er[s] += R[i];
+            ec[s] += C[j];
+        }
+    for (int s = 1; s <= 3; ++s) {
+        L.Emax = std::max(L.Emax, er[s] + ec[s]);
+        L.Pmax = std::max(L.Pmax, std::max(er[s], ec[s]));
+    }
+    L.n_tiles_cap = 2 * L.Emax + 8;
+    L.n_items_cap = 2 * L.Emax + 8;
+    L.n_stats_cap = kStatsJobsMax * 2 * L.nb + 8;
+    L.n_sse_cap = L.Emax + 8;
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t o = off;
+        off = align_up(off + std::max<int64_t>(bytes, 1), 256);
+        return o;
+    };
+    const int64_t nnz = c.nnz;
+    L.csr_ptr = take(8 * (L.E_r + L.nb));
+    L.csr_idx = take(4 * nnz);
+    L.csr_val = take(L.vs * nnz);
+    L.csc_ptr = take(8 * (L.E_c + L.nb));
+    L.csc_idx = take(4 * nnz);
+    L.csc_val = take(L.vs * nnz);
+    L.ord = take(4 * (L.E_r + L.E_c));
+    L.X = take(L.ss * L.E_r * L.ks_m);
+    L.W = take(L.ss * L.E_c * L.ks_m);
+    L.hyper = take(8 * L.nb * 2 * L.hy);
+    L.tau = take(8 * L.nb);
+    L.mu0 = take(8 * c.K);
+    L.W0inv = take(8 * c.K * c.K);
+    L.mm = take(8 * (L.E_r + L.E_c) * L.prow);
+    L.agg_x = take(8 * c.N * c.K);
+    L.agg_w = take(8 * c.D * c.K);
+    L.sample = take(L.sp * (int64_t)c.max_kept * L.Emax * L.ks_p);
+    L.probe = take(L.sp * L.Emax * L.ks_p);
+    L.sse_part = take(8 * L.n_sse_cap);
+    L.sse_final = take(8 * L.nb);
+    L.stats_part = take(8 * L.n_stats_cap * L.npair);
+    L.stats_final = take(8 * 2 * L.nb * L.npair);
+    L.counters = take(4 * kNumCounters);
+    L.fb_list = take(8 * (L.Pmax + 8));
+    L.m_sides = take(sizeof(SideDesc) * 2 * L.nb);
+    L.m_tiles = take(sizeof(Tile) * L.n_tiles_cap);
+    L.m_reduce = take(sizeof(ReduceJob) * (3 * L.nb + 8));
+    L.m_items = take(sizeof(int2) * L.n_items_cap);
+    L.m_items2 = take(sizeof(int2) * (L.Emax + 8));
+    L.m_stats = take(sizeof(StatsJob) * L.n_stats_cap);
+    L.m_hyper = take(sizeof(HyperJob) * 3 * L.nb);
+    L.m_mmout = take(sizeof(double *) * 2 * L.nb);
+    L.m_agg_jobs = take(sizeof(AggJob) * (c.I + c.J));
+    L.m_agg_items = take(sizeof(int2) * (c.N + c.D));
+    L.p_xslot = take(8 * kPredictChunk);
+    L.p_wslot = take(8 * kPredictChunk);
+    L.p_out = take(4 * kPredictChunk);
+    L.total = off;
+    return true;
+}
+
+// Work lists of one stage (host copies of what is uploaded).
+struct StageLists {
+    std::vector<int32_t> blocks;                    // global block ids in the stage
+    std::vector<SideDesc> sides;                    // rows of blocks[k] at k, columns at nbs + k
+    // register kernel tiles: [rows grouped by block | rows heavy-first | cols grouped | cols heavy]
+    std::vector<Tile> tiles;
+    int64_t t_row_blk = 0, t_row_heavy = 0, t_col_blk = 0, t_col_heavy = 0, t_end = 0;
+    std::vector<int64_t> row_tile_begin, col_tile_begin;   // per block k, within the grouped lists
+    // wave kernel items, same four lists
+    std::vector<int2> items;
+    int64_t i_row_blk = 0, i_row_heavy = 0, i_col_blk = 0, i_col_heavy = 0, i_end = 0;
+    std::vector<int64_t> row_item_begin, col_item_begin;
+    std::vector<int2> ents;                         // every (side, entity) of the stage
+    std::vector<StatsJob> stats;
+    std::vector<int64_t> side_stats_begin;          // per side, into stats (size 2*nbs + 1)
+    std::vector<HyperJob> hyper;
+    std::vector<int32_t> hyper_begin;               // per block k: first hyper job; size nbs + 1
+    std::vector<int32_t> hyper_kind;                // kind of each job
+    std::vector<int64_t> sse_tile_begin;            // SSE tiles per block (== row tiles grouped)
+    int64_t row_ents = 0, col_ents = 0;
+    int64_t row_updates = 0, ratings = 0;
+};
+
+}  // namespace
+
+struct bmf_ctx {
+    bmf_config cfg{};
+    std::string err;
+    bool device = false;
+    hipStream_t stream = nullptr;
+    Layout L;
+    Plan plan;
+    double ybar = 0.0;
+    std::vector<double> mu0, W0inv;
+    // host offsets per block
+    std::vector<int64_t> csr_ptr_off, csc_ptr_off, x_off, w_off, ord_row_off, ord_col_off;
+    // device memory
+    char *base = nullptr;
+    bool own = false;
+    // stage state
+    int32_t stage = 0;          // active stage, 0 = none
+    int32_t finalized = 0;      // highest stage whose moment matching is done
+    int64_t t = 0;              // sweeps run in the active stage
+    int32_t kept = 0;
+    bool agg_valid = false;
+    StageLists S;
+    int32_t done_stages[4] = {0, 0, 0, 0};
+    // timing
+    bool timing = false;
+    struct Pending { int32_t k; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    int64_t tlaunch[kNumK] = {0};
+    double tms[kNumK] = {0};
+
+    template <typename T> T *dev(int64_t off) { return reinterpret_cast<T *>(base + off); }
+    bool bf() const { return cfg.precision == BMF_PREC_BF16; }
+    bool fp64() const { return cfg.precision == BMF_PREC_FP64; }
+    int32_t prec() const { return cfg.precision == BMF_PREC_FP64 ? kP64 : (bf() ? kPBF : kP32); }
+    bool reg() const { return L.kc <= 16; }
+};
+
+namespace {
+
+bmf_status fail(bmf_ctx *c, bmf_status s, const std::string &m) {
+    if (c) c->err = m;
+    return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(ctx, BMF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+// Timed launch wrapper: records events around the launch when timing is on.
+template <typename F>
+bmf_status timed(bmf_ctx *c, int32_t k, F &&launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (c->timing) {
+        HIPCHK(c, hipEventCreate(&a));
+        HIPCHK(c, hipEventCreate(&b));
+        HIPCHK(c, hipEventRecord(a, c->stream));
+    }
+    const hipError_t e = launch();
+    if (e != hipSuccess) return fail(c, BMF_EDEVICE, std::string(kKNames[k]) + ": " + hipGetErrorString(e));
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(b, c->stream));
+        c->pending.push_back({k, a, b});
+    }
+    return BMF_OK;
+}
+
+bool spd_cholesky(int K, const double *A, std::vector<double> &L) {
+    L.assign((size_t)K * K, 0.0);
+    for (int i = 0; i < K; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * K + j];
+            for (int p = 0; p < j; ++p) s -= L[i * K + p] * L[j * K + p];
+            if (i == j) {
+                if (!(s > 0.0)) return false;
+                L[i * K + i] = std::sqrt(s);
+            } else {
+                L[i * K + j] = s / L[j * K + j];
+            }
+        }
+    return true;
+}
+
+bmf_status validate(const bmf_config *cfg, std::string &err) {
+    if (!cfg) { err = "null config"; return BMF_EINVAL; }
+    const bmf_config &c = *cfg;
+    if (c.N <= 0 || c.D <= 0) { err = "N and D must be positive"; return BMF_EINVAL; }
+    if (c.N > (int64_t)INT32_MAX || c.D > (int64_t)INT32_MAX) { err = "N, D must fit int32"; return BMF_EUNSUPPORTED; }
+    if (c.K < 1) { err = "K must be >= 1"; return BMF_EINVAL; }
+    if (c.K > 64) { err = "K > 64 is not supported"; return BMF_EUNSUPPORTED; }
+    if (c.nnz < 0 || (c.nnz > 0 && (!c.row || !c.col || !c.val))) { err = "bad COO arrays"; return BMF_EINVAL; }
+    if (c.nnz > (int64_t)INT32_MAX) { err = "nnz must fit int32"; return BMF_EUNSUPPORTED; }
+    if (c.I < 1 || c.J < 1 || c.I > c.N || c.J > c.D) { err = "bad partition"; return BMF_EINVAL; }
+    if (c.I > 65 || c.J > 65) { err = "at most 65 parts per dimension"; return BMF_EUNSUPPORTED; }
+    if (c.order < BMF_ORDER_GIVEN || c.order > BMF_ORDER_DECREASING) { err = "bad order"; return BMF_EINVAL; }
+    if (!(c.beta0 > 0.0)) { err = "beta0 must be > 0"; return BMF_EINVAL; }
+    if (!(c.nu0 > c.K - 1)) { err = "nu0 must be > K - 1"; return BMF_EINVAL; }
+    if (c.sample_tau) {
+        if (!(c.tau_a0 > 0.0) || !(c.tau_b0 > 0.0)) { err = "tau prior must be positive"; return BMF_EINVAL; }
+    } else if (!(c.tau_fixed > 0.0) || !std::isfinite(c.tau_fixed)) {
+        err = "tau_fixed must be positive";
+        return BMF_EINVAL;
+    }
+    if (c.burnin < 0 || c.thin < 1 || c.max_kept < 1) { err = "bad burnin/thin/max_kept"; return BMF_EINVAL; }
+    if (c.precision < BMF_PREC_FP64 || c.precision > BMF_PREC_BF16) { err = "bad precision"; return BMF_EINVAL; }
+    if (c.pivot_theta < 0.0 || c.pivot_theta >= 1.0) { err = "pivot_theta must be in [0, 1)"; return BMF_EINVAL; }
+    for (int64_t e = 0; e < c.nnz; ++e)
+        if (!std::isfinite(c.val[e])) { err = "non-finite value at entry " + std::to_string(e); return BMF_EINVAL; }
+    if (c.W0) {
+        std::vector<double> L;
+        if (!spd_cholesky(c.K, c.W0, L)) { err = "W0 is not SPD"; return BMF_EINVAL; }
+    }
+    if (c.mu0)
+        for (int k = 0; k < c.K; ++k)
+            if (!std::isfinite(c.mu0[k])) { err = "mu0 not finite"; return BMF_EINVAL; }
+    return BMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// schedules
+// ---------------------------------------------------------------------------
+// Lanes per entity for the register kernel: about `per` entries per lane, a
+// power of two in [1, 256] (groups above 64 lanes span several waves).
+int32_t g_lane_nnz = 12;
+int32_t lanes_for(int64_t deg) {
+    const int64_t per = g_lane_nnz;
+    int32_t G = 1;
+    while (G < 256 && (int64_t)G * per < deg) G <<= 1;
+    return G;
+}
+
+void side_tiles(int32_t side, int64_t ord_off, const std::vector<int64_t> &ptr, const std::vector<int32_t> &ord,
+                std::vector<Tile> &out, std::vector<int64_t> &cost) {
+    const int64_t n = (int64_t)ord.size();
+    int64_t k = 0;
+    while (k < n) {
+        const int64_t deg = ptr[ord[k] + 1] - ptr[ord[k]];
+        const int32_t G = lanes_for(deg);
+        const int32_t cap = 256 / G;
+        int32_t cnt = 0;
+        int64_t cst = 0;
+        while (k + cnt < n && cnt < cap) {
+            const int64_t d = ptr[ord[k + cnt] + 1] - ptr[ord[k + cnt]];
+            if (lanes_for(d) != G) break;
+            cst += d + 16;
+            ++cnt;
+        }
+        out.push_back(Tile{side, (int32_t)(ord_off + k), cnt, G});
+        cost.push_back(cst);
+        k += cnt;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// stage construction
+// ---------------------------------------------------------------------------
+static void build_stage_lists(bmf_ctx *c, int32_t s) {
+    StageLists &S = c->S;
+    S = StageLists();
+    const Plan &P = c->plan;
+    const int32_t J = P.J;
+    for (int32_t b = 0; b < (int32_t)P.blocks.size(); ++b)
+        if (P.blocks[b].stage == s) S.blocks.push_back(b);
+    const int32_t nbs = (int32_t)S.blocks.size();
+    const Layout &L = c->L;
+    double *hyper = c->dev<double>(L.hyper);
+    double *mm = c->dev<double>(L.mm);
+    double *tau = c->dev<double>(L.tau);
+    S.sides.resize(2 * nbs);
+    int64_t soff = 0;
+    for (int32_t k = 0; k < nbs; ++k) {
+        const int32_t b = S.blocks[k];
+        const PlanBlock &B = P.blocks[b];
+        const bool xp = B.j > 0, wp = B.i > 0;
+        SideDesc r{}, q{};
+        r.ptr_off = c->csr_ptr_off[b];
+        r.self_off = c->x_off[b];
+        r.other_off = c->w_off[b];
+        r.sample_off = soff;
+        soff += B.R;
+        r.prior = xp ? mm + c->x_off[B.i * J + 0] * L.prow : hyper + ((int64_t)b * 2 + 0) * L.hy;
+        r.tau = tau + b;
+        r.n = (int32_t)B.R;
+        r.per_row = xp;
+        r.c2 = counter_word(b, kRow);
+        r.c2_init = counter_word(b, kInitX);
+        r.block = b;
+        q.ptr_off = c->csc_ptr_off[b];
+        q.self_off = c->w_off[b];
+        q.other_off = c->x_off[b];
+        q.sample_off = soff;
+        soff += B.C;
+        q.prior = wp ? mm + (L.E_r + c->w_off[0 * J + B.j]) * L.prow : hyper + ((int64_t)b * 2 + 1) * L.hy;
+        q.tau = tau + b;
+        q.n = (int32_t)B.C;
+        q.per_row = wp;
+        q.c2 = counter_word(b, kCol);
+        q.c2_init = counter_word(b, kInitW);
+        q.block = b;
+        S.sides[k] = r;
+        S.sides[nbs + k] = q;
+        S.row_updates += B.R + B.C;
+        S.ratings += B.M;
+        S.row_ents += B.R;
+        S.col_ents += B.C;
+    }
+    // degree orders of each side (host copies, same as uploaded at init)
+    auto orders = [&](int32_t k, bool rows, std::vector<int32_t> &ord, const std::vector<int64_t> *&ptr) {
+        const PlanBlock &B = P.blocks[S.blocks[k]];
+        ptr = rows ? &B.csr_ptr : &B.csc_ptr;
+        ord = degree_order(*ptr);
+    };
+    // register tiles and wave items
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool rows = pass == 0;
+        std::vector<Tile> grouped;
+        std::vector<int64_t> gcost;
+        std::vector<int64_t> &tbeg = rows ? S.row_tile_begin : S.col_tile_begin;
+        std::vector<int2> igrp;
+        std::vector<int64_t> ideg;
+        std::vector<int64_t> &ibeg = rows ? S.row_item_begin : S.col_item_begin;
+        for (int32_t k = 0; k < nbs; ++k) {
+            std::vector<int32_t> ord;
+            const std::vector<int64_t> *ptr;
+            orders(k, rows, ord, ptr);
+            const int32_t b = S.blocks[k];
+            const int64_t ooff = rows ? c->ord_row_off[b] : c->ord_col_off[b];
+            const int32_t side = rows ? k : nbs + k;
+            tbeg.push_back((int64_t)grouped.size());
+            side_tiles(side, ooff, *ptr, ord, grouped, gcost);
+            ibeg.push_back((int64_t)igrp.size());
+            for (int32_t e : ord) {
+                igrp.push_back(make_int2(side, e));
+                ideg.push_back((*ptr)[e + 1] - (*ptr)[e]);
+            }
+        }
+        tbeg.push_back((int64_t)grouped.size());
+        ibeg.push_back((int64_t)igrp.size());
+        std::vector<int64_t> perm(grouped.size());
+        for (size_t q = 0; q < perm.size(); ++q) perm[q] = (int64_t)q;
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b2) { return gcost[a] > gcost[b2]; });
+        std::vector<int64_t> iperm(igrp.size());
+        for (size_t q = 0; q < iperm.size(); ++q) iperm[q] = (int64_t)q;
+        std::stable_sort(iperm.begin(), iperm.end(), [&](int64_t a, int64_t b2) { return ideg[a] > ideg[b2]; });
+        if (rows) {
+            S.t_row_blk = (int64_t)S.tiles.size();
+            S.tiles.insert(S.tiles.end(), grouped.begin(), grouped.end());
+            S.t_row_heavy = (int64_t)S.tiles.size();
+            for (int64_t q : perm) S.tiles.push_back(grouped[q]);
+            S.i_row_blk = (int64_t)S.items.size();
+            S.items.insert(S.items.end(), igrp.begin(), igrp.end());
+            S.i_row_heavy = (int64_t)S.items.size();
+            for (int64_t q : iperm) S.items.push_back(igrp[q]);
+        } else {
+            S.t_col_blk = (int64_t)S.tiles.size();
+            S.tiles.insert(S.tiles.end(), grouped.begin(), grouped.end());
+            S.t_col_heavy = (int64_t)S.tiles.size();
+            for (int64_t q : perm) S.tiles.push_back(grouped[q]);
+            S.i_col_blk = (int64_t)S.items.size();
+            S.items.insert(S.items.end(), igrp.begin(), igrp.end());
+            S.i_col_heavy = (int64_t)S.items.size();
+            for (int64_t q : iperm) S.items.push_back(igrp[q]);
+        }
+    }
+    S.t_end = (int64_t)S.tiles.size();
+    S.i_end = (int64_t)S.items.size();
+    S.sse_tile_begin = S.row_tile_begin;
+    // every entity, for init and moment matching
+    for (int32_t side = 0; side < 2 * nbs; ++side)
+        for (int32_t e = 0; e < S.sides[side].n; ++e) S.ents.push_back(make_int2(side, e));
+    // NW statistics jobs (non-propagated sides only): contiguous entity ranges
+    S.side_stats_begin.assign(2 * nbs + 1, 0);
+    for (int32_t side = 0; side < 2 * nbs; ++side) {
+        S.side_stats_begin[side] = (int64_t)S.stats.size();
+        if (S.sides[side].per_row) continue;
+        const int32_t n = S.sides[side].n;
+        const int32_t nj = std::max(1, std::min(kStatsJobsMax, (n + kStatsRowsPerJob - 1) / kStatsRowsPerJob));
+        const int32_t chunk = (n + nj - 1) / nj;
+        for (int32_t f = 0; f < n; f += chunk) {
+            StatsJob j{side, f, std::min(chunk, n - f), (int32_t)S.stats.size()};
+            S.stats.push_back(j);
+        }
+    }
+    S.side_stats_begin[2 * nbs] = (int64_t)S.stats.size();
+    // hyperparameter jobs, grouped by block
+    for (int32_t k = 0; k < nbs; ++k) {
+        const int32_t b = S.blocks[k];
+        const PlanBlock &B = P.blocks[b];
+        S.hyper_begin.push_back((int32_t)S.hyper.size());
+        if (!S.sides[k].per_row) {
+            HyperJob h{0, b, k, k + 1, B.R, hyper + ((int64_t)b * 2 + 0) * L.hy};
+            S.hyper.push_back(h);
+            S.hyper_kind.push_back(0);
+        }
+        if (!S.sides[nbs + k].per_row) {
+            HyperJob h{1, b, nbs + k, nbs + k + 1, B.C, hyper + ((int64_t)b * 2 + 1) * L.hy};
+            S.hyper.push_back(h);
+            S.hyper_kind.push_back(1);
+        }
+        if (c->cfg.sample_tau) {
+            HyperJob h{2, b, k, k + 1, B.M, tau + b};
+            S.hyper.push_back(h);
+            S.hyper_kind.push_back(2);
+        }
+    }
+    S.hyper_begin.push_back((int32_t)S.hyper.size());
+}
+
+static bmf_status upload(bmf_ctx *c, int64_t off, const void *src, size_t bytes) {
+    if (bytes == 0) return BMF_OK;
+    HIPCHK(c, hipMemcpyAsync(c->base + off, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return BMF_OK;
+}
+
+static bmf_status upload_stage(bmf_ctx *c) {
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    bmf_status st;
+    if ((int64_t)S.tiles.size() > L.n_tiles_cap || (int64_t)S.items.size() > L.n_items_cap ||
+        (int64_t)S.ents.size() > L.Emax + 8 || (int64_t)S.stats.size() > L.n_stats_cap)
+        return fail(c, BMF_ENOMEM, "stage work lists exceed their reserved space");
+    if ((st = upload(c, L.m_sides, S.sides.data(), S.sides.size() * sizeof(SideDesc)))) return st;
+    if ((st = upload(c, L.m_tiles, S.tiles.data(), S.tiles.size() * sizeof(Tile)))) return st;
+    if ((st = upload(c, L.m_items, S.items.data(), S.items.size() * sizeof(int2)))) return st;
+    if ((st = upload(c, L.m_items2, S.ents.data(), S.ents.size() * sizeof(int2)))) return st;
+    if ((st = upload(c, L.m_stats, S.stats.data(), S.stats.size() * sizeof(StatsJob)))) return st;
+    if ((st = upload(c, L.m_hyper, S.hyper.data(), S.hyper.size() * sizeof(HyperJob)))) return st;
+    {
+        // fixed-order reductions: SSE of stage block k at k, NW sums of side q at nbs + q
+        const int32_t nbs2 = (int32_t)S.blocks.size();
+        std::vector<ReduceJob> rj;
+        for (int32_t k = 0; k < nbs2; ++k)
+            rj.push_back(ReduceJob{c->dev<double>(L.sse_part) + S.sse_tile_begin[k], c->dev<double>(L.sse_final) + k,
+                                   (int32_t)(S.sse_tile_begin[k + 1] - S.sse_tile_begin[k]), 1});
+        for (int32_t q = 0; q < 2 * nbs2; ++q)
+            rj.push_back(ReduceJob{c->dev<double>(L.stats_part) + S.side_stats_begin[q] * L.npair,
+                                   c->dev<double>(L.stats_final) + (int64_t)q * L.npair,
+                                   (int32_t)(S.side_stats_begin[q + 1] - S.side_stats_begin[q]), L.npair});
+        if ((st = upload(c, L.m_reduce, rj.data(), rj.size() * sizeof(ReduceJob)))) return st;
+    }
+    std::vector<double *> outs(S.sides.size());
+    const int32_t nbs = (int32_t)S.blocks.size();
+    for (int32_t k = 0; k < nbs; ++k) {
+        const int32_t b = S.blocks[k];
+        outs[k] = c->dev<double>(L.mm) + c->x_off[b] * L.prow;
+        outs[nbs + k] = c->dev<double>(L.mm) + (L.E_r + c->w_off[b]) * L.prow;
+    }
+    if ((st = upload(c, L.m_mmout, outs.data(), outs.size() * sizeof(double *)))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return BMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernel drivers
+// ---------------------------------------------------------------------------
+static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample) {
+    const Layout &L = c->L;
+    UpdArgs a{};
+    a.sides = c->dev<SideDesc>(L.m_sides);
+    a.ord = c->dev<int32_t>(L.ord);
+    a.ptr = c->dev<int64_t>(rows ? L.csr_ptr : L.csc_ptr);
+    a.idx = c->dev<int32_t>(rows ? L.csr_idx : L.csc_idx);
+    a.val = c->dev<void>(rows ? L.csr_val : L.csc_val);
+    a.other = c->dev<void>(rows ? L.W : L.X);
+    a.ks_other = L.ks_m;
+    a.self = c->dev<void>(rows ? L.X : L.W);
+    a.ks_self = L.ks_m;
+    a.sample = sample;
+    a.ks_sample = L.ks_p;
+    a.K = c->cfg.K;
+    a.prow = L.prow;
+    a.t = t;
+    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(c->cfg.seed >> 32);
+    int32_t *cnt = c->dev<int32_t>(L.counters);
+    a.nonpd = cnt + kNonPD;
+    a.fb_total = cnt + kFbTotal;
+    if (!c->fp64()) {
+        a.theta = (float)(c->cfg.pivot_theta > 0.0 ? c->cfg.pivot_theta : std::ldexp(1.0, -10));
+        a.fb_count = cnt + (rows ? kFbRow : kFbCol);
+        a.fb_list = c->dev<int2>(L.fb_list);
+    }
+    return a;
+}
+
+// One conditional-update pass over the rows (or columns) of the active stage;
+// block k = -1 means every block, else only stage block k.
+static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int32_t k) {
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    const int32_t nbs = (int32_t)S.blocks.size();
+    UpdArgs a = upd_args(c, rows, t, sample);
+    bmf_status st;
+    const int32_t kcls = rows ? kKRows : kKCols;
+    if (!c->fp64()) {
+        int32_t *fb = a.fb_count;
+        if ((st = timed(c, kKFill, [&] { return launch_fill_i32(fb, 0, 1, c->stream); }))) return st;
+    }
+    // which blocks: one launch for all (batched, heavy-first) or one per block
+    std::vector<std::pair<int64_t, int64_t>> ranges;   // tile or item ranges
+    const bool batched = c->cfg.batched && k < 0;
+    if (c->reg()) {
+        if (batched) {
+            ranges.push_back(rows ? std::make_pair(S.t_row_heavy, S.t_col_blk) : std::make_pair(S.t_col_heavy, S.t_end));
+        } else {
+            const std::vector<int64_t> &tb = rows ? S.row_tile_begin : S.col_tile_begin;
+            const int64_t base = rows ? S.t_row_blk : S.t_col_blk;
+            for (int32_t q = 0; q < nbs; ++q)
+                if (k < 0 || q == k) ranges.push_back({base + tb[q], base + tb[q + 1]});
+        }
+        for (auto &r : ranges) {
+            UpdArgs b = a;
+            b.tiles = c->dev<Tile>(L.m_tiles) + r.first;
+            const int32_t n = (int32_t)(r.second - r.first);
+            if ((st = timed(c, kcls, [&] { return launch_update_reg(L.kc, c->prec(), b, n, c->stream); }))) return st;
+        }
+    } else {
+        if (batched) {
+            ranges.push_back(rows ? std::make_pair(S.i_row_heavy, S.i_col_blk) : std::make_pair(S.i_col_heavy, S.i_end));
+        } else {
+            const std::vector<int64_t> &ib = rows ? S.row_item_begin : S.col_item_begin;
+            const int64_t base = rows ? S.i_row_blk : S.i_col_blk;
+            for (int32_t q = 0; q < nbs; ++q)
+                if (k < 0 || q == k) ranges.push_back({base + ib[q], base + ib[q + 1]});
+        }
+        for (auto &r : ranges) {
+            UpdArgs b = a;
+            b.items = c->dev<int2>(L.m_items) + r.first;
+            b.nitems = (int32_t)(r.second - r.first);
+            const int32_t g = (int32_t)std::min<int64_t>(b.nitems, kWaveGridCap);
+            if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->stream); }))) return st;
+        }
+    }
+    if (!c->fp64()) {
+        UpdArgs f = a;
+        f.items = a.fb_list;
+        f.nitems_dev = a.fb_count;
+        f.fb_list = nullptr;
+        f.fb_count = nullptr;
+        f.theta = 0.0f;
+        const int32_t fp = c->bf() ? kPFB16 : kPFB32;
+        if ((st = timed(c, kKFallback, [&] { return launch_update_wave(L.kc, fp, f, kFallbackGrid, c->stream); })))
+            return st;
+    }
+    return BMF_OK;
+}
+
+static bmf_status run_sse(bmf_ctx *c, int32_t k) {
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    SseArgs a{};
+    a.sides = c->dev<SideDesc>(L.m_sides);
+    a.ord = c->dev<int32_t>(L.ord);
+    a.ptr = c->dev<int64_t>(L.csr_ptr);
+    a.idx = c->dev<int32_t>(L.csr_idx);
+    a.val = c->dev<void>(L.csr_val);
+    a.X = c->dev<void>(L.X);
+    a.W = c->dev<void>(L.W);
+    a.ks = L.ks_m;
+    a.part = c->dev<double>(L.sse_part);
+    const int32_t nbs = (int32_t)S.blocks.size();
+    const int64_t lo = k < 0 ? 0 : S.sse_tile_begin[k];
+    const int64_t hi = k < 0 ? S.sse_tile_begin[nbs] : S.sse_tile_begin[k + 1];
+    a.tiles = c->dev<Tile>(L.m_tiles) + S.t_row_blk + lo;
+    a.part_base = (int32_t)lo;
+    const int32_t n = (int32_t)(hi - lo);
+    bmf_status st = timed(c, kKSse, [&] { return launch_sse(L.kc, c->prec(), a, n, c->stream); });
+    if (st) return st;
+    const ReduceJob *rj = c->dev<ReduceJob>(L.m_reduce) + (k < 0 ? 0 : k);
+    const int32_t nr = k < 0 ? nbs : 1;
+    return timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->stream); });
+}
+
+static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi) {
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    const int64_t lo = S.side_stats_begin[side_lo], hi = S.side_stats_begin[side_hi];
+    if (hi <= lo) return BMF_OK;
+    // rows and columns live in different arrays: split at the row/column boundary
+    const int32_t nbs = (int32_t)S.blocks.size();
+    const int64_t mid = S.side_stats_begin[nbs];
+    bmf_status st;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int64_t a0 = pass == 0 ? lo : std::max(lo, mid);
+        const int64_t a1 = pass == 0 ? std::min(hi, mid) : hi;
+        if (a1 <= a0) continue;
+        StatsArgs a{};
+        a.jobs = c->dev<StatsJob>(L.m_stats) + a0;
+        a.sides = c->dev<SideDesc>(L.m_sides);
+        a.X = c->dev<void>(pass == 0 ? L.X : L.W);
+        a.ks = L.ks_m;
+        a.K = c->cfg.K;
+        a.part = c->dev<double>(L.stats_part);
+        const int32_t n = (int32_t)(a1 - a0);
+        if ((st = timed(c, kKStats, [&] { return launch_stats(c->prec(), a, n, c->stream); })))
+            return st;
+    }
+    const ReduceJob *rj = c->dev<ReduceJob>(L.m_reduce) + nbs + side_lo;
+    return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->stream); });
+}
+
+static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t) {
+    if (j1 <= j0) return BMF_OK;
+    const Layout &L = c->L;
+    HyperArgs a{};
+    a.jobs = c->dev<HyperJob>(L.m_hyper) + j0;
+    a.part = c->dev<double>(L.stats_final);
+    a.sse_part = c->dev<double>(L.sse_final);
+    a.mu0 = c->dev<double>(L.mu0);
+    a.W0inv = c->dev<double>(L.W0inv);
+    a.beta0 = c->cfg.beta0;
+    a.nu0 = c->cfg.nu0;
+    a.a0 = c->cfg.tau_a0;
+    a.b0 = c->cfg.tau_b0;
+    a.K = c->cfg.K;
+    a.t = t;
+    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(c->cfg.seed >> 32);
+    a.nonpd = c->dev<int32_t>(L.counters) + kNonPD;
+    return timed(c, kKHyper, [&] { return launch_hyper(a, j1 - j0, c->stream); });
+}
+
+static void *sample_slot(bmf_ctx *c, int32_t q) {
+    const Layout &L = c->L;
+    return c->base + L.sample + (int64_t)q * L.Emax * L.ks_p * L.sp;
+}
+
+static bmf_status sweep_once(bmf_ctx *c) {
+    StageLists &S = c->S;
+    const uint32_t t = (uint32_t)c->t;
+    const bmf_config &g = c->cfg;
+    const bool keep = c->t >= g.burnin && (c->t - g.burnin) % g.thin == 0 && c->kept < g.max_kept;
+    void *slot = keep ? sample_slot(c, c->kept) : nullptr;
+    bmf_status st;
+    const int32_t nbs = (int32_t)S.blocks.size();
+    const int32_t nblk = (c->cfg.batched) ? 1 : nbs;
+    for (int32_t q = 0; q < nblk; ++q) {
+        const int32_t k = c->cfg.batched ? -1 : q;
+        if ((st = run_pass(c, true, t, slot, k))) return st;
+        if ((st = run_pass(c, false, t, slot, k))) return st;
+        if (g.sample_tau && (st = run_sse(c, k))) return st;
+        if (k < 0) {
+            if ((st = run_stats(c, 0, 2 * nbs))) return st;
+        } else {
+            if ((st = run_stats(c, k, k + 1))) return st;
+            if ((st = run_stats(c, nbs + k, nbs + k + 1))) return st;
+        }
+        const int32_t j0 = k < 0 ? 0 : S.hyper_begin[k];
+        const int32_t j1 = k < 0 ? S.hyper_begin[nbs] : S.hyper_begin[k + 1];
+        if ((st = run_hyper(c, j0, j1, t))) return st;
+    }
+    if (keep) c->kept += 1;
+    c->t += 1;
+    c->agg_valid = false;
+    return BMF_OK;
+}
+
+// Begin stage s: work lists, priors, initial state.
+static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
+    build_stage_lists(c, s);
+    bmf_status st;
+    if ((st = upload_stage(c))) return st;
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    // hyperparameters (0, I), tau
+    const int32_t K = c->cfg.K;
+    std::vector<double> hy(L.hy, 0.0);
+    for (int k = 0; k < K; ++k) hy[k * K + k] = 1.0;
+    const double tau0 = c->cfg.sample_tau ? c->cfg.tau_a0 / c->cfg.tau_b0 : c->cfg.tau_fixed;
+    std::vector<double> hall;
+    for (int32_t b : S.blocks) {
+        if ((st = upload(c, L.hyper + ((int64_t)b * 2 + 0) * L.hy * 8, hy.data(), 8 * L.hy))) return st;
+        if ((st = upload(c, L.hyper + ((int64_t)b * 2 + 1) * L.hy * 8, hy.data(), 8 * L.hy))) return st;
+        if ((st = upload(c, L.tau + 8 * (int64_t)b, &tau0, 8))) return st;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    InitArgs a{};
+    a.items = c->dev<int2>(L.m_items2);
+    a.nitems = (int32_t)S.ents.size();
+    a.sides = c->dev<SideDesc>(L.m_sides);
+    a.K = K;
+    a.prow = L.prow;
+    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(c->cfg.seed >> 32);
+    // rows and columns live in different arrays: two launches over the entity list halves
+    const int64_t nrow_items = S.row_ents;
+    for (int pass = 0; pass < 2; ++pass) {
+        InitArgs b = a;
+        b.items = a.items + (pass == 0 ? 0 : nrow_items);
+        b.nitems = (int32_t)(pass == 0 ? nrow_items : (int64_t)S.ents.size() - nrow_items);
+        b.self = c->dev<void>(pass == 0 ? L.X : L.W);
+        b.ks_self = L.ks_m;
+        if ((st = timed(c, kKInit, [&] { return launch_init(c->prec(), b, c->stream); }))) return st;
+    }
+    c->stage = s;
+    c->t = 0;
+    c->kept = 0;
+    c->agg_valid = false;
+    return BMF_OK;
+}
+
+static bmf_status finalize_stage(bmf_ctx *c) {
+    if (c->stage == 0 || c->finalized >= c->stage) return BMF_OK;
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    if (c->kept < 1) return fail(c, BMF_ESTATE, "no kept sample in the active stage");
+    MmArgs a{};
+    a.items = c->dev<int2>(L.m_items2);
+    a.nitems = (int32_t)S.ents.size();
+    a.sides = c->dev<SideDesc>(L.m_sides);
+    a.sample = c->base + L.sample;
+    a.slot_elems = L.Emax * L.ks_p;
+    a.ks = L.ks_p;
+    a.S = c->kept;
+    a.K = c->cfg.K;
+    a.prow = L.prow;
+    a.out = c->dev<double *>(L.m_mmout);
+    a.ridged = c->dev<int32_t>(L.counters) + kRidged;
+    bmf_status st = timed(c, kKMM, [&] { return launch_mm(c->fp64() ? kP64 : kP32, a, c->stream); });
+    if (st) return st;
+    c->finalized = c->stage;
+    c->done_stages[c->stage] = c->kept;
+    return BMF_OK;
+}
+
+static bool stage_has_blocks(const bmf_ctx *c, int32_t s) {
+    for (const PlanBlock &B : c->plan.blocks)
+        if (B.stage == s) return true;
+    return false;
+}
+
+static int32_t last_stage(const bmf_ctx *c) {
+    int32_t s = 1;
+    for (int32_t q = 2; q <= 3; ++q)
+        if (stage_has_blocks(c, q)) s = q;
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+bmf_status bmf_config_defaults(bmf_config *cfg) {
+    if (!cfg) return BMF_EINVAL;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->K = 10;
+    cfg->I = 1;
+    cfg->J = 1;
+    cfg->order = BMF_ORDER_GIVEN;
+    cfg->beta0 = 2.0;
+    cfg->nu0 = 10.0;
+    cfg->sample_tau = 1;
+    cfg->tau_a0 = 1.0;
+    cfg->tau_b0 = 1.0;
+    cfg->tau_fixed = 1.0;
+    cfg->burnin = 0;
+    cfg->thin = 1;
+    cfg->max_kept = 1;
+    cfg->precision = BMF_PREC_FP32;
+    cfg->pivot_theta = std::ldexp(1.0, -10);
+    cfg->batched = 1;
+    return BMF_OK;
+}
+
+const char *bmf_status_string(bmf_status s) {
+    switch (s) {
+    case BMF_OK: return "BMF_OK";
+    case BMF_EINVAL: return "BMF_EINVAL";
+    case BMF_ENOMEM: return "BMF_ENOMEM";
+    case BMF_EDEVICE: return "BMF_EDEVICE";
+    case BMF_ENOTPD: return "BMF_ENOTPD";
+    case BMF_ESTATE: return "BMF_ESTATE";
+    case BMF_EUNSUPPORTED: return "BMF_EUNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+const char *bmf_last_error(const bmf_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+bmf_status bmf_workspace_size(const bmf_config *cfg, size_t *bytes) {
+    std::string err;
+    bmf_status st = validate(cfg, err);
+    if (st) return st;
+    if (!bytes) return BMF_EINVAL;
+    Layout L;
+    if (!layout_for(*cfg, L, err)) return BMF_EINVAL;
+    *bytes = (size_t)L.total;
+    return BMF_OK;
+}
+
+static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device) {
+    if (!out) return BMF_EINVAL;
+    *out = nullptr;
+    bmf_ctx *c = new (std::nothrow) bmf_ctx();
+    if (!c) return BMF_ENOMEM;
+    std::string err;
+    bmf_status st = validate(cfg, err);
+    if (!st && !layout_for(*cfg, c->L, err)) st = BMF_EINVAL;
+    if (st) {
+        *out = c;
+        c->err = err;
+        return st;
+    }
+    c->cfg = *cfg;
+    c->cfg.row = nullptr;
+    c->cfg.col = nullptr;
+    c->cfg.val = nullptr;
+    c->cfg.mu0 = nullptr;
+    c->cfg.W0 = nullptr;
+    const int32_t K = cfg->K;
+    c->mu0.assign(K, 0.0);
+    if (cfg->mu0) std::copy(cfg->mu0, cfg->mu0 + K, c->mu0.begin());
+    {
+        std::vector<double> W0(K * K, 0.0), Lf;
+        if (cfg->W0) std::copy(cfg->W0, cfg->W0 + K * K, W0.begin());
+        else
+            for (int k = 0; k < K; ++k) W0[k * K + k] = 1.0;
+        spd_cholesky(K, W0.data(), Lf);
+        // W0^-1 = L^-T L^-1, column by column
+        c->W0inv.assign(K * K, 0.0);
+        std::vector<double> y(K), x(K);
+        for (int col = 0; col < K; ++col) {
+            for (int i = 0; i < K; ++i) {
+                double s = (i == col) ? 1.0 : 0.0;
+                for (int p = 0; p < i; ++p) s -= Lf[i * K + p] * y[p];
+                y[i] = s / Lf[i * K + i];
+            }
+            for (int i = K - 1; i >= 0; --i) {
+                double s = y[i];
+                for (int p = i + 1; p < K; ++p) s -= Lf[p * K + i] * x[p];
+                x[i] = s / Lf[i * K + i];
+            }
+            for (int r = 0; r < K; ++r) c->W0inv[r * K + col] = x[r];
+        }
+    }
+    // centering: sequential FP64 mean in COO order
+    double s = 0.0;
+    for (int64_t e = 0; e < cfg->nnz; ++e) s += (double)cfg->val[e];
+    c->ybar = cfg->nnz > 0 ? s / (double)cfg->nnz : 0.0;
+    st = build_plan(*cfg, c->plan, err);
+    if (st) {
+        *out = c;
+        c->err = err;
+        return st;
+    }
+    const Plan &P = c->plan;
+    const int64_t nb = (int64_t)P.blocks.size();
+    int64_t pr = 0, pc = 0, xr = 0, wc = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const PlanBlock &B = P.blocks[b];
+        c->csr_ptr_off.push_back(pr);
+        c->csc_ptr_off.push_back(pc);
+        c->x_off.push_back(xr);
+        c->w_off.push_back(wc);
+        c->ord_row_off.push_back(xr);
+        c->ord_col_off.push_back(c->L.E_r + wc);
+        pr += B.R + 1;
+        pc += B.C + 1;
+        xr += B.R;
+        wc += B.C;
+    }
+    *out = c;
+    if (!device) return BMF_OK;
+
+    // ---- device part
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(c, BMF_EDEVICE, "no HIP device");
+    c->stream = (hipStream_t)cfg->stream;
+    const Layout &L = c->L;
+    if (cfg->workspace) {
+        if ((int64_t)cfg->workspace_bytes < L.total)
+            return fail(c, BMF_ENOMEM, "workspace too small: need " + std::to_string(L.total) + " bytes");
+        if (((uintptr_t)cfg->workspace & 255u) != 0) return fail(c, BMF_EINVAL, "workspace must be 256-byte aligned");
+        c->base = (char *)cfg->workspace;
+    } else {
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)L.total) != hipSuccess) return fail(c, BMF_ENOMEM, "hipMalloc of the workspace failed");
+        c->base = (char *)p;
+        c->own = true;
+    }
+    c->device = true;
+    HIPCHK(c, hipMemsetAsync(c->base, 0, (size_t)L.total, c->stream));
+    // CSR / CSC with centred values, degree orders
+    const bool fp64 = cfg->precision == BMF_PREC_FP64;
+    std::vector<int64_t> hptr;
+    std::vector<int32_t> hidx;
+    std::vector<double> vd;
+    std::vector<float> vf;
+    std::vector<int32_t> hord;
+    for (int pass = 0; pass < 2; ++pass) {
+        hptr.clear();
+        hidx.clear();
+        vd.clear();
+        vf.clear();
+        hord.clear();
+        int64_t base_nz = 0;
+        for (int64_t b = 0; b < nb; ++b) {
+            const PlanBlock &B = P.blocks[b];
+            const std::vector<int64_t> &bp = pass == 0 ? B.csr_ptr : B.csc_ptr;
+            const std::vector<int32_t> &bi = pass == 0 ? B.csr_idx : B.csc_idx;
+            const std::vector<int64_t> &be = pass == 0 ? B.csr_entry : B.csc_entry;
+            for (int64_t v : bp) hptr.push_back(base_nz + v);
+            hidx.insert(hidx.end(), bi.begin(), bi.end());
+            for (int64_t e : be) {
+                const double r = (double)cfg->val[e] - c->ybar;
+                if (fp64) vd.push_back(r);
+                else vf.push_back((float)r);
+            }
+            std::vector<int32_t> o = degree_order(bp);
+            hord.insert(hord.end(), o.begin(), o.end());
+            base_nz += B.M;
+        }
+        const int64_t o_ptr = pass == 0 ? L.csr_ptr : L.csc_ptr;
+        const int64_t o_idx = pass == 0 ? L.csr_idx : L.csc_idx;
+        const int64_t o_val = pass == 0 ? L.csr_val : L.csc_val;
+        if ((st = upload(c, o_ptr, hptr.data(), hptr.size() * 8))) return st;
+        if ((st = upload(c, o_idx, hidx.data(), hidx.size() * 4))) return st;
+        if (fp64) {
+            if ((st = upload(c, o_val, vd.data(), vd.size() * 8))) return st;
+        } else {
+            if ((st = upload(c, o_val, vf.data(), vf.size() * 4))) return st;
+        }
+        if ((st = upload(c, L.ord + (pass == 0 ? 0 : 4 * L.E_r), hord.data(), hord.size() * 4))) return st;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if ((st = upload(c, L.mu0, c->mu0.data(), 8 * K))) return st;
+    if ((st = upload(c, L.W0inv, c->W0inv.data(), 8 * K * K))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return BMF_OK;
+}
+
+bmf_status bmf_init(const bmf_config *cfg, bmf_ctx **out) {
+    if (const char *e = std::getenv("BMF_LANE_NNZ")) g_lane_nnz = std::max(1, std::atoi(e));
+    return init_common(cfg, out, true);
+}
+bmf_status bmf_init_host(const bmf_config *cfg, bmf_ctx **out) { return init_common(cfg, out, false); }
+
+bmf_status bmf_free(bmf_ctx *c) {
+    if (!c) return BMF_OK;
+    if (c->device) {
+        hipStreamSynchronize(c->stream);
+        for (auto &p : c->pending) {
+            hipEventDestroy(p.a);
+            hipEventDestroy(p.b);
+        }
+        if (c->own && c->base) hipFree(c->base);
+    }
+    delete c;
+    return BMF_OK;
+}
+
+bmf_status bmf_gibbs_sweep(bmf_ctx *c, int32_t nsweeps) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (nsweeps < 0) return fail(c, BMF_EINVAL, "nsweeps < 0");
+    bmf_status st;
+    if (c->stage == 0 && (st = begin_stage(c, 1))) return st;
+    if (c->finalized >= c->stage) c->finalized = c->stage - 1;   // more samples: redo MM later
+    for (int32_t q = 0; q < nsweeps; ++q)
+        if ((st = sweep_once(c))) return st;
+    return BMF_OK;
+}
+
+bmf_status bmf_pp_stage(bmf_ctx *c, int32_t stage, int32_t nsweeps) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (stage < 1 || stage > 3 || nsweeps < 0) return fail(c, BMF_EINVAL, "bad stage or nsweeps");
+    if (!stage_has_blocks(c, stage)) return BMF_OK;
+    int32_t prev = 0;
+    for (int32_t q = stage - 1; q >= 1; --q)
+        if (stage_has_blocks(c, q)) { prev = q; break; }
+    if (c->stage != prev && !(stage == 1 && c->stage == 0))
+        return fail(c, BMF_ESTATE, "stages must be run in order");
+    if (prev > 0) {
+        bmf_status st = finalize_stage(c);
+        if (st) return st;
+        if (c->done_stages[prev] < 2)
+            return fail(c, BMF_ESTATE, "propagation needs at least 2 kept samples per block");
+    }
+    bmf_status st = begin_stage(c, stage);
+    if (st) return st;
+    for (int32_t q = 0; q < nsweeps; ++q)
+        if ((st = sweep_once(c))) return st;
+    return BMF_OK;
+}
+
+bmf_status bmf_aggregate(bmf_ctx *c) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (c->agg_valid) return BMF_OK;
+    if (c->stage != last_stage(c)) return fail(c, BMF_ESTATE, "every PP stage must be run before aggregation");
+    bmf_status st = finalize_stage(c);
+    if (st) return st;
+    const Layout &L = c->L;
+    const Plan &P = c->plan;
+    const int32_t I = P.I, J = P.J;
+    if ((I > 1 || J > 1))
+        for (int32_t s = 1; s <= 3; ++s)
+            if (stage_has_blocks(c, s) && c->done_stages[s] < 2)
+                return fail(c, BMF_ESTATE, "aggregation needs at least 2 kept samples per block");
+    double *mm = c->dev<double>(L.mm);
+    for (int side = 0; side < 2; ++side) {
+        std::vector<AggJob> jobs;
+        std::vector<int2> items;
+        const int32_t nparts = side == 0 ? I : J;
+        for (int32_t p = 0; p < nparts; ++p) {
+            AggJob jb{};
+            if (side == 0) {
+                jb.base = mm + c->x_off[p * J + 0] * L.prow;
+                for (int32_t j = 1; j < J; ++j) jb.sib[j - 1] = mm + c->x_off[p * J + j] * L.prow;
+                jb.nsib = J - 1;
+                jb.n = (int32_t)P.R[p];
+                jb.out_off = (int64_t)p * P.bs_r;
+            } else {
+                jb.base = mm + (L.E_r + c->w_off[0 * J + p]) * L.prow;
+                for (int32_t i = 1; i < I; ++i) jb.sib[i - 1] = mm + (L.E_r + c->w_off[i * J + p]) * L.prow;
+                jb.nsib = I - 1;
+                jb.n = (int32_t)P.C[p];
+                jb.out_off = (int64_t)p * P.bs_c;
+            }
+            for (int32_t n = 0; n < jb.n; ++n) items.push_back(make_int2(p, n));
+            jobs.push_back(jb);
+        }
+        if ((st = upload(c, L.m_agg_jobs, jobs.data(), jobs.size() * sizeof(AggJob)))) return st;
+        if ((st = upload(c, L.m_agg_items, items.data(), items.size() * sizeof(int2)))) return st;
+        AggArgs a{};
+        a.jobs = c->dev<AggJob>(L.m_agg_jobs);
+        a.items = c->dev<int2>(L.m_agg_items);
+        a.nitems = (int32_t)items.size();
+        a.K = c->cfg.K;
+        a.prow = L.prow;
+        a.out = c->dev<double>(side == 0 ? L.agg_x : L.agg_w);
+        a.corrections = c->dev<int32_t>(L.counters) + kCorr;
+        if ((st = timed(c, kKAgg, [&] { return launch_agg(a, c->stream); }))) return st;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->agg_valid = true;
+    return BMF_OK;
+}
+
+bmf_status bmf_predict(bmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col, float *out) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (n < 0 || (n > 0 && (!row || !col || !out))) return fail(c, BMF_EINVAL, "bad prediction arrays");
+    bmf_status st = bmf_aggregate(c);
+    if (st) return st;
+    const Layout &L = c->L;
+    const Plan &P = c->plan;
+    std::vector<int64_t> xs, ws;
+    for (int64_t a = 0; a < n; a += kPredictChunk) {
+        const int64_t m = std::min(kPredictChunk, n - a);
+        xs.resize(m);
+        ws.resize(m);
+        for (int64_t q = 0; q < m; ++q) {
+            const int64_t r = row[a + q], cc = col[a + q];
+            if (r < 0 || r >= P.N || cc < 0 || cc >= P.D) return fail(c, BMF_EINVAL, "prediction id out of range");
+            xs[q] = P.row_pos[r];
+            ws[q] = P.col_pos[cc];
+        }
+        if ((st = upload(c, L.p_xslot, xs.data(), 8 * m))) return st;
+        if ((st = upload(c, L.p_wslot, ws.data(), 8 * m))) return st;
+        PredictArgs pa{c->dev<int64_t>(L.p_xslot), c->dev<int64_t>(L.p_wslot), m, c->dev<double>(L.agg_x),
+                       c->dev<double>(L.agg_w), c->cfg.K, c->ybar, c->dev<float>(L.p_out)};
+        if ((st = timed(c, kKPredict, [&] { return launch_predict(pa, c->stream); }))) return st;
+        HIPCHK(c, hipMemcpyAsync(out + a, c->base + L.p_out, 4 * m, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return BMF_OK;
+}
+
+bmf_status bmf_block_info(const bmf_ctx *c, int32_t b, int64_t *R, int64_t *C, int64_t *M, int32_t *stage) {
+    if (!c || b < 0 || b >= (int32_t)c->plan.blocks.size()) return BMF_EINVAL;
+    const PlanBlock &B = c->plan.blocks[b];
+    if (R) *R = B.R;
+    if (C) *C = B.C;
+    if (M) *M = B.M;
+    if (stage) *stage = B.stage;
+    return BMF_OK;
+}
+
+bmf_status bmf_global_mean(const bmf_ctx *c, double *ybar) {
+    if (!c || !ybar) return BMF_EINVAL;
+    *ybar = c->ybar;
+    return BMF_OK;
+}
+
+bmf_status bmf_get_positions(const bmf_ctx *c, int64_t *pos_row, int64_t *pos_col) {
+    if (!c) return BMF_EINVAL;
+    if (pos_row) std::copy(c->plan.row_pos.begin(), c->plan.row_pos.end(), pos_row);
+    if (pos_col) std::copy(c->plan.col_pos.begin(), c->plan.col_pos.end(), pos_col);
+    return BMF_OK;
+}
+
+bmf_status bmf_get_block_csr(const bmf_ctx *c, int32_t b, int32_t which, int64_t *ptr, int32_t *idx,
+                             int64_t *entry) {
+    if (!c || b < 0 || b >= (int32_t)c->plan.blocks.size() || which < 0 || which > 1) return BMF_EINVAL;
+    const PlanBlock &B = c->plan.blocks[b];
+    const std::vector<int64_t> &p = which == 0 ? B.csr_ptr : B.csc_ptr;
+    const std::vector<int32_t> &i = which == 0 ? B.csr_idx : B.csc_idx;
+    const std::vector<int64_t> &e = which == 0 ? B.csr_entry : B.csc_entry;
+    if (ptr) std::copy(p.begin(), p.end(), ptr);
+    if (idx) std::copy(i.begin(), i.end(), idx);
+    if (entry) std::copy(e.begin(), e.end(), entry);
+    return BMF_OK;
+}
+
+// Host conversions between FP64 and the state element type (FP64, FP32, BF16).
+static double state_to_double(const bmf_ctx *c, const char *buf, int64_t i) {
+    if (c->fp64()) return reinterpret_cast<const double *>(buf)[i];
+    if (!c->bf()) return (double)reinterpret_cast<const float *>(buf)[i];
+    const uint32_t u = (uint32_t)reinterpret_cast<const uint16_t *>(buf)[i] << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static void double_to_state(const bmf_ctx *c, char *buf, int64_t i, double v) {
+    if (c->fp64()) {
+        reinterpret_cast<double *>(buf)[i] = v;
+    } else if (!c->bf()) {
+        reinterpret_cast<float *>(buf)[i] = (float)v;
+    } else {
+        const float f = (float)v;
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+        reinterpret_cast<uint16_t *>(buf)[i] = (uint16_t)(u >> 16);
+    }
+}
+
+static int32_t stage_index(const bmf_ctx *c, int32_t b) {
+    for (size_t k = 0; k < c->S.blocks.size(); ++k)
+        if (c->S.blocks[k] == b) return (int32_t)k;
+    return -1;
+}
+
+bmf_status bmf_get_state(bmf_ctx *c, int32_t b, double *X, double *W, double *hyper, double *tau) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device || c->stage == 0) return fail(c, BMF_ESTATE, "no active stage");
+    if (stage_index(c, b) < 0) return fail(c, BMF_EINVAL, "block is not in the active stage");
+    const Layout &L = c->L;
+    const PlanBlock &B = c->plan.blocks[b];
+    const int32_t K = c->cfg.K;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int side = 0; side < 2; ++side) {
+        double *dst = side == 0 ? X : W;
+        if (!dst) continue;
+        const int64_t n = side == 0 ? B.R : B.C;
+        const int64_t off = side == 0 ? c->x_off[b] : c->w_off[b];
+        const int64_t arr = side == 0 ? L.X : L.W;
+        std::vector<char> buf((size_t)(n * L.ks_m * L.ss));
+        HIPCHK(c, hipMemcpy(buf.data(), c->base + arr + off * L.ks_m * L.ss, buf.size(), hipMemcpyDeviceToHost));
+        for (int64_t r = 0; r < n; ++r)
+            for (int k = 0; k < K; ++k) dst[r * K + k] = state_to_double(c, buf.data(), r * L.ks_m + k);
+    }
+    if (hyper) {
+        std::vector<double> h(2 * L.hy);
+        HIPCHK(c, hipMemcpy(h.data(), c->base + L.hyper + (int64_t)b * 2 * L.hy * 8, 16 * L.hy, hipMemcpyDeviceToHost));
+        for (int side = 0; side < 2; ++side) {
+            std::copy(h.begin() + side * L.hy, h.begin() + side * L.hy + K * K, hyper + side * (K * K + K));
+            std::copy(h.begin() + side * L.hy + K * K, h.begin() + side * L.hy + K * K + K,
+                      hyper + side * (K * K + K) + K * K);
+        }
+    }
+    if (tau) HIPCHK(c, hipMemcpy(tau, c->base + L.tau + 8 * (int64_t)b, 8, hipMemcpyDeviceToHost));
+    return BMF_OK;
+}
+
+bmf_status bmf_set_state(bmf_ctx *c, int32_t b, const double *X, const double *W, const double *hyper,
+                         const double *tau) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device || c->stage == 0) return fail(c, BMF_ESTATE, "no active stage");
+    if (stage_index(c, b) < 0) return fail(c, BMF_EINVAL, "block is not in the active stage");
+    const Layout &L = c->L;
+    const PlanBlock &B = c->plan.blocks[b];
+    const int32_t K = c->cfg.K;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int side = 0; side < 2; ++side) {
+        const double *src = side == 0 ? X : W;
+        if (!src) continue;
+        const int64_t n = side == 0 ? B.R : B.C;
+        const int64_t off = side == 0 ? c->x_off[b] : c->w_off[b];
+        std::vector<char> buf((size_t)(n * L.ks_m * L.ss), 0);
+        for (int64_t r = 0; r < n; ++r)
+            for (int k = 0; k < K; ++k) double_to_state(c, buf.data(), r * L.ks_m + k, src[r * K + k]);
+        HIPCHK(c, hipMemcpy(c->base + (side == 0 ? L.X : L.W) + off * L.ks_m * L.ss, buf.data(), buf.size(),
+                            hipMemcpyHostToDevice));
+    }
+    if (hyper) {
+        std::vector<double> h(2 * L.hy, 0.0);
+        for (int side = 0; side < 2; ++side) {
+            const double *Lam = hyper + side * (K * K + K);
+            const double *mu = Lam + K * K;
+            std::copy(Lam, Lam + K * K, h.begin() + side * L.hy);
+            std::copy(mu, mu + K, h.begin() + side * L.hy + K * K);
+            for (int a = 0; a < K; ++a) {
+                double s = 0.0;
+                for (int q = 0; q < K; ++q) s += Lam[a * K + q] * mu[q];
+                h[side * L.hy + K * K + K + a] = s;
+            }
+        }
+        HIPCHK(c, hipMemcpy(c->base + L.hyper + (int64_t)b * 2 * L.hy * 8, h.data(), 16 * L.hy, hipMemcpyHostToDevice));
+    }
+    if (tau) HIPCHK(c, hipMemcpy(c->base + L.tau + 8 * (int64_t)b, tau, 8, hipMemcpyHostToDevice));
+    c->agg_valid = false;
+    return BMF_OK;
+}
+
+bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device || c->stage == 0) return fail(c, BMF_ESTATE, "no active stage");
+    const int32_t k = stage_index(c, b);
+    if (k < 0) return fail(c, BMF_EINVAL, "block is not in the active stage");
+    if (t < 0 || t > 0xFFFFFFFELL) return fail(c, BMF_EINVAL, "bad sweep index");
+    const uint32_t tt = (uint32_t)t;
+    StageLists &S = c->S;
+    const int32_t nbs = (int32_t)S.blocks.size();
+    bmf_status st;
+    switch (which) {
+    case 0: st = run_pass(c, true, tt, c->base + c->L.probe, k); break;
+    case 1: st = run_pass(c, false, tt, c->base + c->L.probe, k); break;
+    case 2:
+    case 3: {
+        const int32_t side = which == 2 ? k : nbs + k;
+        if (S.sides[side].per_row) return fail(c, BMF_ESTATE, "side is propagated: no Normal-Wishart draw");
+        if ((st = run_stats(c, side, side + 1))) return st;
+        int32_t j = -1;
+        for (int32_t q = S.hyper_begin[k]; q < S.hyper_begin[k + 1]; ++q)
+            if (S.hyper_kind[q] == which - 2) j = q;
+        st = run_hyper(c, j, j + 1, tt);
+        break;
+    }
+    case 4: {
+        if (!c->cfg.sample_tau) return fail(c, BMF_ESTATE, "tau is fixed");
+        if ((st = run_sse(c, k))) return st;
+        int32_t j = -1;
+        for (int32_t q = S.hyper_begin[k]; q < S.hyper_begin[k + 1]; ++q)
+            if (S.hyper_kind[q] == 2) j = q;
+        st = run_hyper(c, j, j + 1, tt);
+        break;
+    }
+    default: return fail(c, BMF_EINVAL, "bad step kind");
+    }
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->agg_valid = false;
+    return BMF_OK;
+}
+
+bmf_status bmf_get_draw(bmf_ctx *c, int32_t b, int32_t side, double *x) {
+    if (!c || !x || side < 0 || side > 1) return BMF_EINVAL;
+    if (!c->device || c->stage == 0) return fail(c, BMF_ESTATE, "no active stage");
+    const int32_t k = stage_index(c, b);
+    if (k < 0) return fail(c, BMF_EINVAL, "block is not in the active stage");
+    const Layout &L = c->L;
+    const int32_t nbs = (int32_t)c->S.blocks.size();
+    const SideDesc &sd = c->S.sides[side == 0 ? k : nbs + k];
+    const int32_t K = c->cfg.K;
+    std::vector<char> buf((size_t)((int64_t)sd.n * L.ks_p * L.sp));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(buf.data(), c->base + L.probe + sd.sample_off * L.ks_p * L.sp, buf.size(),
+                        hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < sd.n; ++r)
+        for (int q = 0; q < K; ++q)
+            x[r * K + q] = c->fp64() ? reinterpret_cast<double *>(buf.data())[r * L.ks_p + q]
+                                     : (double)reinterpret_cast<float *>(buf.data())[r * L.ks_p + q];
+    return BMF_OK;
+}
+
+bmf_status bmf_get_mm(bmf_ctx *c, int32_t b, int32_t side, double *mu, double *Lam) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (b < 0 || b >= (int32_t)c->plan.blocks.size() || side < 0 || side > 1) return fail(c, BMF_EINVAL, "bad block");
+    const PlanBlock &B = c->plan.blocks[b];
+    if (c->finalized < B.stage) {
+        if (c->stage == B.stage) {
+            bmf_status st = finalize_stage(c);
+            if (st) return st;
+        } else {
+            return fail(c, BMF_ESTATE, "the block's stage has not been run");
+        }
+    }
+    const Layout &L = c->L;
+    const int32_t K = c->cfg.K;
+    const int64_t n = side == 0 ? B.R : B.C;
+    const int64_t row0 = side == 0 ? c->x_off[b] : L.E_r + c->w_off[b];
+    std::vector<double> buf((size_t)(n * L.prow));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(buf.data(), c->base + L.mm + row0 * L.prow * 8, buf.size() * 8, hipMemcpyDeviceToHost));
+    const int32_t kk2 = K * (K + 1) / 2;
+    for (int64_t r = 0; r < n; ++r) {
+        const double *row = buf.data() + r * L.prow;
+        if (mu)
+            for (int k = 0; k < K; ++k) mu[r * K + k] = row[kk2 + K + k];
+        if (Lam) {
+            int q = 0;
+            for (int a = 0; a < K; ++a)
+                for (int bb = 0; bb <= a; ++bb, ++q) {
+                    Lam[(r * K + a) * K + bb] = row[q];
+                    Lam[(r * K + bb) * K + a] = row[q];
+                }
+        }
+    }
+    return BMF_OK;
+}
+
+bmf_status bmf_get_aggregate(bmf_ctx *c, int32_t side, double *mu) {
+    if (!c || !mu || side < 0 || side > 1) return BMF_EINVAL;
+    bmf_status st = bmf_aggregate(c);
+    if (st) return st;
+    const Layout &L = c->L;
+    const Plan &P = c->plan;
+    const int32_t K = c->cfg.K;
+    const int64_t n = side == 0 ? P.N : P.D;
+    std::vector<double> buf((size_t)(n * K));
+    HIPCHK(c, hipMemcpy(buf.data(), c->base + (side == 0 ? L.agg_x : L.agg_w), buf.size() * 8, hipMemcpyDeviceToHost));
+    const std::vector<int64_t> &pos = side == 0 ? P.row_pos : P.col_pos;
+    for (int64_t r = 0; r < n; ++r)
+        for (int k = 0; k < K; ++k) mu[r * K + k] = buf[pos[r] * K + k];
+    return BMF_OK;
+}
+
+bmf_status bmf_get_stats(bmf_ctx *c, int64_t *fallback_rows, int64_t *nonpd_rows, int64_t *mm_ridged,
+                         int64_t *agg_corrections) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    int32_t h[kNumCounters];
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(h, c->base + c->L.counters, sizeof(h), hipMemcpyDeviceToHost));
+    if (fallback_rows) *fallback_rows = h[kFbTotal];
+    if (nonpd_rows) *nonpd_rows = h[kNonPD];
+    if (mm_ridged) *mm_ridged = h[kRidged];
+    if (agg_corrections) *agg_corrections = h[kCorr];
+    return BMF_OK;
+}
+
+bmf_status bmf_enable_timing(bmf_ctx *c, int32_t on) {
+    if (!c) return BMF_EINVAL;
+    c->timing = on != 0;
+    return BMF_OK;
+}
+
+bmf_status bmf_kernel_times(bmf_ctx *c, int32_t n, const char **names, int64_t *launches, double *ms,
+                            int32_t *count) {
+    if (!c) return BMF_EINVAL;
+    if (c->device) HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->pending) {
+        float e = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&e, p.a, p.b));
+        c->tlaunch[p.k] += 1;
+        c->tms[p.k] += e;
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    c->pending.clear();
+    for (int32_t k = 0; k < kNumK && k < n; ++k) {
+        if (names) names[k] = kKNames[k];
+        if (launches) launches[k] = c->tlaunch[k];
+        if (ms) ms[k] = c->tms[k];
+    }
+    if (count) *count = kNumK;
+    return BMF_OK;
+}
+
+bmf_status bmf_stage_work(const bmf_ctx *c, int64_t *row_updates, int64_t *ratings) {
+    if (!c) return BMF_EINVAL;
+    if (row_updates) *row_updates = c->S.row_updates;
+    if (ratings) *ratings = c->S.ratings;
+    return BMF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1333 @@
+// HIP kernels (gfx950) of the BPMF Gibbs sweep under posterior propagation.
+//
+// Conditional update of one side of a block (Sec. 2.1 model; Gibbs sampler of
+// Salakhutdinov & Mnih 2008b as used in Sec. 5.1): for entity n with observed
+// set Omega_n,
+//     A = P_n + tau * sum_{d in Omega_n} w_d w_d^T,
+//     h = P_n m_n + tau * sum_{d in Omega_n} r_nd w_d,
+//     L L^T = A,  x_n = L^-T (L^-1 h + z),  z ~ N(0, I)  (Philox counter (n, t, c2, g)).
+// (P_n, P_n m_n) is the side's shared Normal-Wishart-drawn prior, or the
+// propagated moment-matched per-row prior of PP stages 2-3 (eq. stage2a-stage3).
+//
+// Two update kernels:
+//   * k_update_reg<KC>: K <= 16.  G lanes per entity (G a power of two <= 64,
+//     chosen per degree), each lane accumulating the full packed Gram and
+//     right-hand side in registers over a strided share of Omega_n; a
+//     butterfly reduction leaves the exact same sums in every lane of the
+//     group, which then factor and solve redundantly in registers.
+//   * k_update_wave<KP>: K <= 64, one wavefront per entity, factors staged in
+//     LDS, 8x8 lane grid of register tiles for the Gram, and a
+//     column-parallel Cholesky and triangular solves in LDS.  Also runs the
+//     FP64 redo of rows whose FP32 pivot test failed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "kernels.hpp"
+
+namespace bmf {
+
+// --------------------------------------------------------------------------
+// scalar helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+// uniform on (0,1): (m + 1/2) 2^-23 from the top 23 bits; exact in FP32 and FP64
+__device__ __forceinline__ float unif_f(uint32_t x) { return ((float)(x >> 9) + 0.5f) * 1.1920928955078125e-7f; }
+__device__ __forceinline__ double unif_d(uint32_t x) { return ((double)(x >> 9) + 0.5) * 1.1920928955078125e-7; }
+
+// Four standard normals of counter (c0, c1, c2, g) by two Box-Muller transforms.
+__device__ __forceinline__ void normals4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t g,
+                                         uint32_t k0, uint32_t k1, float z[4]) {
+    uint32_t o[4];
+    philox4x32_10(c0, c1, c2, g, k0, k1, o);
+    const float r1 = sqrtf(-2.0f * logf(unif_f(o[0])));
+    const float r2 = sqrtf(-2.0f * logf(unif_f(o[2])));
+    float s1, co1, s2, co2;
+    sincosf(6.28318530717958647692f * unif_f(o[1]), &s1, &co1);
+    sincosf(6.28318530717958647692f * unif_f(o[3]), &s2, &co2);
+    z[0] = r1 * co1; z[1] = r1 * s1; z[2] = r2 * co2; z[3] = r2 * s2;
+}
+__device__ __forceinline__ void normals4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t g,
+                                         uint32_t k0, uint32_t k1, double z[4]) {
+    uint32_t o[4];
+    philox4x32_10(c0, c1, c2, g, k0, k1, o);
+    const double two_pi = 6.283185307179586476925286766559;
+    const double r1 = sqrt(-2.0 * log(unif_d(o[0])));
+    const double r2 = sqrt(-2.0 * log(unif_d(o[2])));
+    const double t1 = two_pi * unif_d(o[1]), t2 = two_pi * unif_d(o[3]);
+    z[0] = r1 * cos(t1); z[1] = r1 * sin(t1); z[2] = r2 * cos(t2); z[3] = r2 * sin(t2);
+}
+
+// Gamma(shape, 1), Marsaglia & Tsang (2000); attempt k on counter (c0,c1,c2,k);
+// shape < 1 boosted by U^(1/shape) with U from counter (c0,c1,c2,0xFFFFFFFF).
+__device__ double gamma_draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2,
+                             double shape) {
+    double boost = 1.0, a = shape;
+    if (a < 1.0) {
+        uint32_t o[4];
+        philox4x32_10(c0, c1, c2, 0xFFFFFFFFu, k0, k1, o);
+        boost = pow(unif_d(o[0]), 1.0 / a);
+        a += 1.0;
+    }
+    const double d = a - 1.0 / 3.0, c = 1.0 / sqrt(9.0 * d);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (uint32_t k = 0; k < 64u; ++k) {
+        uint32_t o[4];
+        philox4x32_10(c0, c1, c2, k, k0, k1, o);
+        const double z = sqrt(-2.0 * log(unif_d(o[0]))) * cos(two_pi * unif_d(o[1]));
+        double v = 1.0 + c * z;
+        if (v <= 0.0) continue;
+        v = v * v * v;
+        if (log(unif_d(o[2])) < 0.5 * z * z + d - d * v + d * log(v)) return d * v * boost;
+    }
+    return d * boost;
+}
+
+// --------------------------------------------------------------------------
+// precision traits and vector row loads/stores
+// --------------------------------------------------------------------------
+// acc: arithmetic; w: gathered factors (= the other side's state); v: values;
+// s: state written; p: kept samples.
+template <int P> struct PrecT;
+template <> struct PrecT<kP64> { using acc = double; using w = double; using v = double; using s = double; using p = double; };
+template <> struct PrecT<kP32> { using acc = float; using w = float; using v = float; using s = float; using p = float; };
+template <> struct PrecT<kPBF> { using acc = float; using w = uint16_t; using v = float; using s = uint16_t; using p = float; };
+template <> struct PrecT<kPFB32> { using acc = double; using w = float; using v = float; using s = float; using p = float; };
+template <> struct PrecT<kPFB16> { using acc = double; using w = uint16_t; using v = float; using s = uint16_t; using p = float; };
+
+template <typename T> __host__ __device__ constexpr int vec_of() { return 16 / (int)sizeof(T); }
+template <typename T> __host__ __device__ constexpr int ks_of(int kc) {
+    return kc >= 32 ? kc : ((kc + vec_of<T>() - 1) / vec_of<T>()) * vec_of<T>();
+}
+
+template <typename Tacc, int KS>
+__device__ __forceinline__ void load_row(const float *p, Tacc (&w)[KS]) {
+    const float4 *q = reinterpret_cast<const float4 *>(p);
+#pragma unroll
+    for (int v = 0; v < KS / 4; ++v) {
+        const float4 f = q[v];
+        w[4 * v] = (Tacc)f.x; w[4 * v + 1] = (Tacc)f.y; w[4 * v + 2] = (Tacc)f.z; w[4 * v + 3] = (Tacc)f.w;
+    }
+}
+template <typename Tacc, int KS>
+__device__ __forceinline__ void load_row(const double *p, Tacc (&w)[KS]) {
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+#pragma unroll
+    for (int v = 0; v < KS / 2; ++v) {
+        const double2 f = q[v];
+        w[2 * v] = (Tacc)f.x; w[2 * v + 1] = (Tacc)f.y;
+    }
+}
+template <typename Tacc, int KS>
+__device__ __forceinline__ void load_row(const uint16_t *p, Tacc (&w)[KS]) {
+    const uint4 *q = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int v = 0; v < KS / 8; ++v) {
+        const uint4 u = q[v];
+        const uint32_t x[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            w[8 * v + 2 * c] = (Tacc)__uint_as_float(x[c] << 16);
+            w[8 * v + 2 * c + 1] = (Tacc)__uint_as_float(x[c] & 0xFFFF0000u);
+        }
+    }
+}
+
+// Store K values (zero padded to the stride) of x into a storage row.
+template <int KC, typename Tacc>
+__device__ __forceinline__ void store_row(float *p, const Tacc (&x)[KC], int K) {
+    constexpr int KS = ks_of<float>(KC);
+    float4 *q = reinterpret_cast<float4 *>(p);
+#pragma unroll
+    for (int v = 0; v < KS / 4; ++v) {
+        float e[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int k = 4 * v + c;
+            e[c] = (k < KC && k < K) ? (float)x[k < KC ? k : 0] : 0.0f;
+        }
+        q[v] = make_float4(e[0], e[1], e[2], e[3]);
+    }
+}
+template <int KC, typename Tacc>
+__device__ __forceinline__ void store_row(double *p, const Tacc (&x)[KC], int K) {
+    constexpr int KS = ks_of<double>(KC);
+    double2 *q = reinterpret_cast<double2 *>(p);
+#pragma unroll
+    for (int v = 0; v < KS / 2; ++v) {
+        const int k0 = 2 * v, k1 = 2 * v + 1;
+        const double e0 = (k0 < KC && k0 < K) ? (double)x[k0 < KC ? k0 : 0] : 0.0;
+        const double e1 = (k1 < KC && k1 < K) ? (double)x[k1 < KC ? k1 : 0] : 0.0;
+        q[v] = make_double2(e0, e1);
+    }
+}
+template <int KC, typename Tacc>
+__device__ __forceinline__ void store_row_bf16(uint16_t *p, const Tacc (&x)[KC], int K) {
+    constexpr int KS = ks_of<uint16_t>(KC);
+    uint4 *q = reinterpret_cast<uint4 *>(p);
+#pragma unroll
+    for (int v = 0; v < KS / 8; ++v) {
+        uint32_t e[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int ka = 8 * v + 2 * c, kb = ka + 1;
+            const uint32_t lo = (ka < KC && ka < K) ? f32_to_bf16((float)x[ka < KC ? ka : 0]) : 0u;
+            const uint32_t hi = (kb < KC && kb < K) ? f32_to_bf16((float)x[kb < KC ? kb : 0]) : 0u;
+            e[c] = lo | (hi << 16);
+        }
+        q[v] = make_uint4(e[0], e[1], e[2], e[3]);
+    }
+}
+
+__host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+
+template <typename T> __device__ __forceinline__ double elem_to_d(T v) { return (double)v; }
+template <> __device__ __forceinline__ double elem_to_d<uint16_t>(uint16_t v) { return (double)bf16_to_f32(v); }
+template <typename T> __device__ __forceinline__ T elem_from(double v) { return (T)v; }
+template <> __device__ __forceinline__ uint16_t elem_from<uint16_t>(double v) { return f32_to_bf16((float)v); }
+
+template <int KC, typename Tacc>
+__device__ __forceinline__ void store_row(uint16_t *p, const Tacc (&x)[KC], int K) { store_row_bf16<KC>(p, x, K); }
+
+// --------------------------------------------------------------------------
+// k_update_reg: K <= KC <= 16, G lanes per entity, Gram in registers.
+// --------------------------------------------------------------------------
+template <int KC, int P>
+__global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
+    using Tacc = typename PrecT<P>::acc;
+    using Tw = typename PrecT<P>::w;
+    using Tv = typename PrecT<P>::v;
+    using Ts = typename PrecT<P>::s;
+    using Tp = typename PrecT<P>::p;
+    constexpr int NT = KC * (KC + 1) / 2;
+    constexpr int KSW = ks_of<Tw>(KC);
+    constexpr int KSS = ks_of<Ts>(KC);
+    constexpr int KSP = ks_of<Tp>(KC);
+    constexpr bool kFP32 = sizeof(Tacc) == 4;
+
+    const Tile tl = a.tiles[blockIdx.x];
+    const int G = tl.G;                    // lanes per entity: 1..64, or 128/256 (several waves)
+    const int grp = threadIdx.x / G;
+    const bool wide = G > 64;              // uniform per tile
+    if (!wide && grp >= tl.count) return;  // whole groups only: shuffles stay inside a group
+    const bool active = grp < tl.count;
+    const int gl = threadIdx.x & (G - 1);
+    const SideDesc &sd = a.sides[tl.side];
+    const int K = a.K;
+    const int n = active ? a.ord[tl.start + grp] : 0;
+    const int64_t p0 = active ? a.ptr[sd.ptr_off + n] : 0;
+    const int64_t p1 = active ? a.ptr[sd.ptr_off + n + 1] : 0;
+    const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * KSW;
+    const Tv *val = reinterpret_cast<const Tv *>(a.val);
+
+    Tacc g[NT];
+    Tacc hs[KC];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) g[q] = 0;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) hs[i] = 0;
+
+    // two entries per iteration: both gathers are in flight before the FMAs
+    int64_t e = p0 + gl;
+    for (; e + G < p1; e += 2 * G) {
+        const int d0 = a.idx[e], d1 = a.idx[e + G];
+        const Tacc r0 = (Tacc)val[e], r1 = (Tacc)val[e + G];
+        Tacc w0[KSW], w1[KSW];
+        load_row<Tacc, KSW>(other + (int64_t)d0 * KSW, w0);
+        load_row<Tacc, KSW>(other + (int64_t)d1 * KSW, w1);
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            hs[i] += r0 * w0[i];
+            hs[i] += r1 * w1[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                g[tri(i, j)] += w0[i] * w0[j];
+                g[tri(i, j)] += w1[i] * w1[j];
+            }
+        }
+    }
+    if (e < p1) {
+        const int d = a.idx[e];
+        const Tacc r = (Tacc)val[e];
+        Tacc w[KSW];
+        load_row<Tacc, KSW>(other + (int64_t)d * KSW, w);
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            hs[i] += r * w[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) g[tri(i, j)] += w[i] * w[j];
+        }
+    }
+    // butterfly inside the wave: every lane of the group ends with bitwise
+    // identical sums
+    const int Gw = G < 64 ? G : 64;
+    for (int m = 1; m < Gw; m <<= 1) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q) g[q] += __shfl_xor(g[q], m);
+#pragma unroll
+        for (int i = 0; i < KC; ++i) hs[i] += __shfl_xor(hs[i], m);
+    }
+    if (wide) {
+        // groups spanning several waves: wave sums through LDS, added in wave order
+        __shared__ Tacc wsum[4][NT + KC];
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+            for (int q = 0; q < NT; ++q) wsum[wave][q] = g[q];
+#pragma unroll
+            for (int i = 0; i < KC; ++i) wsum[wave][NT + i] = hs[i];
+        }
+        __syncthreads();
+        const int w0 = (grp * G) >> 6, nw = G >> 6;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            Tacc v = wsum[w0][q];
+            for (int u = 1; u < nw; ++u) v += wsum[w0 + u][q];
+            g[q] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            Tacc v = wsum[w0][NT + i];
+            for (int u = 1; u < nw; ++u) v += wsum[w0 + u][NT + i];
+            hs[i] = v;
+        }
+        if (!active) return;
+    }
+
+    // A = P + tau G, h = P m + tau hs (identity padding beyond K)
+    const Tacc tau = (Tacc)(*sd.tau);
+    if (sd.per_row) {
+        const double *pr = sd.prior + (int64_t)n * a.prow;
+        const double *eta = pr + K * (K + 1) / 2;
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                g[tri(i, j)] = (i < K) ? (Tacc)pr[tri(i, j)] + tau * g[tri(i, j)] : (Tacc)(i == j);
+            hs[i] = (i < K) ? (Tacc)eta[i] + tau * hs[i] : (Tacc)0;
+        }
+    } else {
+        const double *Lam = sd.prior;
+        const double *Lmu = sd.prior + K * K + K;
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                g[tri(i, j)] = (i < K) ? (Tacc)Lam[i * K + j] + tau * g[tri(i, j)] : (Tacc)(i == j);
+            hs[i] = (i < K) ? (Tacc)Lmu[i] + tau * hs[i] : (Tacc)0;
+        }
+    }
+
+    // Cholesky (column by column) with the pivot test
+    const Tacc theta = (Tacc)a.theta;
+    bool ok = true;
+    Tacc inv[KC];
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        const Tacc diag = g[tri(j, j)];
+        Tacc dj = diag;
+#pragma unroll
+        for (int p = 0; p < j; ++p) dj -= g[tri(j, p)] * g[tri(j, p)];
+        ok = ok && (kFP32 ? (dj > theta * diag) : (dj > (Tacc)0));
+        dj = dj > (Tacc)0 ? dj : (Tacc)1;
+        const Tacc l = sqrt(dj);
+        const Tacc il = (Tacc)1 / l;
+        g[tri(j, j)] = l;
+        inv[j] = il;
+#pragma unroll
+        for (int i = j + 1; i < KC; ++i) {
+            Tacc s = g[tri(i, j)];
+#pragma unroll
+            for (int p = 0; p < j; ++p) s -= g[tri(i, p)] * g[tri(j, p)];
+            g[tri(i, j)] = s * il;
+        }
+    }
+    if (!ok) {
+        if (gl == 0) {
+            if (a.fb_list) {
+                const int slot = atomicAdd(a.fb_count, 1);
+                a.fb_list[slot] = make_int2(tl.side, n);
+                atomicAdd(a.fb_total, 1);
+            } else {
+                atomicAdd(a.nonpd, 1);
+            }
+        }
+        return;
+    }
+
+    // y = L^-1 h;  y += z;  x = L^-T y
+    Tacc y[KC];
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+        Tacc s = hs[i];
+#pragma unroll
+        for (int p = 0; p < i; ++p) s -= g[tri(i, p)] * y[p];
+        y[i] = s * inv[i];
+    }
+#pragma unroll
+    for (int q = 0; q < (KC + 3) / 4; ++q) {
+        if (4 * q < K) {
+            Tacc z[4];
+            normals4((uint32_t)n, a.t, sd.c2, (uint32_t)q, a.k0, a.k1, z);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (4 * q + c < KC && 4 * q + c < K) y[4 * q + c < KC ? 4 * q + c : 0] += z[c];
+        }
+    }
+    Tacc x[KC];
+#pragma unroll
+    for (int i = KC - 1; i >= 0; --i) {
+        Tacc s = y[i];
+#pragma unroll
+        for (int p = i + 1; p < KC; ++p) s -= g[tri(p, i)] * x[p];
+        x[i] = s * inv[i];
+    }
+
+    if (gl == 0) {
+        Ts *self = reinterpret_cast<Ts *>(a.self);
+        store_row<KC>(self + (sd.self_off + n) * KSS, x, K);
+        if (a.sample) store_row<KC>(reinterpret_cast<Tp *>(a.sample) + (sd.sample_off + n) * KSP, x, K);
+    }
+}
+
+
+// --------------------------------------------------------------------------
+// LDS linear algebra for one wavefront (all 64 lanes call these)
+// --------------------------------------------------------------------------
+// In-place Cholesky of the leading K x K block of M (row stride ld, lower
+// triangle).  With theta > 0 a pivot that is not above theta * diag0[k] fails;
+// with theta = 0 a pivot that is not positive fails.  *flag is LDS scratch.
+template <typename T>
+__device__ bool chol_lds(T *M, int K, int ld, T theta, const T *diag0, int lane, int *flag) {
+    if (lane == 0) *flag = 0;
+    __syncthreads();
+    for (int k = 0; k < K; ++k) {
+        if (lane == 0) {
+            const T d = M[k * ld + k];
+            const bool bad = (theta > (T)0) ? !(d > theta * diag0[k]) : !(d > (T)0);
+            if (bad) *flag = 1;
+            M[k * ld + k] = sqrt(d > (T)0 ? d : (T)1);
+        }
+        __syncthreads();
+        const T lkk = M[k * ld + k];
+        for (int i = k + 1 + lane; i < K; i += 64) M[i * ld + k] /= lkk;
+        __syncthreads();
+        for (int i = k + 1 + lane; i < K; i += 64) {
+            const T lik = M[i * ld + k];
+            for (int j = k + 1; j <= i; ++j) M[i * ld + j] -= lik * M[j * ld + k];
+        }
+        __syncthreads();
+    }
+    return *flag == 0;
+}
+
+// y <- L^-1 y, L lower in M.
+template <typename T>
+__device__ void fwd_lds(const T *M, int K, int ld, T *y, int lane) {
+    for (int k = 0; k < K; ++k) {
+        if (lane == 0) y[k] /= M[k * ld + k];
+        __syncthreads();
+        const T yk = y[k];
+        for (int i = k + 1 + lane; i < K; i += 64) y[i] -= M[i * ld + k] * yk;
+        __syncthreads();
+    }
+}
+
+// x <- L^-T x, L lower in M.
+template <typename T>
+__device__ void bwd_lds(const T *M, int K, int ld, T *x, int lane) {
+    for (int k = K - 1; k >= 0; --k) {
+        if (lane == 0) x[k] /= M[k * ld + k];
+        __syncthreads();
+        const T xk = x[k];
+        for (int i = lane; i < k; i += 64) x[i] -= M[k * ld + i] * xk;
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void unrank_tri(int q, int &r, int &c) {
+    r = 0;
+    while ((r + 1) * (r + 2) / 2 <= q) ++r;
+    c = q - r * (r + 1) / 2;
+}
+
+template <typename T> __device__ __forceinline__ T to_acc(float v) { return (T)v; }
+template <typename T> __device__ __forceinline__ T to_acc(double v) { return (T)v; }
+template <typename T> __device__ __forceinline__ T to_acc(uint16_t v) { return (T)bf16_to_f32(v); }
+
+// --------------------------------------------------------------------------
+// k_update_wave: one wavefront per entity, any K <= KP.
+// --------------------------------------------------------------------------
+template <int KP, int P>
+__global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
+    using Tacc = typename PrecT<P>::acc;
+    using Tw = typename PrecT<P>::w;
+    using Tv = typename PrecT<P>::v;
+    using Ts = typename PrecT<P>::s;
+    using Tp = typename PrecT<P>::p;
+    constexpr int TL = KP / 8;
+    constexpr int CH = 32;
+    constexpr int LD = KP + 1;
+    __shared__ Tacc sA[KP * LD];
+    __shared__ Tacc sw[CH * KP];
+    __shared__ Tacc sr[CH];
+    __shared__ Tacc sh[KP];
+    __shared__ Tacc sz[KP];
+    __shared__ Tacc sd0[KP];
+    __shared__ int sflag;
+
+    const int lane = threadIdx.x;
+    const int K = a.K;
+    const int nitems = a.nitems_dev ? *a.nitems_dev : a.nitems;
+    const int ti = lane >> 3, tj = lane & 7;
+    const Tw *otherb = reinterpret_cast<const Tw *>(a.other);
+    const Tv *val = reinterpret_cast<const Tv *>(a.val);
+
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int2 item = a.items[it];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        const int64_t p0 = a.ptr[sd.ptr_off + n];
+        const int64_t p1 = a.ptr[sd.ptr_off + n + 1];
+        const Tw *other = otherb + sd.other_off * a.ks_other;
+
+        Tacc acc[TL][TL];
+        Tacc hacc[TL];
+#pragma unroll
+        for (int i = 0; i < TL; ++i) {
+            hacc[i] = 0;
+#pragma unroll
+            for (int j = 0; j < TL; ++j) acc[i][j] = 0;
+        }
+        for (int64_t c0 = p0; c0 < p1; c0 += CH) {
+            const int nc = (int)((p1 - c0) < CH ? (p1 - c0) : CH);
+            __syncthreads();
+            for (int q = lane; q < CH * KP; q += 64) {
+                const int nz = q / KP, k = q - nz * KP;
+                Tacc v = 0;
+                if (nz < nc && k < K) v = to_acc<Tacc>(other[(int64_t)a.idx[c0 + nz] * a.ks_other + k]);
+                sw[q] = v;
+            }
+            if (lane < CH) sr[lane] = lane < nc ? (Tacc)val[c0 + lane] : (Tacc)0;
+            __syncthreads();
+            for (int nz = 0; nz < nc; ++nz) {
+                Tacc wi[TL], wj[TL];
+#pragma unroll
+                for (int i = 0; i < TL; ++i) {
+                    wi[i] = sw[nz * KP + ti * TL + i];
+                    wj[i] = sw[nz * KP + tj * TL + i];
+                }
+#pragma unroll
+                for (int i = 0; i < TL; ++i)
+#pragma unroll
+                    for (int j = 0; j < TL; ++j) acc[i][j] += wi[i] * wj[j];
+                if (tj == 0) {
+                    const Tacc r = sr[nz];
+#pragma unroll
+                    for (int i = 0; i < TL; ++i) hacc[i] += r * wi[i];
+                }
+            }
+        }
+        __syncthreads();
+
+        const Tacc tau = (Tacc)(*sd.tau);
+        const double *pr = sd.per_row ? sd.prior + (int64_t)n * a.prow : sd.prior;
+        const double *pv = sd.per_row ? pr + K * (K + 1) / 2 : pr + K * K + K;
+#pragma unroll
+        for (int i = 0; i < TL; ++i) {
+#pragma unroll
+            for (int j = 0; j < TL; ++j) {
+                const int ra = ti * TL + i, cb = tj * TL + j;
+                Tacc v;
+                if (ra < K && cb < K) {
+                    const double p = sd.per_row ? pr[ra >= cb ? tri(ra, cb) : tri(cb, ra)] : pr[ra * K + cb];
+                    v = (Tacc)p + tau * acc[i][j];
+                } else {
+                    v = (Tacc)(ra == cb);
+                }
+                sA[ra * LD + cb] = v;
+            }
+        }
+        if (tj == 0) {
+#pragma unroll
+            for (int i = 0; i < TL; ++i) {
+                const int ra = ti * TL + i;
+                sh[ra] = ra < K ? (Tacc)pv[ra] + tau * hacc[i] : (Tacc)0;
+            }
+        }
+        if (lane * 4 < K) {
+            Tacc z[4];
+            normals4((uint32_t)n, a.t, sd.c2, (uint32_t)lane, a.k0, a.k1, z);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (4 * lane + c < K) sz[4 * lane + c] = z[c];
+        }
+        __syncthreads();
+        if (lane < KP) sd0[lane] = sA[lane * LD + lane];
+        __syncthreads();
+        const bool ok = chol_lds<Tacc>(sA, K, LD, (Tacc)a.theta, sd0, lane, &sflag);
+        if (!ok) {
+            if (lane == 0) {
+                if (a.fb_list) {
+                    const int slot = atomicAdd(a.fb_count, 1);
+                    a.fb_list[slot] = make_int2(item.x, n);
+                    atomicAdd(a.fb_total, 1);
+                } else {
+                    atomicAdd(a.nonpd, 1);
+                }
+            }
+            continue;
+        }
+        fwd_lds<Tacc>(sA, K, LD, sh, lane);
+        if (lane < K) sh[lane] += sz[lane];
+        __syncthreads();
+        bwd_lds<Tacc>(sA, K, LD, sh, lane);
+        const Tacc xv = lane < K ? sh[lane] : (Tacc)0;
+        Ts *self = reinterpret_cast<Ts *>(a.self);
+        if (lane < a.ks_self) self[(sd.self_off + n) * a.ks_self + lane] = elem_from<Ts>((double)xv);
+        if (a.sample && lane < a.ks_sample)
+            reinterpret_cast<Tp *>(a.sample)[(sd.sample_off + n) * a.ks_sample + lane] = (Tp)xv;
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_sse: sum of squared residuals of each row tile, fixed-order reduction.
+// --------------------------------------------------------------------------
+template <int KC, int P>
+__global__ __launch_bounds__(256) void k_sse(const SseArgs a) {
+    using Tacc = typename PrecT<P>::acc;
+    using Ts = typename PrecT<P>::s;
+    using Tv = typename PrecT<P>::v;
+    constexpr int KS = ks_of<Ts>(KC);
+    __shared__ double red[256];
+    const Tile tl = a.tiles[blockIdx.x];
+    const int G = tl.G;
+    const int grp = threadIdx.x / G;
+    const int gl = threadIdx.x & (G - 1);
+    double s = 0.0;
+    if (grp < tl.count) {
+        const SideDesc &sd = a.sides[tl.side];
+        const int n = a.ord[tl.start + grp];
+        const int64_t p0 = a.ptr[sd.ptr_off + n], p1 = a.ptr[sd.ptr_off + n + 1];
+        const Ts *W = reinterpret_cast<const Ts *>(a.W) + sd.other_off * KS;
+        const Tv *val = reinterpret_cast<const Tv *>(a.val);
+        Tacc xr[KS];
+        load_row<Tacc, KS>(reinterpret_cast<const Ts *>(a.X) + (sd.self_off + n) * KS, xr);
+        for (int64_t e = p0 + gl; e < p1; e += G) {
+            Tacc w[KS];
+            load_row<Tacc, KS>(W + (int64_t)a.idx[e] * KS, w);
+            Tacc pred = 0;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) pred += xr[k] * w[k];
+            const double res = (double)((Tacc)val[e] - pred);
+            s += res * res;
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.part[a.part_base + blockIdx.x] = red[0];
+}
+
+// --------------------------------------------------------------------------
+// k_stats: FP64 partial sums sum x and sum x x^T of one side (for the
+// Normal-Wishart draw).  A job covers a contiguous range of entities, staged
+// through LDS in sub-chunks; thread (pair p, slice s) sums its pair over its
+// slice of rows and slices are combined in order.  k_reduce then sums the
+// jobs of a side in job order.  Fixed order throughout: deterministic.
+// --------------------------------------------------------------------------
+template <typename Ts>
+__global__ __launch_bounds__(256) void k_stats(const StatsArgs a) {
+    constexpr int kLds = 4096;                 // doubles of staged factors
+    constexpr int kMaxPairsPerThread = 9;      // ceil((64 + 64*65/2) / 256)
+    __shared__ double xs[kLds];
+    __shared__ double red[256 * 2];
+    __shared__ short pr_a[2144], pr_b[2144];
+    const StatsJob jb = a.jobs[blockIdx.x];
+    const SideDesc &sd = a.sides[jb.side];
+    const Ts *X = reinterpret_cast<const Ts *>(a.X) + sd.self_off * a.ks;
+    const int K = a.K;
+    const int npair = K + K * (K + 1) / 2;
+    const int t = threadIdx.x;
+    for (int p = t; p < npair; p += 256) {
+        int ra, cb;
+        if (p < K) { ra = p; cb = -1; } else unrank_tri(p - K, ra, cb);
+        pr_a[p] = (short)ra;
+        pr_b[p] = (short)cb;
+    }
+    // thread layout: S slices of npair threads when npair <= 256
+    const int S = npair <= 256 ? 256 / npair : 1;
+    const int slice = npair <= 256 ? t / npair : 0;
+    const int p0 = npair <= 256 ? t % npair : t;
+    const bool active = slice < S;
+    double acc[kMaxPairsPerThread];
+#pragma unroll
+    for (int q = 0; q < kMaxPairsPerThread; ++q) acc[q] = 0.0;
+    const int sc = kLds / K;                   // rows per sub-chunk
+    for (int r0 = 0; r0 < jb.count; r0 += sc) {
+        const int nr = min(sc, jb.count - r0);
+        __syncthreads();
+        for (int q = t; q < nr * K; q += 256) {
+            const int r = q / K, k = q - r * K;
+            xs[q] = elem_to_d(X[(int64_t)(jb.first + r0 + r) * a.ks + k]);
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int q = 0; q < kMaxPairsPerThread; ++q) {
+                const int p = p0 + 256 * q;
+                if (p < npair && (npair <= 256 ? q == 0 : true)) {
+                    const int ra = pr_a[p], cb = pr_b[p];
+                    double s0 = 0.0, s1 = 0.0;
+                    int r = slice;
+                    for (; r + S < nr; r += 2 * S) {
+                        const double x0 = xs[r * K + ra], x1 = xs[(r + S) * K + ra];
+                        s0 += cb < 0 ? x0 : x0 * xs[r * K + cb];
+                        s1 += cb < 0 ? x1 : x1 * xs[(r + S) * K + cb];
+                    }
+                    if (r < nr) {
+                        const double x0 = xs[r * K + ra];
+                        s0 += cb < 0 ? x0 : x0 * xs[r * K + cb];
+                    }
+                    acc[q] += s0 + s1;
+                }
+            }
+        }
+    }
+    // combine slices in order, write the job partial
+    double *part = a.part + (int64_t)jb.part * npair;
+    if (npair <= 256) {
+        __syncthreads();
+        if (active) red[t] = acc[0];
+        __syncthreads();
+        if (t < npair) {
+            double s = 0.0;
+            for (int q = 0; q < S; ++q) s += red[q * npair + t];
+            part[t] = s;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < kMaxPairsPerThread; ++q)
+            if (p0 + 256 * q < npair) part[p0 + 256 * q] = acc[q];
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_reduce: dst[p] = sum_{q < count} src[q * width + p], one workgroup per job.
+// Thread t takes element p = t mod E and the q-slice t div E (E = min(width,
+// 256)); each slice sums its q's in increasing order, slices are then added
+// in slice order.  Deterministic for a given (count, width).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(const ReduceJob *jobs) {
+    __shared__ double red[256];
+    const ReduceJob jb = jobs[blockIdx.x];
+    const int t = threadIdx.x;
+    const int E = jb.width < 256 ? jb.width : 256;
+    const int Q = 256 / E;
+    const int s = t / E;
+    for (int base = 0; base < jb.width; base += E) {
+        const int p = base + t % E;
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        if (s < Q && p < jb.width) {
+            int q = s;
+            for (; q + 3 * Q < jb.count; q += 4 * Q) {
+                acc0 += jb.src[(int64_t)q * jb.width + p];
+                acc1 += jb.src[(int64_t)(q + Q) * jb.width + p];
+                acc2 += jb.src[(int64_t)(q + 2 * Q) * jb.width + p];
+                acc3 += jb.src[(int64_t)(q + 3 * Q) * jb.width + p];
+            }
+            for (; q < jb.count; q += Q) acc0 += jb.src[(int64_t)q * jb.width + p];
+        }
+        __syncthreads();
+        red[t] = (acc0 + acc1) + (acc2 + acc3);
+        __syncthreads();
+        if (t < E && p < jb.width) {
+            double v = 0.0;
+            for (int q = 0; q < Q; ++q) v += red[q * E + t];
+            jb.dst[p] = v;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_hyper: Normal-Wishart draw of one side of one block, or a tau draw (FP64).
+//   x_bar = sum x / N,  N S_bar = sum x x^T - N x_bar x_bar^T (the footnote's
+//   alternative to the centred form), beta* = beta0 + N, nu* = nu0 + N,
+//   mu* = (beta0 mu0 + N x_bar) / beta*,
+//   W*^-1 = W0^-1 + N S_bar + (beta0 N / beta*) (mu0 - x_bar)(mu0 - x_bar)^T;
+//   Bartlett: R R^T = W*^-1, T = R^-T, A lower (A_kk^2 ~ chi2(nu* - k + 1),
+//   A_kl ~ N(0,1)), Lambda = (T A)(T A)^T; mu = mu* + beta*^-1/2 C^-T z with
+//   C C^T = Lambda.  tau ~ Gamma(a0 + M/2, rate b0 + SSE/2).
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
+    constexpr int LD = 64;
+    __shared__ double M0[64 * LD];
+    __shared__ double M1[64 * LD];
+    __shared__ double M2[64 * LD];
+    __shared__ double sx[64], xbar[64], mus[64], zz[64];
+    __shared__ int flag;
+    const HyperJob jb = a.jobs[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int K = a.K;
+    if (jb.kind == 2) {
+        if (lane == 0) {
+            const double s = a.sse_part[jb.part_begin];
+            const double shape = a.a0 + 0.5 * (double)jb.n;
+            const double rate = a.b0 + 0.5 * s;
+            *jb.out = gamma_draw(a.k0, a.k1, 0u, a.t, counter_word(jb.block, kTau), shape) / rate;
+        }
+        return;
+    }
+    const uint32_t c2 = counter_word(jb.block, jb.kind == 0 ? kHyperX : kHyperW);
+    const int npair = K + K * (K + 1) / 2;
+    // 1. the side's sums (reduced in fixed order by the statistics kernel)
+    for (int p = lane; p < npair; p += 64) {
+        const double s = a.part[(int64_t)jb.part_begin * npair + p];
+        if (p < K) {
+            sx[p] = s;
+        } else {
+            int r, c;
+            unrank_tri(p - K, r, c);
+            M0[r * LD + c] = s;
+            M0[c * LD + r] = s;
+        }
+    }
+    __syncthreads();
+    const double N = (double)jb.n;
+    const double beta_s = a.beta0 + N, nu_s = a.nu0 + N;
+    if (lane < K) {
+        xbar[lane] = sx[lane] / N;
+        mus[lane] = (a.beta0 * a.mu0[lane] + sx[lane]) / beta_s;
+    }
+    __syncthreads();
+    // 2. W*^-1
+    const double coef = a.beta0 * N / beta_s;
+    for (int q = lane; q < K * K; q += 64) {
+        const int r = q / K, c = q - r * K;
+        const double ns = M0[r * LD + c] - N * xbar[r] * xbar[c];
+        M0[r * LD + c] = a.W0inv[r * K + c] + ns + coef * (a.mu0[r] - xbar[r]) * (a.mu0[c] - xbar[c]);
+    }
+    __syncthreads();
+    // 3. R = chol(W*^-1)
+    bool ok = chol_lds<double>(M0, K, LD, 0.0, nullptr, lane, &flag);
+    // 4. M1 = R^-1 (lower), column c by lane c
+    for (int c = lane; c < K; c += 64) {
+        for (int i = 0; i < K; ++i) {
+            if (i < c) {
+                M1[i * LD + c] = 0.0;
+            } else {
+                double s = (i == c) ? 1.0 : 0.0;
+                for (int p = c; p < i; ++p) s -= M0[i * LD + p] * M1[p * LD + c];
+                M1[i * LD + c] = s / M0[i * LD + i];
+            }
+        }
+    }
+    // 5. Bartlett factor into M2
+    for (int q = lane; q < K * K; q += 64) M2[q / K * LD + q % K] = 0.0;
+    __syncthreads();
+    if (lane < K)
+        M2[lane * LD + lane] =
+            sqrt(2.0 * gamma_draw(a.k0, a.k1, (uint32_t)(lane + 1), a.t, c2, 0.5 * (nu_s - lane)));
+    const int noff = K * (K - 1) / 2;
+    for (int g = lane; 4 * g < noff; g += 64) {
+        double z[4];
+        normals4(0u, a.t, c2, (uint32_t)g, a.k0, a.k1, z);
+        for (int c = 0; c < 4; ++c) {
+            const int q = 4 * g + c;
+            if (q < noff) {
+                int r, cc;
+                unrank_tri(q, r, cc);          // strict lower, row-major: row r+1, column cc
+                M2[(r + 1) * LD + cc] = z[c];
+            }
+        }
+    }
+    __syncthreads();
+    // 6. B = T A with T[r][p] = M1[p][r] (p >= r) and A[p][c] = M2[p][c] (p >= c) -> M0
+    for (int q = lane; q < K * K; q += 64) {
+        const int r = q / K, c = q - r * K;
+        double s = 0.0;
+        for (int p = (r > c ? r : c); p < K; ++p) s += M1[p * LD + r] * M2[p * LD + c];
+        M0[r * LD + c] = s;
+    }
+    __syncthreads();
+    // 7. Lambda = B B^T -> M1 and the output
+    double *outL = jb.out;
+    for (int q = lane; q < K * K; q += 64) {
+        const int r = q / K, c = q - r * K;
+        double s = 0.0;
+        for (int p = 0; p < K; ++p) s += M0[r * LD + p] * M0[c * LD + p];
+        M1[r * LD + c] = s;
+        M2[r * LD + c] = s;
+        outL[q] = s;
+    }
+    __syncthreads();
+    // 8. C = chol(Lambda) in M2; 9. mu = mu* + C^-T z / sqrt(beta*)
+    ok = chol_lds<double>(M2, K, LD, 0.0, nullptr, lane, &flag) && ok;
+    if (lane * 4 < K) {
+        double z[4];
+        normals4((uint32_t)(K + 1), a.t, c2, (uint32_t)lane, a.k0, a.k1, z);
+        for (int c = 0; c < 4; ++c)
+            if (4 * lane + c < K) zz[4 * lane + c] = z[c];
+    }
+    __syncthreads();
+    bwd_lds<double>(M2, K, LD, zz, lane);
+    if (lane < K) {
+        const double m = mus[lane] + zz[lane] / sqrt(beta_s);
+        sx[lane] = m;
+        outL[K * K + lane] = m;
+    }
+    __syncthreads();
+    if (lane < K) {
+        double s = 0.0;
+        for (int c = 0; c < K; ++c) s += M1[lane * LD + c] * sx[c];
+        outL[K * K + K + lane] = s;
+    }
+    if (!ok && lane == 0) atomicAdd(a.nonpd, 1);
+}
+
+// --------------------------------------------------------------------------
+// k_init: initial factors (K^-1/4 z from the INIT counters, or the propagated
+// means) for every entity of the listed sides.
+// --------------------------------------------------------------------------
+template <typename Ts>
+__global__ __launch_bounds__(256) void k_init(const InitArgs a) {
+    const int K = a.K;
+    const double scale = pow((double)K, -0.25);
+    for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < a.nitems; it += gridDim.x * blockDim.x) {
+        const int2 item = a.items[it];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        Ts *dst = reinterpret_cast<Ts *>(a.self) + (sd.self_off + n) * a.ks_self;
+        for (int k = K; k < a.ks_self; ++k) dst[k] = elem_from<Ts>(0.0);
+        if (sd.per_row) {
+            const double *mu = sd.prior + (int64_t)n * a.prow + K * (K + 1) / 2 + K;
+            for (int k = 0; k < K; ++k) dst[k] = elem_from<Ts>(mu[k]);
+        } else {
+            for (int g = 0; 4 * g < K; ++g) {
+                double z[4];
+                normals4((uint32_t)n, 0xFFFFFFFFu, sd.c2_init, (uint32_t)g, a.k0, a.k1, z);
+                for (int c = 0; c < 4 && 4 * g + c < K; ++c) dst[4 * g + c] = elem_from<Ts>(scale * z[c]);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_mm: moment matching of one entity from the S kept samples (FP64):
+// mean, covariance with 1/(S-1) (two passes), ridge when S <= K or not SPD,
+// Lambda_hat = L^-T L^-1, eta = Lambda_hat mu_hat.  Output row:
+// [Lambda_hat packed lower, eta, mu_hat].
+// --------------------------------------------------------------------------
+template <typename Ts>
+__global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
+    constexpr int LD = 64;
+    __shared__ double sig[64 * LD];
+    __shared__ double lin[64 * LD];
+    __shared__ double mu[64];
+    __shared__ int flag;
+    const int lane = threadIdx.x;
+    const int K = a.K, S = a.S;
+    const int kk2 = K * (K + 1) / 2;
+    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        const int2 item = a.items[it];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        const Ts *smp = reinterpret_cast<const Ts *>(a.sample) + (sd.sample_off + n) * a.ks;
+        double *out = a.out[item.x] + (int64_t)n * a.prow;
+        if (lane < K) {
+            double s = 0.0;
+            for (int q = 0; q < S; ++q) s += (double)smp[(int64_t)q * a.slot_elems + lane];
+            mu[lane] = s / (double)S;
+        }
+        __syncthreads();
+        if (S < 2) {
+            for (int q = lane; q < kk2 + K; q += 64) out[q] = 0.0;
+            if (lane < K) out[kk2 + K + lane] = mu[lane];
+            __syncthreads();
+            continue;
+        }
+        for (int q = lane; q < K * K; q += 64) {
+            const int r = q / K, c = q - r * K;
+            if (c <= r) {
+                double s = 0.0;
+                for (int t = 0; t < S; ++t)
+                    s += ((double)smp[(int64_t)t * a.slot_elems + r] - mu[r]) *
+                         ((double)smp[(int64_t)t * a.slot_elems + c] - mu[c]);
+                s /= (double)(S - 1);
+                sig[r * LD + c] = s;
+                sig[c * LD + r] = s;
+            }
+        }
+        __syncthreads();
+        bool need = S <= K;
+        if (!need) {
+            for (int q = lane; q < K * K; q += 64) lin[q / K * LD + q % K] = sig[q / K * LD + q % K];
+            __syncthreads();
+            need = !chol_lds<double>(lin, K, LD, 0.0, nullptr, lane, &flag);
+        }
+        if (need) {
+            double tr = 0.0;
+            for (int k = 0; k < K; ++k) tr += sig[k * LD + k];
+            const double delta = 1e-6 * tr / (double)K + 1e-300;
+            __syncthreads();
+            if (lane < K) sig[lane * LD + lane] += delta;
+            __syncthreads();
+            for (int q = lane; q < K * K; q += 64) lin[q / K * LD + q % K] = sig[q / K * LD + q % K];
+            __syncthreads();
+            chol_lds<double>(lin, K, LD, 0.0, nullptr, lane, &flag);
+            if (lane == 0) atomicAdd(a.ridged, 1);
+        }
+        // sig <- L^-1 (column c by lane c)
+        for (int c = lane; c < K; c += 64) {
+            for (int i = 0; i < K; ++i) {
+                if (i < c) {
+                    sig[i * LD + c] = 0.0;
+                } else {
+                    double s = (i == c) ? 1.0 : 0.0;
+                    for (int p = c; p < i; ++p) s -= lin[i * LD + p] * sig[p * LD + c];
+                    sig[i * LD + c] = s / lin[i * LD + i];
+                }
+            }
+        }
+        __syncthreads();
+        for (int q = lane; q < K * K; q += 64) {
+            const int r = q / K, c = q - r * K;
+            if (c <= r) {
+                double s = 0.0;
+                for (int p = r; p < K; ++p) s += sig[p * LD + r] * sig[p * LD + c];
+                lin[r * LD + c] = s;
+                lin[c * LD + r] = s;
+            }
+        }
+        __syncthreads();
+        for (int q = lane; q < kk2; q += 64) {
+            int r, c;
+            unrank_tri(q, r, c);
+            out[q] = lin[r * LD + c];
+        }
+        if (lane < K) {
+            double s = 0.0;
+            for (int c = 0; c < K; ++c) s += lin[lane * LD + c] * mu[c];
+            out[kk2 + lane] = s;
+            out[kk2 + K + lane] = mu[lane];
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_agg: Algorithm 2 for one row of a row (or column) block (FP64).
+// --------------------------------------------------------------------------
+// Smallest eigenvalue of the symmetric K x K matrix in A (destroyed), cyclic
+// Jacobi rotations (Golub & Van Loan, Sec. 8.5), single lane.
+__device__ double jacobi_min_eig(double *A, int K, int ld) {
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int p = 0; p < K; ++p)
+            for (int q = 0; q < K; ++q) {
+                const double v = A[p * ld + q] * A[p * ld + q];
+                tot += v;
+                if (p != q) off += v;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < K - 1; ++p) {
+            for (int q = p + 1; q < K; ++q) {
+                const double apq = A[p * ld + q];
+                if (apq == 0.0) continue;
+                const double th = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+                for (int k = 0; k < K; ++k) {
+                    const double akp = A[k * ld + p], akq = A[k * ld + q];
+                    A[k * ld + p] = c * akp - s * akq;
+                    A[k * ld + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < K; ++k) {
+                    const double apk = A[p * ld + k], aqk = A[q * ld + k];
+                    A[p * ld + k] = c * apk - s * aqk;
+                    A[q * ld + k] = s * apk + c * aqk;
+                }
+            }
+        }
+    }
+    double m = A[0];
+    for (int k = 1; k < K; ++k) m = fmin(m, A[k * ld + k]);
+    return m;
+}
+
+__global__ __launch_bounds__(64) void k_agg(const AggArgs a) {
+    constexpr int LD = 64;
+    __shared__ double Lb[64 * LD];
+    __shared__ double Ls[64 * LD];
+    __shared__ double Dm[64 * LD];
+    __shared__ double Wm[64 * LD];
+    __shared__ double mub[64], rhs[64];
+    __shared__ double lmin;
+    __shared__ int flag;
+    const int lane = threadIdx.x;
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        const int2 item = a.items[it];
+        const AggJob &jb = a.jobs[item.x];
+        const int n = item.y;
+        const double *brow = jb.base + (int64_t)n * a.prow;
+        double *out = a.out + (jb.out_off + n) * K;
+        if (jb.nsib == 0) {
+            if (lane < K) out[lane] = brow[kk2 + K + lane];
+            continue;
+        }
+        for (int q = lane; q < kk2; q += 64) {
+            int r, c;
+            unrank_tri(q, r, c);
+            Lb[r * LD + c] = brow[q];
+            Lb[c * LD + r] = brow[q];
+        }
+        if (lane < K) mub[lane] = brow[kk2 + K + lane];
+        __syncthreads();
+        const double cb = 2.0 - (double)(jb.nsib + 1);
+        for (int q = lane; q < K * K; q += 64) Ls[q / K * LD + q % K] = cb * Lb[q / K * LD + q % K];
+        if (lane < K) {
+            double s = 0.0;
+            for (int c = 0; c < K; ++c) s += Lb[lane * LD + c] * mub[c];
+            rhs[lane] = cb * s;
+        }
+        double tr = 0.0;
+        for (int k = 0; k < K; ++k) tr += Lb[k * LD + k];
+        const double eps = 1e-6 * tr / (double)K;
+        __syncthreads();
+        for (int s = 0; s < jb.nsib; ++s) {
+            const double *srow = jb.sib[s] + (int64_t)n * a.prow;
+            for (int q = lane; q < kk2; q += 64) {
+                int r, c;
+                unrank_tri(q, r, c);
+                const double v = srow[q];
+                Wm[r * LD + c] = v;
+                Wm[c * LD + r] = v;
+                Dm[r * LD + c] = v - Lb[r * LD + c];
+                Dm[c * LD + r] = v - Lb[c * LD + r];
+            }
+            __syncthreads();
+            const bool pd = chol_lds<double>(Dm, K, LD, 0.0, nullptr, lane, &flag);
+            if (!pd) {
+                for (int q = lane; q < K * K; q += 64) {
+                    const int r = q / K, c = q - r * K;
+                    Dm[r * LD + c] = Wm[r * LD + c] - Lb[r * LD + c];
+                }
+                __syncthreads();
+                if (lane == 0) {
+                    lmin = jacobi_min_eig(Dm, K, LD);
+                    atomicAdd(a.corrections, 1);
+                }
+                __syncthreads();
+                const double shift = fabs(lmin) + eps;
+                for (int q = lane; q < K * K; q += 64) {
+                    const int r = q / K, c = q - r * K;
+                    Wm[r * LD + c] = (Wm[r * LD + c] - Lb[r * LD + c]) + (r == c ? shift : 0.0) + Lb[r * LD + c];
+                }
+                __syncthreads();
+            }
+            for (int q = lane; q < K * K; q += 64) Ls[q / K * LD + q % K] += Wm[q / K * LD + q % K];
+            if (lane < K) {
+                double s2 = 0.0;
+                for (int c = 0; c < K; ++c) s2 += Wm[lane * LD + c] * srow[kk2 + K + c];
+                rhs[lane] += s2;
+            }
+            __syncthreads();
+        }
+        chol_lds<double>(Ls, K, LD, 0.0, nullptr, lane, &flag);
+        fwd_lds<double>(Ls, K, LD, rhs, lane);
+        bwd_lds<double>(Ls, K, LD, rhs, lane);
+        if (lane < K) out[lane] = rhs[lane];
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_predict: y_hat = y_bar + mu*_x^T mu*_w (FP64), one thread per pair.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.n;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const double *x = a.mux + a.xslot[q] * a.K;
+        const double *w = a.muw + a.wslot[q] * a.K;
+        double s = 0.0;
+        for (int k = 0; k < a.K; ++k) s += x[k] * w[k];
+        a.out[q] = (float)(a.ybar + s);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// --------------------------------------------------------------------------
+// host launchers
+// --------------------------------------------------------------------------
+int32_t capacity_for(int32_t K) {
+    const int32_t caps[] = {2, 4, 6, 8, 10, 12, 16, 32, 64};
+    for (int32_t c : caps)
+        if (K <= c) return c;
+    return -1;
+}
+
+int32_t stride_for(int32_t kc, int32_t elem_bytes) {
+    const int32_t v = 16 / elem_bytes;
+    return kc >= 32 ? kc : ((kc + v - 1) / v) * v;
+}
+
+static inline int grid_for(int64_t work, int per, int cap) {
+    int64_t g = (work + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+template <int KC>
+static hipError_t upd_reg_kc(int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {
+    switch (prec) {
+    case kP64: hipLaunchKernelGGL((k_update_reg<KC, kP64>), dim3(ntiles), dim3(256), 0, s, a); break;
+    case kP32: hipLaunchKernelGGL((k_update_reg<KC, kP32>), dim3(ntiles), dim3(256), 0, s, a); break;
+    case kPBF: hipLaunchKernelGGL((k_update_reg<KC, kPBF>), dim3(ntiles), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (kc) {
+    case 2: return upd_reg_kc<2>(prec, a, ntiles, s);
+    case 4: return upd_reg_kc<4>(prec, a, ntiles, s);
+    case 6: return upd_reg_kc<6>(prec, a, ntiles, s);
+    case 8: return upd_reg_kc<8>(prec, a, ntiles, s);
+    case 10: return upd_reg_kc<10>(prec, a, ntiles, s);
+    case 12: return upd_reg_kc<12>(prec, a, ntiles, s);
+    case 16: return upd_reg_kc<16>(prec, a, ntiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int KP>
+static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    switch (prec) {
+    case kP64: hipLaunchKernelGGL((k_update_wave<KP, kP64>), dim3(grid), dim3(64), 0, s, a); break;
+    case kP32: hipLaunchKernelGGL((k_update_wave<KP, kP32>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPBF: hipLaunchKernelGGL((k_update_wave<KP, kPBF>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPFB32: hipLaunchKernelGGL((k_update_wave<KP, kPFB32>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPFB16: hipLaunchKernelGGL((k_update_wave<KP, kPFB16>), dim3(grid), dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (kp <= 16) return upd_wave_kp<16>(prec, a, grid, s);
+    if (kp <= 32) return upd_wave_kp<32>(prec, a, grid, s);
+    if (kp <= 64) return upd_wave_kp<64>(prec, a, grid, s);
+    return hipErrorInvalidValue;
+}
+
+template <int KC>
+static hipError_t sse_kc(int32_t prec, const SseArgs &a, int32_t ntiles, hipStream_t s) {
+    if (prec == kP64)
+        hipLaunchKernelGGL((k_sse<KC, kP64>), dim3(ntiles), dim3(256), 0, s, a);
+    else if (prec == kPBF)
+        hipLaunchKernelGGL((k_sse<KC, kPBF>), dim3(ntiles), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sse<KC, kP32>), dim3(ntiles), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_sse(int32_t kc, int32_t prec, const SseArgs &a, int32_t ntiles, hipStream_t s) {
+    if (ntiles <= 0) return hipSuccess;
+    switch (kc) {
+    case 2: return sse_kc<2>(prec, a, ntiles, s);
+    case 4: return sse_kc<4>(prec, a, ntiles, s);
+    case 6: return sse_kc<6>(prec, a, ntiles, s);
+    case 8: return sse_kc<8>(prec, a, ntiles, s);
+    case 10: return sse_kc<10>(prec, a, ntiles, s);
+    case 12: return sse_kc<12>(prec, a, ntiles, s);
+    case 16: return sse_kc<16>(prec, a, ntiles, s);
+    case 32: return sse_kc<32>(prec, a, ntiles, s);
+    case 64: return sse_kc<64>(prec, a, ntiles, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    if (prec == kP64)
+        hipLaunchKernelGGL(k_stats<double>, dim3(njobs), dim3(256), 0, s, a);
+    else if (prec == kPBF)
+        hipLaunchKernelGGL(k_stats<uint16_t>, dim3(njobs), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_stats<float>, dim3(njobs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce, dim3(njobs), dim3(256), 0, s, jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hyper, dim3(njobs), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    const int g = grid_for(a.nitems, 256, 65536);
+    if (prec == kP64)
+        hipLaunchKernelGGL(k_init<double>, dim3(g), dim3(256), 0, s, a);
+    else if (prec == kPBF)
+        hipLaunchKernelGGL(k_init<uint16_t>, dim3(g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    const int g = grid_for(a.nitems, 1, 65536);
+    if (prec == kP64)
+        hipLaunchKernelGGL(k_mm<double>, dim3(g), dim3(64), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_mm<float>, dim3(g), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_agg(const AggArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_agg, dim3(grid_for(a.nitems, 1, 65536)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_predict, dim3(grid_for(a.n, 256, 65536)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace bmf

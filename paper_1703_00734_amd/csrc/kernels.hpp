@@ -1,0 +1,153 @@
+// Device kernels of the BMF library and their host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace bmf {
+
+// Arithmetic of a conditional-update launch.
+enum Prec : int32_t {
+    kP64 = 0,    // FP64 state, gathers and arithmetic
+    kP32 = 1,    // FP32 state and gathers, FP32 arithmetic
+    kPBF = 2,    // BF16 state and gathers, FP32 arithmetic, FP32 samples
+    kPFB32 = 3,  // FP32 state, FP64 arithmetic (pivot fallback of kP32)
+    kPFB16 = 4   // BF16 state, FP64 arithmetic (pivot fallback of kPBF)
+};
+
+// Capacity (compile-time K) used for a rank K: the register kernel handles
+// K <= 16 with capacities {2,4,6,8,10,12,16}; the wave kernel 32 and 64.
+int32_t capacity_for(int32_t K);
+// Row stride (elements) of a factor array for capacity kc and element size.
+int32_t stride_for(int32_t kc, int32_t elem_bytes);
+
+struct UpdArgs {
+    const Tile *tiles;        // register kernel: one tile per workgroup
+    const int2 *items;        // wave kernel: (side, entity) items ...
+    const int32_t *nitems_dev;// ... counted on the device (fallback queue), or
+    int32_t nitems;           // ... counted on the host when nitems_dev is null
+    const SideDesc *sides;
+    const int32_t *ord;       // degree-sorted local ids (register kernel)
+    const int64_t *ptr;
+    const int32_t *idx;
+    const void *val;          // double (kP64) or float
+    const void *other;        // gathered factors (the other side's state)
+    int32_t ks_other;
+    void *self;               // updated factors (state precision)
+    int32_t ks_self;
+    void *sample;             // this sweep's sample slot (null when not kept)
+    int32_t ks_sample;
+    int32_t K;
+    int32_t prow;             // doubles per moment-matched row
+    uint32_t t;               // sweep index (Philox c1)
+    uint32_t k0, k1;          // Philox key
+    float theta;              // FP32 pivot threshold (0 in FP64)
+    int32_t *fb_count;        // FP64 fallback queue (null: count as non-PD)
+    int2 *fb_list;
+    int32_t *fb_total;        // running count of rows sent to the fallback
+    int32_t *nonpd;           // FP64 Cholesky failures
+};
+
+struct SseArgs {
+    const Tile *tiles;        // CSR row tiles grouped by block (tile.side = block in stage)
+    const SideDesc *sides;    // row sides (self = X, other = W)
+    const int32_t *ord;
+    const int64_t *ptr;
+    const int32_t *idx;
+    const void *val;
+    const void *X;            // row factors (storage precision)
+    const void *W;            // column factors (storage precision)
+    int32_t ks;
+    double *part;             // one partial per tile ...
+    int32_t part_base;        // ... at part[part_base + tile]
+};
+
+struct StatsArgs {
+    const StatsJob *jobs;
+    const SideDesc *sides;
+    const void *X;            // factors of the side (storage precision)
+    int32_t ks;
+    int32_t K;
+    double *part;             // njobs x (K + K(K+1)/2)
+};
+
+// Fixed-order sum of `count` partial vectors of `width` doubles.
+struct ReduceJob {
+    const double *src;
+    double *dst;
+    int32_t count;
+    int32_t width;
+};
+
+struct HyperArgs {
+    const HyperJob *jobs;     // part_begin: slot of the final sums / final SSE
+    const double *part;       // NW final sums, per side
+    const double *sse_part;   // final SSE, per stage block
+    const double *mu0;        // K
+    const double *W0inv;      // K x K
+    double beta0, nu0, a0, b0;
+    int32_t K;
+    uint32_t t, k0, k1;
+    int32_t *nonpd;
+};
+
+struct InitArgs {
+    const int2 *items;        // (side, entity)
+    int32_t nitems;
+    const SideDesc *sides;
+    void *self;
+    int32_t ks_self;
+    int32_t K, prow;
+    uint32_t k0, k1;
+};
+
+struct MmArgs {
+    const int2 *items;        // (side, entity)
+    int32_t nitems;
+    const SideDesc *sides;    // sample_off per side
+    const void *sample;       // slot 0 of the sample store
+    int64_t slot_elems;       // elements per slot
+    int32_t ks;
+    int32_t S;                // kept samples
+    int32_t K, prow;
+    double *const *out;       // per side: moment-matched rows
+    int32_t *ridged;
+};
+
+struct AggArgs {
+    const AggJob *jobs;
+    const int2 *items;        // (job, row)
+    int32_t nitems;
+    int32_t K, prow;
+    double *out;              // aggregated means, K per slot
+    int32_t *corrections;
+};
+
+struct PredictArgs {
+    const int64_t *xslot;
+    const int64_t *wslot;
+    int64_t n;
+    const double *mux;
+    const double *muw;
+    int32_t K;
+    double ybar;
+    float *out;
+};
+
+hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t ntiles,
+                             hipStream_t s);
+hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid,
+                              hipStream_t s);
+hipError_t launch_sse(int32_t kc, int32_t prec, const SseArgs &a, int32_t ntiles, hipStream_t s);
+hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s);
+hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s);
+hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
+hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s);
+hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
+hipError_t launch_agg(const AggArgs &a, hipStream_t s);
+hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace bmf
