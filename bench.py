@@ -49,10 +49,23 @@ def algorithmic_bytes(kind, M, n, K, state_bytes, kept):
     return b
 
 
+def stages_of(cfg):
+    I, J = cfg["I"], cfg["J"]
+    st = [1]
+    if I > 1 or J > 1:
+        st.append(2)
+    if I > 1 and J > 1:
+        st.append(3)
+    return st
+
+
 def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
-    """Time `steps` sweeps after `warmup` (every timed sweep stores a sample),
-    then, in a second context, run the configuration's chain (sweeps, burn-in)
-    and compute the test RMSE of the posterior-mean prediction."""
+    """For every PP stage of the configuration: `warmup` sweeps, then `steps`
+    timed sweeps as launched in production (graph replays when batched), then
+    as many sweeps launched eagerly with HIP events around every kernel.  Every
+    sweep stores a sample (so the next stage has its moment-matched priors).
+    Then, in a second context, the configuration's own chain (sweeps per stage,
+    burn-in) and the test RMSE of its posterior-mean prediction."""
     import torch
     from paper_1703_00734_amd import BMF
 
@@ -61,37 +74,63 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
                    order=cfg["order"], seed=seed, burnin=burnin, thin=1, max_kept=kept,
                    precision=precision, batched=batched)
 
-    g = ctx(warmup, steps)
     stream = torch.cuda.current_stream()
-    g.gibbs_sweep(warmup)
-    torch.cuda.synchronize()
-    g.enable_timing(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    g.gibbs_sweep(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / steps
-    g.enable_timing(False)
-    ktimes = g.kernel_times()
-    row_updates, ratings = g.stage_work()
-    out = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps, ktimes=ktimes,
-               row_updates=row_updates, ratings=ratings, stats=g.stats())
+    g = ctx(0, warmup + 2 * steps)
+    per_stage = {}
+    for s in stages_of(cfg):
+        g.pp_stage(s, 0)
+        g.gibbs_sweep(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        g.gibbs_sweep(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        g.kernel_times()                     # drop what earlier stages recorded
+        g.enable_timing(True)
+        g.gibbs_sweep(steps)
+        torch.cuda.synchronize()
+        g.enable_timing(False)
+        row_updates, ratings = g.stage_work()
+        per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
+                            ktimes=g.kernel_times(), row_updates=row_updates, ratings=ratings,
+                            schedule=g.schedule())
+    out = dict(per_stage=per_stage, stats=g.stats())
     g.close()
     if rmse:
         sweeps, burnin = cfg["sweeps"], cfg["burnin"]
         h = ctx(burnin, sweeps - burnin)
-        h.gibbs_sweep(sweeps)
+        t0 = time.perf_counter()
+        for s in stages_of(cfg):
+            h.pp_stage(s, sweeps)
         p = h.predict(d["test_row"], d["test_col"])
+        torch.cuda.synchronize()
+        out["chain_wall_s"] = time.perf_counter() - t0
         out["rmse"] = float(np.sqrt(np.mean((p - d["test_val"]) ** 2)))
         out["rmse_sweeps"] = sweeps
         out["rmse_burnin"] = burnin
         h.close()
     return out
+
+
+def rows_cols_of_stage(d, cfg, s):
+    """Rows and columns updated per sweep by the blocks of stage s."""
+    N, D, I, J = d["N"], d["D"], cfg["I"], cfg["J"]
+    bs_r, bs_c = -(-N // I), -(-D // J)
+    R = [min(bs_r, N - i * bs_r) for i in range(I)]
+    C = [min(bs_c, D - j * bs_c) for j in range(J)]
+    rows = cols = 0
+    for i in range(I):
+        for j in range(J):
+            st = 1 if (i == 0 and j == 0) else (2 if (i == 0 or j == 0) else 3)
+            if st == s:
+                rows += R[i]
+                cols += C[j]
+    return rows, cols
 
 
 def cpu_baseline(d, cfg, seconds, seed):
@@ -135,16 +174,16 @@ def main():
     arms = {}
     arms["batched_" + main_prec] = run_arm(d, cfg, main_prec, True, a.steps, a.warmup,
                                            not a.no_rmse, 101)
-    print("arm batched %s: %.4f ms/step" % (main_prec, arms["batched_" + main_prec]["ms_per_step"]),
-          file=sys.stderr, flush=True)
+    print("arm batched %s done" % main_prec, file=sys.stderr, flush=True)
     if main_prec != "fp64":
         arms["plain_fp32"] = run_arm(d, cfg, "fp32", False, a.steps, a.warmup, not a.no_rmse, 101)
-        print("arm plain fp32: %.4f ms/step" % arms["plain_fp32"]["ms_per_step"], file=sys.stderr,
-              flush=True)
-    m = arms["batched_" + main_prec]
+        print("arm plain fp32 done", file=sys.stderr, flush=True)
+    stages = stages_of(cfg)
+    head = stages[-1]                          # the largest, most parallel stage
+    m = arms["batched_" + main_prec]["per_stage"][head]
     ms = m["ms_per_step"]
     value = m["ratings"] / (ms / 1000.0)
-    # dominant kernel of the timed region
+    # dominant kernel of the per-kernel region of the headline stage
     kt = {k: v for k, v in m["ktimes"].items() if v[0] > 0}
     dom = max(kt, key=lambda k: kt[k][1])
     launches, tot_ms = kt[dom]
@@ -152,8 +191,8 @@ def main():
     roof = None
     if dom in ("update_rows", "update_cols"):
         M = m["ratings"]
-        n = d["N"] if dom == "update_rows" else d["D"]
-        # one launch per pass in batched mode; every timed sweep stores a sample
+        # entities of the pass: rows (or columns) of every block of the stage
+        n = rows_cols_of_stage(d, cfg, head)[0 if dom == "update_rows" else 1]
         per_launch = algorithmic_bytes(dom, M, n, K, state_bytes, True)
         avg_ms = tot_ms / launches
         ach = per_launch / (avg_ms / 1000.0) / 1e9
@@ -173,21 +212,31 @@ def main():
         "vs_baseline": None,
         "dtype": main_prec,
         "data": "synthetic",
-        "config": {"workload": "ratings-shaped single block N=%d D=%d K=%d, %d train entries, "
-                               "Zipf(1.2) degrees, %dx%d partition" % (d["N"], d["D"], K,
-                                                                    d["row"].size, cfg["I"],
-                                                                    cfg["J"]),
+        "config": {"workload": "%s N=%d D=%d K=%d, %d train entries, Zipf(1.2) degrees, %dx%d "
+                               "partition, %s order; step = one sweep of PP stage %d"
+                               % ("ratings-shaped" if cfg["kind"] == "ratings" else cfg["kind"],
+                                  d["N"], d["D"], K, d["row"].size, cfg["I"], cfg["J"],
+                                  cfg["order"], head),
                    "N": d["N"], "D": d["D"], "K": K, "train_nnz": int(d["row"].size),
-                   "partition": "%dx%d" % (cfg["I"], cfg["J"])},
+                   "partition": "%dx%d" % (cfg["I"], cfg["J"]), "stage": head},
         "row_updates_per_s": m["row_updates"] / (ms / 1000.0),
         "roofline": roof,
         "kernel_ms_per_step": {k: v[1] / a.steps for k, v in kt.items()},
-        "arms": {k: {"ms_per_step": v["ms_per_step"],
-                     "ratings_per_s": v["ratings"] / (v["ms_per_step"] / 1000.0),
-                     "row_updates_per_s": v["row_updates"] / (v["ms_per_step"] / 1000.0),
-                     "test_rmse": v.get("rmse"), "fallback_rows": v["stats"]["fallback_rows"]}
-                 for k, v in arms.items()},
+        "timing": "ms_per_step: HIP events around the timed sweeps (graph replays in the batched "
+                  "arm); kernel times and roofline: a second region of as many sweeps launched "
+                  "eagerly with HIP events around every kernel",
+        "arms": {},
     }
+    for k, v in arms.items():
+        arm = {"test_rmse": v.get("rmse"), "chain_wall_s": v.get("chain_wall_s"),
+               "fallback_rows": v["stats"]["fallback_rows"], "stages": {}}
+        for s_, ps in v["per_stage"].items():
+            arm["stages"][str(s_)] = {
+                "ms_per_step": ps["ms_per_step"],
+                "ratings_per_s": ps["ratings"] / (ps["ms_per_step"] / 1000.0),
+                "row_updates_per_s": ps["row_updates"] / (ps["ms_per_step"] / 1000.0),
+                "schedule": ps["schedule"]}
+        out["arms"][k] = arm
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(d, cfg, a.cpu_seconds, 101)
     print(json.dumps(out))

@@ -100,7 +100,13 @@ typedef struct {
                                     falls below pivot_theta * its diagonal entry
                                     is redone in FP64 (0 => 2^-10) */
     int32_t batched;             /* 1: all blocks of a stage in one launch per
-                                    pass; 0: one launch sequence per block */
+                                    pass, each sweep replayed from a captured
+                                    HIP graph; 0: one launch sequence per block,
+                                    launched eagerly */
+    int32_t lane_nnz;            /* K <= 16 update kernels: observed entries per
+                                    lane when sizing lane groups; 0 = chosen by
+                                    the autotuner at each stage begin (batched)
+                                    or 32 (per block) */
     void *workspace;             /* device memory owned by the caller, or NULL */
     size_t workspace_bytes;      /* its size; see bmf_workspace_size */
     void *stream;                /* hipStream_t, NULL = default stream */
@@ -108,7 +114,7 @@ typedef struct {
 
 /* Fill *cfg with defaults: K = 10, I = J = 1, beta0 = 2, nu0 = K, tau Gamma(1,1)
  * sampled, tau_fixed = 1, burnin = 0, thin = 1, max_kept = 1, FP32, batched,
- * pivot_theta = 2^-10.  Data pointers are NULL. */
+ * lane_nnz = 0 (autotuned), pivot_theta = 2^-10.  Data pointers are NULL. */
 bmf_status bmf_config_defaults(bmf_config *cfg);
 
 /* Bytes of device workspace bmf_init needs for cfg (host only, touches no
@@ -216,12 +222,16 @@ bmf_status bmf_get_stats(bmf_ctx *c, int64_t *fallback_rows, int64_t *nonpd_rows
                          int64_t *mm_ridged, int64_t *agg_corrections);
 
 /* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
- * the context's stream; bmf_kernel_times returns, for up to n kernel classes,
+ * the context's stream (sweeps are then launched eagerly, not from the graph); bmf_kernel_times returns, for up to n kernel classes,
  * their names (static strings), launch counts and total milliseconds, and the
  * number of classes in *count. */
 bmf_status bmf_enable_timing(bmf_ctx *c, int32_t on);
 bmf_status bmf_kernel_times(bmf_ctx *c, int32_t n, const char **names, int64_t *launches,
                             double *ms, int32_t *count);
+
+/* Lane-group sizing of the active stage's K <= 16 update kernels: observed
+ * entries per lane of the row pass and of the column pass (autotuned or set). */
+bmf_status bmf_get_schedule(const bmf_ctx *c, int32_t *lane_nnz_rows, int32_t *lane_nnz_cols);
 
 /* Rows + columns updated per sweep and training entries visited per sweep,
  * summed over the blocks of the active stage. */

@@ -34,6 +34,7 @@ class bmf_config(ctypes.Structure):
         ("burnin", _i32), ("thin", _i32), ("max_kept", _i32),
         ("precision", _i32), ("pivot_theta", _d),
         ("batched", _i32),
+        ("lane_nnz", _i32),
         ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
         ("stream", _vp),
     ]
@@ -84,6 +85,7 @@ def load():
         "bmf_enable_timing": [_vp, _i32],
         "bmf_kernel_times": [_vp, _i32, _vp, _vp, _vp, _P(_i32)],
         "bmf_stage_work": [_vp, _P(_i64), _P(_i64)],
+        "bmf_get_schedule": [_vp, _P(_i32), _P(_i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -108,7 +110,7 @@ def exported_symbols():
             "bmf_status_string", "bmf_block_info", "bmf_global_mean", "bmf_get_positions",
             "bmf_get_block_csr", "bmf_get_state", "bmf_set_state", "bmf_step", "bmf_get_draw", "bmf_get_mm",
             "bmf_aggregate", "bmf_get_aggregate", "bmf_get_stats", "bmf_enable_timing",
-            "bmf_kernel_times", "bmf_stage_work"]
+            "bmf_kernel_times", "bmf_get_schedule", "bmf_stage_work"]
 
 
 class BMF:
@@ -122,7 +124,7 @@ class BMF:
     def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
                  seed=0, burnin=0, thin=1, max_kept=1, precision="fp32", pivot_theta=0.0,
-                 batched=True, device=True, stream=None):
+                 batched=True, lane_nnz=0, device=True, stream=None):
         self.L = load()
         self.K = int(K)
         self.N, self.D = int(N), int(D)
@@ -149,6 +151,7 @@ class BMF:
         c.precision = PREC[precision] if isinstance(precision, str) else int(precision)
         c.pivot_theta = float(pivot_theta)
         c.batched = 1 if batched else 0
+        c.lane_nnz = int(lane_nnz)
         self.cfg = c
         self.ctx = _vp()
         self.workspace = None
@@ -304,6 +307,11 @@ class BMF:
         self._check(self.L.bmf_kernel_times(self.ctx, n, ctypes.cast(names, _vp), _ptr(launches),
                                             _ptr(ms), ctypes.byref(cnt)))
         return {names[k].decode(): (int(launches[k]), float(ms[k])) for k in range(cnt.value)}
+
+    def schedule(self):
+        r, c = _i32(), _i32()
+        self._check(self.L.bmf_get_schedule(self.ctx, ctypes.byref(r), ctypes.byref(c)))
+        return dict(lane_nnz_rows=r.value, lane_nnz_cols=c.value)
 
     def stage_work(self):
         r, m = _i64(), _i64()

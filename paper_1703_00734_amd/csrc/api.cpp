@@ -26,15 +26,16 @@ namespace {
 constexpr int32_t kStatsRowsPerJob = 512;   // entities per NW statistics job (about)
 constexpr int32_t kStatsJobsMax = 256;      // jobs per side at most
 constexpr int64_t kPredictChunk = 1 << 20;  // prediction pairs per launch
-constexpr int32_t kFallbackGrid = 512;      // workgroups of the FP64 redo pass
+constexpr int32_t kFallbackGrid = 128;      // workgroups of the FP64 redo pass
+constexpr int64_t kSegNnz = 2048;           // MFMA path: entities with more entries are split
 constexpr int32_t kWaveGridCap = 1 << 20;
 
 enum Counter { kFbRow = 0, kFbCol = 1, kFbTotal = 2, kNonPD = 3, kRidged = 4, kCorr = 5, kNumCounters = 16 };
 
 // Kernel classes for the optional per-launch timing.
-enum KClass { kKRows = 0, kKCols, kKFallback, kKSse, kKStats, kKReduce, kKHyper, kKInit, kKMM, kKAgg, kKPredict, kKFill, kNumK };
-const char *kKNames[kNumK] = {"update_rows", "update_cols", "update_fallback_fp64", "sse", "nw_stats", "reduce",
-                              "hyper_draws", "init", "moment_match", "aggregate", "predict", "fill"};
+enum KClass { kKRows = 0, kKCols, kKGram, kKFallback, kKSse, kKStats, kKReduce, kKHyper, kKInit, kKMM, kKAgg, kKPredict, kKFill, kNumK };
+const char *kKNames[kNumK] = {"update_rows", "update_cols", "gram_segments", "update_fallback_fp64", "sse", "nw_stats", "reduce",
+                              "hyper_draws", "init", "moment_match", "aggregate", "predict", "bookkeeping"};
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -45,11 +46,12 @@ struct Layout {
     int64_t vs = 0, ss = 0, sp = 0;  // value / state / sample element bytes
     // byte offsets
     int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, ord, X, W, hyper, tau, mu0,
-        W0inv, mm, agg_x, agg_w, sample, probe, sse_part, sse_final, stats_part, stats_final,
-        counters, fb_list, m_sides, m_tiles, m_reduce,
+        W0inv, mm, agg_x, agg_w, sample, probe, sse_col, sse_final, stats_part, stats_final,
+        counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits,
         m_items, m_items2, m_stats, m_hyper, m_mmout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
         p_out, total;
-    int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap;
+    int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
+    bool mfma = false;
 };
 
 bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
@@ -117,15 +119,22 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.agg_w = take(8 * c.D * c.K);
     L.sample = take(L.sp * (int64_t)c.max_kept * L.Emax * L.ks_p);
     L.probe = take(L.sp * L.Emax * L.ks_p);
-    L.sse_part = take(8 * L.n_sse_cap);
+    L.sse_col = take(8 * 4 * L.E_c);
     L.sse_final = take(8 * L.nb);
     L.stats_part = take(8 * L.n_stats_cap * L.npair);
     L.stats_final = take(8 * 2 * L.nb * L.npair);
     L.counters = take(4 * kNumCounters);
+    L.sweep = take(sizeof(SweepState));
     L.fb_list = take(8 * (L.Pmax + 8));
     L.m_sides = take(sizeof(SideDesc) * 2 * L.nb);
     L.m_tiles = take(sizeof(Tile) * L.n_tiles_cap);
     L.m_reduce = take(sizeof(ReduceJob) * (3 * L.nb + 8));
+    // heavy-entity segments of the MFMA path: at most 2 nnz / kSegNnz per pass
+    L.mfma = c.precision == BMF_PREC_BF16 && L.kc >= 32;
+    L.n_seg_cap = L.mfma ? 2 * (c.nnz / kSegNnz) + 8 : 0;
+    L.gpart = take(4 * L.n_seg_cap * (L.kc * L.kc + L.kc));
+    L.m_segs = take(sizeof(SegItem) * 2 * L.n_seg_cap);
+    L.m_splits = take(sizeof(int2) * L.n_items_cap);
     L.m_items = take(sizeof(int2) * L.n_items_cap);
     L.m_items2 = take(sizeof(int2) * (L.Emax + 8));
     L.m_stats = take(sizeof(StatsJob) * L.n_stats_cap);
@@ -153,6 +162,14 @@ struct StageLists {
     int64_t i_row_blk = 0, i_row_heavy = 0, i_col_blk = 0, i_col_heavy = 0, i_end = 0;
     std::vector<int64_t> row_item_begin, col_item_begin;
     std::vector<int2> ents;                         // every (side, entity) of the stage
+    // MFMA path: segments of heavy entities ([rows grouped | cols grouped]) and,
+    // parallel to `items`, each item's (first partial slot, segment count)
+    std::vector<SegItem> segs;
+    std::vector<int2> splits;
+    int64_t s_row = 0, s_col = 0, s_end = 0;
+    std::vector<int64_t> row_seg_begin, col_seg_begin;   // per stage block, within the pass
+    std::vector<std::vector<int32_t>> ord_row, ord_col;   // degree orders per stage block
+    int32_t lane_row = 32, lane_col = 32;          // entries per lane of the register kernel
     std::vector<StatsJob> stats;
     std::vector<int64_t> side_stats_begin;          // per side, into stats (size 2*nbs + 1)
     std::vector<HyperJob> hyper;
@@ -169,13 +186,17 @@ struct bmf_ctx {
     bmf_config cfg{};
     std::string err;
     bool device = false;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // the caller's stream: all work is ordered on it
+    hipStream_t ls = nullptr;          // where launches go (the capture stream while capturing)
+    hipStream_t cap_stream = nullptr;  // internal stream used only to capture the sweep graph
+    hipGraphExec_t gexec = nullptr;    // one captured sweep of the active stage
     Layout L;
     Plan plan;
     double ybar = 0.0;
     std::vector<double> mu0, W0inv;
     // host offsets per block
     std::vector<int64_t> csr_ptr_off, csc_ptr_off, x_off, w_off, ord_row_off, ord_col_off;
+    std::vector<int64_t> nz_off[2];       // first CSR (0) / CSC (1) entry of each block
     // device memory
     char *base = nullptr;
     bool own = false;
@@ -272,6 +293,7 @@ bmf_status validate(const bmf_config *cfg, std::string &err) {
     if (c.burnin < 0 || c.thin < 1 || c.max_kept < 1) { err = "bad burnin/thin/max_kept"; return BMF_EINVAL; }
     if (c.precision < BMF_PREC_FP64 || c.precision > BMF_PREC_BF16) { err = "bad precision"; return BMF_EINVAL; }
     if (c.pivot_theta < 0.0 || c.pivot_theta >= 1.0) { err = "pivot_theta must be in [0, 1)"; return BMF_EINVAL; }
+    if (c.lane_nnz < 0) { err = "lane_nnz must be >= 0"; return BMF_EINVAL; }
     for (int64_t e = 0; e < c.nnz; ++e)
         if (!std::isfinite(c.val[e])) { err = "non-finite value at entry " + std::to_string(e); return BMF_EINVAL; }
     if (c.W0) {
@@ -288,28 +310,27 @@ bmf_status validate(const bmf_config *cfg, std::string &err) {
 // schedules
 // ---------------------------------------------------------------------------
 // Lanes per entity for the register kernel: about `per` entries per lane, a
-// power of two in [1, 256] (groups above 64 lanes span several waves).
-int32_t g_lane_nnz = 12;
-int32_t lanes_for(int64_t deg) {
-    const int64_t per = g_lane_nnz;
+// power of two in [1, 256] (groups above 64 lanes span several waves).  `per`
+// is chosen per pass by the autotuner.
+int32_t lanes_for(int64_t deg, int32_t per) {
     int32_t G = 1;
     while (G < 256 && (int64_t)G * per < deg) G <<= 1;
     return G;
 }
 
 void side_tiles(int32_t side, int64_t ord_off, const std::vector<int64_t> &ptr, const std::vector<int32_t> &ord,
-                std::vector<Tile> &out, std::vector<int64_t> &cost) {
+                int32_t per, std::vector<Tile> &out, std::vector<int64_t> &cost) {
     const int64_t n = (int64_t)ord.size();
     int64_t k = 0;
     while (k < n) {
         const int64_t deg = ptr[ord[k] + 1] - ptr[ord[k]];
-        const int32_t G = lanes_for(deg);
+        const int32_t G = lanes_for(deg, per);
         const int32_t cap = 256 / G;
         int32_t cnt = 0;
         int64_t cst = 0;
         while (k + cnt < n && cnt < cap) {
             const int64_t d = ptr[ord[k + cnt] + 1] - ptr[ord[k + cnt]];
-            if (lanes_for(d) != G) break;
+            if (lanes_for(d, per) != G) break;
             cst += d + 16;
             ++cnt;
         }
@@ -375,66 +396,69 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         S.col_ents += B.C;
     }
     // degree orders of each side (host copies, same as uploaded at init)
-    auto orders = [&](int32_t k, bool rows, std::vector<int32_t> &ord, const std::vector<int64_t> *&ptr) {
+    for (int32_t k = 0; k < nbs; ++k) {
         const PlanBlock &B = P.blocks[S.blocks[k]];
-        ptr = rows ? &B.csr_ptr : &B.csc_ptr;
-        ord = degree_order(*ptr);
-    };
-    // register tiles and wave items
+        S.ord_row.push_back(degree_order(B.csr_ptr));
+        S.ord_col.push_back(degree_order(B.csc_ptr));
+    }
+    // wave kernel items: grouped by block, then heavy-first across blocks; on
+    // the MFMA path entities above kSegNnz entries are split into segments
+    const bool mf = c->L.mfma;
     for (int pass = 0; pass < 2; ++pass) {
         const bool rows = pass == 0;
-        std::vector<Tile> grouped;
-        std::vector<int64_t> gcost;
-        std::vector<int64_t> &tbeg = rows ? S.row_tile_begin : S.col_tile_begin;
-        std::vector<int2> igrp;
+        std::vector<int2> igrp, sgrp;
         std::vector<int64_t> ideg;
         std::vector<int64_t> &ibeg = rows ? S.row_item_begin : S.col_item_begin;
+        std::vector<int64_t> &sbeg = rows ? S.row_seg_begin : S.col_seg_begin;
+        (rows ? S.s_row : S.s_col) = (int64_t)S.segs.size();
+        int32_t slot = 0;
         for (int32_t k = 0; k < nbs; ++k) {
-            std::vector<int32_t> ord;
-            const std::vector<int64_t> *ptr;
-            orders(k, rows, ord, ptr);
             const int32_t b = S.blocks[k];
-            const int64_t ooff = rows ? c->ord_row_off[b] : c->ord_col_off[b];
+            const PlanBlock &B = P.blocks[b];
+            const std::vector<int64_t> &ptr = rows ? B.csr_ptr : B.csc_ptr;
             const int32_t side = rows ? k : nbs + k;
-            tbeg.push_back((int64_t)grouped.size());
-            side_tiles(side, ooff, *ptr, ord, grouped, gcost);
             ibeg.push_back((int64_t)igrp.size());
-            for (int32_t e : ord) {
+            sbeg.push_back((int64_t)slot);
+            for (int32_t e : (rows ? S.ord_row[k] : S.ord_col[k])) {
+                const int64_t deg = ptr[e + 1] - ptr[e];
                 igrp.push_back(make_int2(side, e));
-                ideg.push_back((*ptr)[e + 1] - (*ptr)[e]);
+                ideg.push_back(deg);
+                if (mf && deg > kSegNnz) {
+                    const int32_t nseg = (int32_t)((deg + kSegNnz - 1) / kSegNnz);
+                    sgrp.push_back(make_int2(slot, nseg));
+                    // global entry offsets of this entity: the uploaded pointer array
+                    // holds block-local offsets shifted by the block's first entry
+                    const int64_t g0 = c->nz_off[pass][b] + ptr[e];
+                    for (int32_t q = 0; q < nseg; ++q) {
+                        SegItem si{};
+                        si.side = side;
+                        si.ent = e;
+                        si.begin = g0 + (int64_t)q * kSegNnz;
+                        si.end = std::min(g0 + deg, si.begin + kSegNnz);
+                        si.slot = slot++;
+                        S.segs.push_back(si);
+                    }
+                } else {
+                    sgrp.push_back(make_int2(0, 0));
+                }
             }
         }
-        tbeg.push_back((int64_t)grouped.size());
         ibeg.push_back((int64_t)igrp.size());
-        std::vector<int64_t> perm(grouped.size());
-        for (size_t q = 0; q < perm.size(); ++q) perm[q] = (int64_t)q;
-        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b2) { return gcost[a] > gcost[b2]; });
+        sbeg.push_back((int64_t)slot);
         std::vector<int64_t> iperm(igrp.size());
         for (size_t q = 0; q < iperm.size(); ++q) iperm[q] = (int64_t)q;
-        std::stable_sort(iperm.begin(), iperm.end(), [&](int64_t a, int64_t b2) { return ideg[a] > ideg[b2]; });
-        if (rows) {
-            S.t_row_blk = (int64_t)S.tiles.size();
-            S.tiles.insert(S.tiles.end(), grouped.begin(), grouped.end());
-            S.t_row_heavy = (int64_t)S.tiles.size();
-            for (int64_t q : perm) S.tiles.push_back(grouped[q]);
-            S.i_row_blk = (int64_t)S.items.size();
-            S.items.insert(S.items.end(), igrp.begin(), igrp.end());
-            S.i_row_heavy = (int64_t)S.items.size();
-            for (int64_t q : iperm) S.items.push_back(igrp[q]);
-        } else {
-            S.t_col_blk = (int64_t)S.tiles.size();
-            S.tiles.insert(S.tiles.end(), grouped.begin(), grouped.end());
-            S.t_col_heavy = (int64_t)S.tiles.size();
-            for (int64_t q : perm) S.tiles.push_back(grouped[q]);
-            S.i_col_blk = (int64_t)S.items.size();
-            S.items.insert(S.items.end(), igrp.begin(), igrp.end());
-            S.i_col_heavy = (int64_t)S.items.size();
-            for (int64_t q : iperm) S.items.push_back(igrp[q]);
+        std::stable_sort(iperm.begin(), iperm.end(), [&](int64_t a2, int64_t b2) { return ideg[a2] > ideg[b2]; });
+        (rows ? S.i_row_blk : S.i_col_blk) = (int64_t)S.items.size();
+        S.items.insert(S.items.end(), igrp.begin(), igrp.end());
+        S.splits.insert(S.splits.end(), sgrp.begin(), sgrp.end());
+        (rows ? S.i_row_heavy : S.i_col_heavy) = (int64_t)S.items.size();
+        for (int64_t q : iperm) {
+            S.items.push_back(igrp[q]);
+            S.splits.push_back(sgrp[q]);
         }
     }
-    S.t_end = (int64_t)S.tiles.size();
+    S.s_end = (int64_t)S.segs.size();
     S.i_end = (int64_t)S.items.size();
-    S.sse_tile_begin = S.row_tile_begin;
     // every entity, for init and moment matching
     for (int32_t side = 0; side < 2 * nbs; ++side)
         for (int32_t e = 0; e < S.sides[side].n; ++e) S.ents.push_back(make_int2(side, e));
@@ -476,9 +500,70 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
     S.hyper_begin.push_back((int32_t)S.hyper.size());
 }
 
+// Register-kernel tiles of the active stage for `per_row`/`per_col` entries
+// per lane: grouped by block (per-block launches, SSE) and heavy-first
+// (batched launches).
+static void build_tiles(bmf_ctx *c, int32_t per_row, int32_t per_col) {
+    StageLists &S = c->S;
+    const Plan &P = c->plan;
+    const int32_t nbs = (int32_t)S.blocks.size();
+    S.tiles.clear();
+    S.row_tile_begin.clear();
+    S.col_tile_begin.clear();
+    S.lane_row = per_row;
+    S.lane_col = per_col;
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool rows = pass == 0;
+        std::vector<Tile> grouped;
+        std::vector<int64_t> gcost;
+        std::vector<int64_t> &tbeg = rows ? S.row_tile_begin : S.col_tile_begin;
+        for (int32_t k = 0; k < nbs; ++k) {
+            const int32_t b = S.blocks[k];
+            const PlanBlock &B = P.blocks[b];
+            const int64_t ooff = rows ? c->ord_row_off[b] : c->ord_col_off[b];
+            tbeg.push_back((int64_t)grouped.size());
+            side_tiles(rows ? k : nbs + k, ooff, rows ? B.csr_ptr : B.csc_ptr, rows ? S.ord_row[k] : S.ord_col[k],
+                       rows ? per_row : per_col, grouped, gcost);
+        }
+        tbeg.push_back((int64_t)grouped.size());
+        std::vector<int64_t> perm(grouped.size());
+        for (size_t q = 0; q < perm.size(); ++q) perm[q] = (int64_t)q;
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a2, int64_t b2) { return gcost[a2] > gcost[b2]; });
+        (rows ? S.t_row_blk : S.t_col_blk) = (int64_t)S.tiles.size();
+        S.tiles.insert(S.tiles.end(), grouped.begin(), grouped.end());
+        (rows ? S.t_row_heavy : S.t_col_heavy) = (int64_t)S.tiles.size();
+        for (int64_t q : perm) S.tiles.push_back(grouped[q]);
+    }
+    S.t_end = (int64_t)S.tiles.size();
+    S.sse_tile_begin = S.row_tile_begin;
+}
+
 static bmf_status upload(bmf_ctx *c, int64_t off, const void *src, size_t bytes) {
     if (bytes == 0) return BMF_OK;
     HIPCHK(c, hipMemcpyAsync(c->base + off, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return BMF_OK;
+}
+
+static bmf_status upload_tiles(bmf_ctx *c) {
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    bmf_status st;
+    if ((int64_t)S.tiles.size() > L.n_tiles_cap) return fail(c, BMF_ENOMEM, "tile list exceeds its reserved space");
+    if ((st = upload(c, L.m_tiles, S.tiles.data(), S.tiles.size() * sizeof(Tile)))) return st;
+    // fixed-order reductions: SSE of stage block k at k, NW sums of side q at nbs + q
+    const int32_t nbs = (int32_t)S.blocks.size();
+    std::vector<ReduceJob> rj;
+    for (int32_t k = 0; k < nbs; ++k) {
+        const int32_t b = S.blocks[k];
+        rj.push_back(ReduceJob{c->dev<double>(L.sse_col) + 4 * c->w_off[b], c->dev<double>(L.sse_final) + k,
+                               (int32_t)(4 * c->plan.blocks[b].C), 1});
+    }
+    for (int32_t q = 0; q < 2 * nbs; ++q)
+        rj.push_back(ReduceJob{c->dev<double>(L.stats_part) + S.side_stats_begin[q] * L.npair,
+                               c->dev<double>(L.stats_final) + (int64_t)q * L.npair,
+                               (int32_t)(S.side_stats_begin[q + 1] - S.side_stats_begin[q]), L.npair});
+    if ((st = upload(c, L.m_reduce, rj.data(), rj.size() * sizeof(ReduceJob)))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return BMF_OK;
 }
 
@@ -486,28 +571,17 @@ static bmf_status upload_stage(bmf_ctx *c) {
     const Layout &L = c->L;
     StageLists &S = c->S;
     bmf_status st;
-    if ((int64_t)S.tiles.size() > L.n_tiles_cap || (int64_t)S.items.size() > L.n_items_cap ||
+    if ((int64_t)S.items.size() > L.n_items_cap ||
         (int64_t)S.ents.size() > L.Emax + 8 || (int64_t)S.stats.size() > L.n_stats_cap)
         return fail(c, BMF_ENOMEM, "stage work lists exceed their reserved space");
     if ((st = upload(c, L.m_sides, S.sides.data(), S.sides.size() * sizeof(SideDesc)))) return st;
-    if ((st = upload(c, L.m_tiles, S.tiles.data(), S.tiles.size() * sizeof(Tile)))) return st;
     if ((st = upload(c, L.m_items, S.items.data(), S.items.size() * sizeof(int2)))) return st;
+    if ((int64_t)S.segs.size() > 2 * L.n_seg_cap) return fail(c, BMF_ENOMEM, "segment list exceeds its reserved space");
+    if ((st = upload(c, L.m_splits, S.splits.data(), S.splits.size() * sizeof(int2)))) return st;
+    if ((st = upload(c, L.m_segs, S.segs.data(), S.segs.size() * sizeof(SegItem)))) return st;
     if ((st = upload(c, L.m_items2, S.ents.data(), S.ents.size() * sizeof(int2)))) return st;
     if ((st = upload(c, L.m_stats, S.stats.data(), S.stats.size() * sizeof(StatsJob)))) return st;
     if ((st = upload(c, L.m_hyper, S.hyper.data(), S.hyper.size() * sizeof(HyperJob)))) return st;
-    {
-        // fixed-order reductions: SSE of stage block k at k, NW sums of side q at nbs + q
-        const int32_t nbs2 = (int32_t)S.blocks.size();
-        std::vector<ReduceJob> rj;
-        for (int32_t k = 0; k < nbs2; ++k)
-            rj.push_back(ReduceJob{c->dev<double>(L.sse_part) + S.sse_tile_begin[k], c->dev<double>(L.sse_final) + k,
-                                   (int32_t)(S.sse_tile_begin[k + 1] - S.sse_tile_begin[k]), 1});
-        for (int32_t q = 0; q < 2 * nbs2; ++q)
-            rj.push_back(ReduceJob{c->dev<double>(L.stats_part) + S.side_stats_begin[q] * L.npair,
-                                   c->dev<double>(L.stats_final) + (int64_t)q * L.npair,
-                                   (int32_t)(S.side_stats_begin[q + 1] - S.side_stats_begin[q]), L.npair});
-        if ((st = upload(c, L.m_reduce, rj.data(), rj.size() * sizeof(ReduceJob)))) return st;
-    }
     std::vector<double *> outs(S.sides.size());
     const int32_t nbs = (int32_t)S.blocks.size();
     for (int32_t k = 0; k < nbs; ++k) {
@@ -523,7 +597,10 @@ static bmf_status upload_stage(bmf_ctx *c) {
 // ---------------------------------------------------------------------------
 // kernel drivers
 // ---------------------------------------------------------------------------
-static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample) {
+// Update-pass arguments.  With use_ss the sweep index and the sample slot
+// are read on the device from the sweep state (sweeps, graph-capturable);
+// otherwise t and sample are taken as given (single steps).
+static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample, bool use_ss) {
     const Layout &L = c->L;
     UpdArgs a{};
     a.sides = c->dev<SideDesc>(L.m_sides);
@@ -535,7 +612,8 @@ static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample) {
     a.ks_other = L.ks_m;
     a.self = c->dev<void>(rows ? L.X : L.W);
     a.ks_self = L.ks_m;
-    a.sample = sample;
+    a.sample = use_ss ? (void *)(c->base + L.sample) : sample;
+    a.ss = use_ss ? c->dev<SweepState>(L.sweep) : nullptr;
     a.ks_sample = L.ks_p;
     a.K = c->cfg.K;
     a.prow = L.prow;
@@ -555,16 +633,20 @@ static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample) {
 
 // One conditional-update pass over the rows (or columns) of the active stage;
 // block k = -1 means every block, else only stage block k.
-static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int32_t k) {
+static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int32_t k, bool use_ss,
+                           bool sse = false) {
     const Layout &L = c->L;
     StageLists &S = c->S;
     const int32_t nbs = (int32_t)S.blocks.size();
-    UpdArgs a = upd_args(c, rows, t, sample);
+    UpdArgs a = upd_args(c, rows, t, sample, use_ss);
+    if (sse && !rows) a.sse_col = c->dev<double>(L.sse_col);
     bmf_status st;
     const int32_t kcls = rows ? kKRows : kKCols;
-    if (!c->fp64()) {
+    // the fallback queue counters start every pass at zero: sweeps reset them in
+    // the sweep-state advance, single steps around their pass
+    if (!c->fp64() && !use_ss) {
         int32_t *fb = a.fb_count;
-        if ((st = timed(c, kKFill, [&] { return launch_fill_i32(fb, 0, 1, c->stream); }))) return st;
+        if ((st = timed(c, kKFill, [&] { return launch_fill_i32(fb, 0, 1, c->ls); }))) return st;
     }
     // which blocks: one launch for all (batched, heavy-first) or one per block
     std::vector<std::pair<int64_t, int64_t>> ranges;   // tile or item ranges
@@ -582,7 +664,7 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
             UpdArgs b = a;
             b.tiles = c->dev<Tile>(L.m_tiles) + r.first;
             const int32_t n = (int32_t)(r.second - r.first);
-            if ((st = timed(c, kcls, [&] { return launch_update_reg(L.kc, c->prec(), b, n, c->stream); }))) return st;
+            if ((st = timed(c, kcls, [&] { return launch_update_reg(L.kc, c->prec(), b, n, c->ls); }))) return st;
         }
     } else {
         if (batched) {
@@ -593,12 +675,35 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
             for (int32_t q = 0; q < nbs; ++q)
                 if (k < 0 || q == k) ranges.push_back({base + ib[q], base + ib[q + 1]});
         }
+        // segments of heavy entities (MFMA path): partial Grams first
+        if (L.mfma) {
+            const int64_t sbase = rows ? S.s_row : S.s_col;
+            const std::vector<int64_t> &sb = rows ? S.row_seg_begin : S.col_seg_begin;
+            const int64_t lo = batched || k < 0 ? sb.front() : sb[k];
+            const int64_t hi = batched || k < 0 ? sb.back() : sb[k + 1];
+            if (hi > lo) {
+                GramPartArgs ga{};
+                ga.segs = c->dev<SegItem>(L.m_segs) + sbase + lo;
+                ga.nseg = (int32_t)(hi - lo);
+                ga.sides = a.sides;
+                ga.idx = a.idx;
+                ga.val = a.val;
+                ga.other = a.other;
+                ga.ks_other = a.ks_other;
+                ga.gpart = c->dev<float>(L.gpart);
+                if ((st = timed(c, kKGram, [&] { return launch_gram_part(L.kc, ga, c->ls); }))) return st;
+            }
+        }
         for (auto &r : ranges) {
             UpdArgs b = a;
             b.items = c->dev<int2>(L.m_items) + r.first;
             b.nitems = (int32_t)(r.second - r.first);
+            if (L.mfma) {
+                b.splits = c->dev<int2>(L.m_splits) + r.first;
+                b.gpart = c->dev<float>(L.gpart);
+            }
             const int32_t g = (int32_t)std::min<int64_t>(b.nitems, kWaveGridCap);
-            if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->stream); }))) return st;
+            if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->ls); }))) return st;
         }
     }
     if (!c->fp64()) {
@@ -609,67 +714,72 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         f.fb_count = nullptr;
         f.theta = 0.0f;
         const int32_t fp = c->bf() ? kPFB16 : kPFB32;
-        if ((st = timed(c, kKFallback, [&] { return launch_update_wave(L.kc, fp, f, kFallbackGrid, c->stream); })))
+        if ((st = timed(c, kKFallback, [&] { return launch_update_wave(L.kc, fp, f, kFallbackGrid, c->ls); })))
             return st;
+        if (!use_ss) {
+            int32_t *fb = a.fb_count;
+            if ((st = timed(c, kKFill, [&] { return launch_fill_i32(fb, 0, 1, c->ls); }))) return st;
+        }
     }
     return BMF_OK;
 }
 
+// Fixed-order SSE of every stage block (k = -1) or of stage block k from the
+// per-column slots.
+static bmf_status reduce_sse(bmf_ctx *c, int32_t k) {
+    const int32_t nbs = (int32_t)c->S.blocks.size();
+    const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce) + (k < 0 ? 0 : k);
+    const int32_t nr = k < 0 ? nbs : 1;
+    return timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->ls); });
+}
+
+// Residual SSE of stage block k's columns on their own (a tau step).
 static bmf_status run_sse(bmf_ctx *c, int32_t k) {
     const Layout &L = c->L;
     StageLists &S = c->S;
     SseArgs a{};
     a.sides = c->dev<SideDesc>(L.m_sides);
     a.ord = c->dev<int32_t>(L.ord);
-    a.ptr = c->dev<int64_t>(L.csr_ptr);
-    a.idx = c->dev<int32_t>(L.csr_idx);
-    a.val = c->dev<void>(L.csr_val);
+    a.ptr = c->dev<int64_t>(L.csc_ptr);
+    a.idx = c->dev<int32_t>(L.csc_idx);
+    a.val = c->dev<void>(L.csc_val);
     a.X = c->dev<void>(L.X);
     a.W = c->dev<void>(L.W);
     a.ks = L.ks_m;
-    a.part = c->dev<double>(L.sse_part);
-    const int32_t nbs = (int32_t)S.blocks.size();
-    const int64_t lo = k < 0 ? 0 : S.sse_tile_begin[k];
-    const int64_t hi = k < 0 ? S.sse_tile_begin[nbs] : S.sse_tile_begin[k + 1];
-    a.tiles = c->dev<Tile>(L.m_tiles) + S.t_row_blk + lo;
-    a.part_base = (int32_t)lo;
+    a.K = c->cfg.K;
+    a.sse_col = c->dev<double>(L.sse_col);
+    const int64_t lo = S.col_tile_begin[k], hi = S.col_tile_begin[k + 1];
+    a.tiles = c->dev<Tile>(L.m_tiles) + S.t_col_blk + lo;
     const int32_t n = (int32_t)(hi - lo);
-    bmf_status st = timed(c, kKSse, [&] { return launch_sse(L.kc, c->prec(), a, n, c->stream); });
+    bmf_status st = timed(c, kKSse, [&] { return launch_sse(L.kc, c->prec(), a, n, c->ls); });
     if (st) return st;
-    const ReduceJob *rj = c->dev<ReduceJob>(L.m_reduce) + (k < 0 ? 0 : k);
-    const int32_t nr = k < 0 ? nbs : 1;
-    return timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->stream); });
+    return reduce_sse(c, k);
 }
 
 static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi) {
     const Layout &L = c->L;
     StageLists &S = c->S;
-    const int64_t lo = S.side_stats_begin[side_lo], hi = S.side_stats_begin[side_hi];
-    if (hi <= lo) return BMF_OK;
-    // rows and columns live in different arrays: split at the row/column boundary
     const int32_t nbs = (int32_t)S.blocks.size();
-    const int64_t mid = S.side_stats_begin[nbs];
+    const int64_t lo = S.side_stats_begin[side_lo], hi = S.side_stats_begin[side_hi];
     bmf_status st;
-    for (int pass = 0; pass < 2; ++pass) {
-        const int64_t a0 = pass == 0 ? lo : std::max(lo, mid);
-        const int64_t a1 = pass == 0 ? std::min(hi, mid) : hi;
-        if (a1 <= a0) continue;
+    if (hi > lo) {
         StatsArgs a{};
-        a.jobs = c->dev<StatsJob>(L.m_stats) + a0;
+        a.jobs = c->dev<StatsJob>(L.m_stats) + lo;
         a.sides = c->dev<SideDesc>(L.m_sides);
-        a.X = c->dev<void>(pass == 0 ? L.X : L.W);
+        a.X = c->dev<void>(L.X);
+        a.W = c->dev<void>(L.W);
+        a.nrow_sides = nbs;
         a.ks = L.ks_m;
         a.K = c->cfg.K;
         a.part = c->dev<double>(L.stats_part);
-        const int32_t n = (int32_t)(a1 - a0);
-        if ((st = timed(c, kKStats, [&] { return launch_stats(c->prec(), a, n, c->stream); })))
-            return st;
+        const int32_t n = (int32_t)(hi - lo);
+        if ((st = timed(c, kKStats, [&] { return launch_stats(c->prec(), a, n, c->ls); }))) return st;
     }
     const ReduceJob *rj = c->dev<ReduceJob>(L.m_reduce) + nbs + side_lo;
-    return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->stream); });
+    return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->ls); });
 }
 
-static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t) {
+static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool use_ss) {
     if (j1 <= j0) return BMF_OK;
     const Layout &L = c->L;
     HyperArgs a{};
@@ -684,31 +794,25 @@ static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t) {
     a.b0 = c->cfg.tau_b0;
     a.K = c->cfg.K;
     a.t = t;
+    a.ss = use_ss ? c->dev<SweepState>(L.sweep) : nullptr;
     a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
     a.k1 = (uint32_t)(c->cfg.seed >> 32);
     a.nonpd = c->dev<int32_t>(L.counters) + kNonPD;
-    return timed(c, kKHyper, [&] { return launch_hyper(a, j1 - j0, c->stream); });
+    return timed(c, kKHyper, [&] { return launch_hyper(a, j1 - j0, c->ls); });
 }
 
-static void *sample_slot(bmf_ctx *c, int32_t q) {
-    const Layout &L = c->L;
-    return c->base + L.sample + (int64_t)q * L.Emax * L.ks_p * L.sp;
-}
-
-static bmf_status sweep_once(bmf_ctx *c) {
+// Enqueue one sweep of the active stage on c->ls: rows, columns, SSE, NW
+// statistics, hyperparameter and tau draws, then the sweep-state advance.
+static bmf_status enqueue_sweep(bmf_ctx *c) {
     StageLists &S = c->S;
-    const uint32_t t = (uint32_t)c->t;
-    const bmf_config &g = c->cfg;
-    const bool keep = c->t >= g.burnin && (c->t - g.burnin) % g.thin == 0 && c->kept < g.max_kept;
-    void *slot = keep ? sample_slot(c, c->kept) : nullptr;
     bmf_status st;
     const int32_t nbs = (int32_t)S.blocks.size();
-    const int32_t nblk = (c->cfg.batched) ? 1 : nbs;
+    const int32_t nblk = c->cfg.batched ? 1 : nbs;
     for (int32_t q = 0; q < nblk; ++q) {
         const int32_t k = c->cfg.batched ? -1 : q;
-        if ((st = run_pass(c, true, t, slot, k))) return st;
-        if ((st = run_pass(c, false, t, slot, k))) return st;
-        if (g.sample_tau && (st = run_sse(c, k))) return st;
+        if ((st = run_pass(c, true, 0, nullptr, k, true))) return st;
+        if ((st = run_pass(c, false, 0, nullptr, k, true, c->cfg.sample_tau != 0))) return st;
+        if (c->cfg.sample_tau && (st = reduce_sse(c, k))) return st;
         if (k < 0) {
             if ((st = run_stats(c, 0, 2 * nbs))) return st;
         } else {
@@ -717,16 +821,157 @@ static bmf_status sweep_once(bmf_ctx *c) {
         }
         const int32_t j0 = k < 0 ? 0 : S.hyper_begin[k];
         const int32_t j1 = k < 0 ? S.hyper_begin[nbs] : S.hyper_begin[k + 1];
-        if ((st = run_hyper(c, j0, j1, t))) return st;
+        if ((st = run_hyper(c, j0, j1, 0, true))) return st;
     }
+    SweepState *ss = c->dev<SweepState>(c->L.sweep);
+    int32_t *fbc = c->dev<int32_t>(c->L.counters) + kFbRow;
+    return timed(c, kKFill, [&] { return launch_advance(ss, fbc, c->ls); });
+}
+
+static void drop_graph(bmf_ctx *c) {
+    if (c->gexec) {
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+}
+
+// Capture one sweep into a graph (batched mode).  The capture runs on an
+// internal stream; the graph is launched on the caller's stream.
+static bmf_status capture_sweep(bmf_ctx *c) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    c->ls = c->cap_stream;
+    const bool timing = c->timing;
+    c->timing = false;
+    bmf_status st = enqueue_sweep(c);
+    c->timing = timing;
+    c->ls = c->stream;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (st) {
+        if (graph) hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(c, BMF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e2 != hipSuccess) {
+        c->gexec = nullptr;
+        return fail(c, BMF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e2));
+    }
+    return BMF_OK;
+}
+
+static bmf_status sweep_once(bmf_ctx *c) {
+    const bmf_config &g = c->cfg;
+    bmf_status st;
+    if (g.batched && !c->timing) {
+        if (!c->gexec && (st = capture_sweep(c))) return st;
+        HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        if ((st = enqueue_sweep(c))) return st;
+    }
+    // host mirror of the device sweep state
+    const bool keep = c->t >= g.burnin && (c->t - g.burnin) % g.thin == 0 && c->kept < g.max_kept;
     if (keep) c->kept += 1;
     c->t += 1;
     c->agg_valid = false;
     return BMF_OK;
 }
 
-// Begin stage s: work lists, priors, initial state.
+static bmf_status write_sweep_state(bmf_ctx *c, uint32_t t, int32_t kept) {
+    const bmf_config &g = c->cfg;
+    SweepState ss{};
+    ss.t = t;
+    ss.kept = kept;
+    ss.burnin = g.burnin;
+    ss.thin = g.thin;
+    ss.max_kept = g.max_kept;
+    ss.slot_bytes = c->L.Emax * c->L.ks_p * c->L.sp;
+    const bool keep = (int64_t)t >= g.burnin && ((int64_t)t - g.burnin) % g.thin == 0 && kept < g.max_kept;
+    ss.slot = keep ? kept : -1;
+    bmf_status st = upload(c, c->L.sweep, &ss, sizeof(ss));
+    if (st) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return BMF_OK;
+}
+
+// Autotuner of the register kernel's lane groups: for every candidate number
+// of entries per lane, rebuild the tiles and time the row and column passes
+// on the stage's real data; keep the fastest per pass.  Runs before the
+// initial state is written, so it leaves no trace in the chain (the FP32
+// fallback counters are restored).
+static bmf_status autotune(bmf_ctx *c) {
+    const int32_t cand[] = {8, 16, 32, 64, 128, 256};
+    const Layout &L = c->L;
+    int32_t saved[kNumCounters];
+    bmf_status st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(saved, c->base + L.counters, sizeof(saved), hipMemcpyDeviceToHost));
+    const bool timing = c->timing;
+    c->timing = false;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    double best[2] = {1e30, 1e30};
+    int32_t pick[2] = {32, 32};
+    for (int32_t v : cand) {
+        build_tiles(c, v, v);
+        if ((st = upload_tiles(c))) break;
+        for (int pass = 0; pass < 2; ++pass) {
+            if ((st = run_pass(c, pass == 0, 0, nullptr, -1, false))) break;   // warm-up
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            for (int r = 0; r < 2 && !st; ++r) st = run_pass(c, pass == 0, 0, nullptr, -1, false);
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best[pass]) {
+                best[pass] = ms;
+                pick[pass] = v;
+            }
+        }
+        if (st) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->timing = timing;
+    if (st) return st;
+    build_tiles(c, pick[0], pick[1]);
+    if ((st = upload_tiles(c))) return st;
+    HIPCHK(c, hipMemcpy(c->base + L.counters, saved, sizeof(saved), hipMemcpyHostToDevice));
+    return BMF_OK;
+}
+
+// Initial factors of every side of the active stage.
+static bmf_status init_factors(bmf_ctx *c) {
+    const Layout &L = c->L;
+    StageLists &S = c->S;
+    InitArgs a{};
+    a.items = c->dev<int2>(L.m_items2);
+    a.nitems = (int32_t)S.ents.size();
+    a.sides = c->dev<SideDesc>(L.m_sides);
+    a.K = c->cfg.K;
+    a.prow = L.prow;
+    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(c->cfg.seed >> 32);
+    // rows and columns live in different arrays: two launches over the entity list halves
+    const int64_t nrow_items = S.row_ents;
+    bmf_status st;
+    for (int pass = 0; pass < 2; ++pass) {
+        InitArgs b = a;
+        b.items = a.items + (pass == 0 ? 0 : nrow_items);
+        b.nitems = (int32_t)(pass == 0 ? nrow_items : (int64_t)S.ents.size() - nrow_items);
+        b.self = c->dev<void>(pass == 0 ? L.X : L.W);
+        b.ks_self = L.ks_m;
+        if ((st = timed(c, kKInit, [&] { return launch_init(c->prec(), b, c->ls); }))) return st;
+    }
+    return BMF_OK;
+}
+
+// Begin stage s: work lists, schedules (autotuned), priors, initial state.
 static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
+    drop_graph(c);
     build_stage_lists(c, s);
     bmf_status st;
     if ((st = upload_stage(c))) return st;
@@ -737,31 +982,22 @@ static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
     std::vector<double> hy(L.hy, 0.0);
     for (int k = 0; k < K; ++k) hy[k * K + k] = 1.0;
     const double tau0 = c->cfg.sample_tau ? c->cfg.tau_a0 / c->cfg.tau_b0 : c->cfg.tau_fixed;
-    std::vector<double> hall;
     for (int32_t b : S.blocks) {
         if ((st = upload(c, L.hyper + ((int64_t)b * 2 + 0) * L.hy * 8, hy.data(), 8 * L.hy))) return st;
         if ((st = upload(c, L.hyper + ((int64_t)b * 2 + 1) * L.hy * 8, hy.data(), 8 * L.hy))) return st;
         if ((st = upload(c, L.tau + 8 * (int64_t)b, &tau0, 8))) return st;
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    InitArgs a{};
-    a.items = c->dev<int2>(L.m_items2);
-    a.nitems = (int32_t)S.ents.size();
-    a.sides = c->dev<SideDesc>(L.m_sides);
-    a.K = K;
-    a.prow = L.prow;
-    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
-    a.k1 = (uint32_t)(c->cfg.seed >> 32);
-    // rows and columns live in different arrays: two launches over the entity list halves
-    const int64_t nrow_items = S.row_ents;
-    for (int pass = 0; pass < 2; ++pass) {
-        InitArgs b = a;
-        b.items = a.items + (pass == 0 ? 0 : nrow_items);
-        b.nitems = (int32_t)(pass == 0 ? nrow_items : (int64_t)S.ents.size() - nrow_items);
-        b.self = c->dev<void>(pass == 0 ? L.X : L.W);
-        b.ks_self = L.ks_m;
-        if ((st = timed(c, kKInit, [&] { return launch_init(c->prec(), b, c->stream); }))) return st;
+    if ((st = init_factors(c))) return st;
+    if (c->reg() && c->cfg.lane_nnz == 0 && c->cfg.batched) {
+        if ((st = autotune(c))) return st;
+        if ((st = init_factors(c))) return st;      // the tuning passes overwrote the factors
+    } else {
+        const int32_t v = c->cfg.lane_nnz > 0 ? c->cfg.lane_nnz : 32;
+        build_tiles(c, v, v);
+        if ((st = upload_tiles(c))) return st;
     }
+    if ((st = write_sweep_state(c, 0, 0))) return st;
     c->stage = s;
     c->t = 0;
     c->kept = 0;
@@ -786,7 +1022,7 @@ static bmf_status finalize_stage(bmf_ctx *c) {
     a.prow = L.prow;
     a.out = c->dev<double *>(L.m_mmout);
     a.ridged = c->dev<int32_t>(L.counters) + kRidged;
-    bmf_status st = timed(c, kKMM, [&] { return launch_mm(c->fp64() ? kP64 : kP32, a, c->stream); });
+    bmf_status st = timed(c, kKMM, [&] { return launch_mm(c->fp64() ? kP64 : kP32, a, c->ls); });
     if (st) return st;
     c->finalized = c->stage;
     c->done_stages[c->stage] = c->kept;
@@ -916,9 +1152,12 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     }
     const Plan &P = c->plan;
     const int64_t nb = (int64_t)P.blocks.size();
-    int64_t pr = 0, pc = 0, xr = 0, wc = 0;
+    int64_t pr = 0, pc = 0, xr = 0, wc = 0, nzb = 0;
     for (int64_t b = 0; b < nb; ++b) {
         const PlanBlock &B = P.blocks[b];
+        c->nz_off[0].push_back(nzb);
+        c->nz_off[1].push_back(nzb);
+        nzb += B.M;
         c->csr_ptr_off.push_back(pr);
         c->csc_ptr_off.push_back(pc);
         c->x_off.push_back(xr);
@@ -937,6 +1176,7 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(c, BMF_EDEVICE, "no HIP device");
     c->stream = (hipStream_t)cfg->stream;
+    c->ls = c->stream;
     const Layout &L = c->L;
     if (cfg->workspace) {
         if ((int64_t)cfg->workspace_bytes < L.total)
@@ -1000,10 +1240,7 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     return BMF_OK;
 }
 
-bmf_status bmf_init(const bmf_config *cfg, bmf_ctx **out) {
-    if (const char *e = std::getenv("BMF_LANE_NNZ")) g_lane_nnz = std::max(1, std::atoi(e));
-    return init_common(cfg, out, true);
-}
+bmf_status bmf_init(const bmf_config *cfg, bmf_ctx **out) { return init_common(cfg, out, true); }
 bmf_status bmf_init_host(const bmf_config *cfg, bmf_ctx **out) { return init_common(cfg, out, false); }
 
 bmf_status bmf_free(bmf_ctx *c) {
@@ -1014,6 +1251,8 @@ bmf_status bmf_free(bmf_ctx *c) {
             hipEventDestroy(p.a);
             hipEventDestroy(p.b);
         }
+        drop_graph(c);
+        if (c->cap_stream) hipStreamDestroy(c->cap_stream);
         if (c->own && c->base) hipFree(c->base);
     }
     delete c;
@@ -1102,7 +1341,7 @@ bmf_status bmf_aggregate(bmf_ctx *c) {
         a.prow = L.prow;
         a.out = c->dev<double>(side == 0 ? L.agg_x : L.agg_w);
         a.corrections = c->dev<int32_t>(L.counters) + kCorr;
-        if ((st = timed(c, kKAgg, [&] { return launch_agg(a, c->stream); }))) return st;
+        if ((st = timed(c, kKAgg, [&] { return launch_agg(a, c->ls); }))) return st;
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     c->agg_valid = true;
@@ -1132,7 +1371,7 @@ bmf_status bmf_predict(bmf_ctx *c, int64_t n, const int32_t *row, const int32_t 
         if ((st = upload(c, L.p_wslot, ws.data(), 8 * m))) return st;
         PredictArgs pa{c->dev<int64_t>(L.p_xslot), c->dev<int64_t>(L.p_wslot), m, c->dev<double>(L.agg_x),
                        c->dev<double>(L.agg_w), c->cfg.K, c->ybar, c->dev<float>(L.p_out)};
-        if ((st = timed(c, kKPredict, [&] { return launch_predict(pa, c->stream); }))) return st;
+        if ((st = timed(c, kKPredict, [&] { return launch_predict(pa, c->ls); }))) return st;
         HIPCHK(c, hipMemcpyAsync(out + a, c->base + L.p_out, 4 * m, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -1288,8 +1527,8 @@ bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
     const int32_t nbs = (int32_t)S.blocks.size();
     bmf_status st;
     switch (which) {
-    case 0: st = run_pass(c, true, tt, c->base + c->L.probe, k); break;
-    case 1: st = run_pass(c, false, tt, c->base + c->L.probe, k); break;
+    case 0: st = run_pass(c, true, tt, c->base + c->L.probe, k, false); break;
+    case 1: st = run_pass(c, false, tt, c->base + c->L.probe, k, false); break;
     case 2:
     case 3: {
         const int32_t side = which == 2 ? k : nbs + k;
@@ -1298,7 +1537,7 @@ bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
         int32_t j = -1;
         for (int32_t q = S.hyper_begin[k]; q < S.hyper_begin[k + 1]; ++q)
             if (S.hyper_kind[q] == which - 2) j = q;
-        st = run_hyper(c, j, j + 1, tt);
+        st = run_hyper(c, j, j + 1, tt, false);
         break;
     }
     case 4: {
@@ -1307,7 +1546,7 @@ bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
         int32_t j = -1;
         for (int32_t q = S.hyper_begin[k]; q < S.hyper_begin[k + 1]; ++q)
             if (S.hyper_kind[q] == 2) j = q;
-        st = run_hyper(c, j, j + 1, tt);
+        st = run_hyper(c, j, j + 1, tt, false);
         break;
     }
     default: return fail(c, BMF_EINVAL, "bad step kind");
@@ -1430,6 +1669,13 @@ bmf_status bmf_kernel_times(bmf_ctx *c, int32_t n, const char **names, int64_t *
         if (ms) ms[k] = c->tms[k];
     }
     if (count) *count = kNumK;
+    return BMF_OK;
+}
+
+bmf_status bmf_get_schedule(const bmf_ctx *c, int32_t *lane_nnz_rows, int32_t *lane_nnz_cols) {
+    if (!c) return BMF_EINVAL;
+    if (lane_nnz_rows) *lane_nnz_rows = c->S.lane_row;
+    if (lane_nnz_cols) *lane_nnz_cols = c->S.lane_col;
     return BMF_OK;
 }
 

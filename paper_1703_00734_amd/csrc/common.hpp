@@ -55,6 +55,18 @@ struct SideDesc {
     int32_t pad_;
 };
 
+// Device-side sweep bookkeeping read by every kernel of a sweep, so one
+// captured graph serves every sweep of a stage.
+struct SweepState {
+    uint32_t t;          // sweep index within the stage (Philox c1)
+    int32_t slot;        // sample slot of this sweep, -1 when it is not kept
+    int32_t kept;        // samples kept so far in the stage
+    int32_t burnin;
+    int32_t thin;
+    int32_t max_kept;
+    int64_t slot_bytes;  // bytes per sample slot
+};
+
 // A workgroup's share of one pass: `count` entities of side `side`, taken from
 // the degree-sorted order array at `start`, each handled by G lanes.
 struct Tile {
@@ -88,6 +100,17 @@ struct SideRange {
     int32_t side;
     int32_t first;
     int32_t count;
+    int32_t pad_;
+};
+
+// One segment of a heavy entity's observed entries [begin, end): its partial
+// Gram and right-hand side go to partial slot `slot`.
+struct SegItem {
+    int32_t side;
+    int32_t ent;
+    int64_t begin;
+    int64_t end;
+    int32_t slot;
     int32_t pad_;
 };
 

@@ -211,6 +211,12 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     constexpr int KSP = ks_of<Tp>(KC);
     constexpr bool kFP32 = sizeof(Tacc) == 4;
 
+    uint32_t t_sw = a.t;
+    void *sample = a.sample;
+    if (a.ss) {
+        t_sw = a.ss->t;
+        sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
+    }
     const Tile tl = a.tiles[blockIdx.x];
     const int G = tl.G;                    // lanes per entity: 1..64, or 128/256 (several waves)
     const int grp = threadIdx.x / G;
@@ -374,7 +380,7 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     for (int q = 0; q < (KC + 3) / 4; ++q) {
         if (4 * q < K) {
             Tacc z[4];
-            normals4((uint32_t)n, a.t, sd.c2, (uint32_t)q, a.k0, a.k1, z);
+            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)q, a.k0, a.k1, z);
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if (4 * q + c < KC && 4 * q + c < K) y[4 * q + c < KC ? 4 * q + c : 0] += z[c];
@@ -392,7 +398,39 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     if (gl == 0) {
         Ts *self = reinterpret_cast<Ts *>(a.self);
         store_row<KC>(self + (sd.self_off + n) * KSS, x, K);
-        if (a.sample) store_row<KC>(reinterpret_cast<Tp *>(a.sample) + (sd.sample_off + n) * KSP, x, K);
+        if (sample) store_row<KC>(reinterpret_cast<Tp *>(sample) + (sd.sample_off + n) * KSP, x, K);
+    }
+    if (a.sse_col) {
+        // residual SSE of this column with the new w as stored: residuals in the
+        // pass's arithmetic, squares summed in FP64
+        Tacc wd[KC];
+#pragma unroll
+        for (int i = 0; i < KC; ++i) wd[i] = i < K ? (Tacc)elem_to_d(elem_from<Ts>((double)x[i])) : (Tacc)0;
+        double acc = 0.0;
+        for (int64_t e2 = p0 + gl; e2 < p1; e2 += G) {
+            Tacc xr[KSW];
+            load_row<Tacc, KSW>(other + (int64_t)a.idx[e2] * KSW, xr);
+            Tacc dot = 0;
+#pragma unroll
+            for (int i = 0; i < KC; ++i) dot += wd[i] * xr[i];
+            const double res = (double)((Tacc)val[e2] - dot);
+            acc += res * res;
+        }
+        for (int m = 1; m < Gw; m <<= 1) acc += __shfl_xor(acc, m);
+        double *slot = a.sse_col + 4 * (sd.self_off + n);
+        if (!wide) {
+            if (gl == 0) {
+                slot[0] = acc;
+                slot[1] = 0.0;
+                slot[2] = 0.0;
+                slot[3] = 0.0;
+            }
+        } else if ((threadIdx.x & 63) == 0) {
+            const int wv = (threadIdx.x >> 6) - ((grp * G) >> 6);
+            slot[wv] = acc;
+            if (wv == 0)
+                for (int u = G >> 6; u < 4; ++u) slot[u] = 0.0;
+        }
     }
 }
 
@@ -451,6 +489,128 @@ __device__ void bwd_lds(const T *M, int K, int ld, T *x, int lane) {
     }
 }
 
+// Blocked variants for the update kernels: panels of PB = 8 columns.  The
+// diagonal block is factored by lane 0 in registers, the panel below it and
+// the trailing lower triangle are updated lane-parallel (one row per lane),
+// three barriers per panel.  Same pivot test as chol_lds.
+constexpr int kPB = 8;
+
+template <typename T>
+__device__ __forceinline__ void diag_block_factor(T *M, int ld, int p0, int pb, T theta, const T *diag0,
+                                                  int *flag) {
+    T a[kPB][kPB];
+#pragma unroll
+    for (int i = 0; i < kPB; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            a[i][j] = (i < pb) ? M[(p0 + i) * ld + p0 + j] : (T)(i == j);
+#pragma unroll
+    for (int i = 0; i < kPB; ++i) {
+#pragma unroll
+        for (int j = 0; j <= i; ++j) {
+            T s = a[i][j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) s -= a[i][q] * a[j][q];
+            if (i == j) {
+                const bool bad = i < pb && ((theta > (T)0) ? !(s > theta * diag0[p0 + i]) : !(s > (T)0));
+                if (bad) *flag = 1;
+                a[i][i] = sqrt(s > (T)0 ? s : (T)1);
+            } else {
+                a[i][j] = s / a[j][j];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < kPB; ++i)
+#pragma unroll
+        for (int j = 0; j <= i; ++j)
+            if (i < pb) M[(p0 + i) * ld + p0 + j] = a[i][j];
+}
+
+template <typename T>
+__device__ bool chol_blocked(T *M, int K, int ld, T theta, const T *diag0, int lane, int *flag) {
+    if (lane == 0) *flag = 0;
+    __syncthreads();
+    for (int p0 = 0; p0 < K; p0 += kPB) {
+        const int pb = K - p0 < kPB ? K - p0 : kPB;
+        if (lane == 0) diag_block_factor<T>(M, ld, p0, pb, theta, diag0, flag);
+        __syncthreads();
+        const int i = p0 + pb + lane;
+        if (i < K) {
+            // panel row i: L[i][p0 + j] = (A[i][p0 + j] - sum_{q<j} L[i][p0+q] L[p0+j][p0+q]) / L[p0+j][p0+j]
+            T r[kPB];
+#pragma unroll
+            for (int j = 0; j < kPB; ++j) {
+                if (j < pb) {
+                    T s = M[i * ld + p0 + j];
+#pragma unroll
+                    for (int q = 0; q < j; ++q) s -= r[q] * M[(p0 + j) * ld + p0 + q];
+                    r[j] = s / M[(p0 + j) * ld + p0 + j];
+                    M[i * ld + p0 + j] = r[j];
+                } else {
+                    r[j] = (T)0;
+                }
+            }
+            // trailing update of row i: A[i][j] -= sum_q L[i][p0+q] L[j][p0+q], p0+pb <= j <= i
+            for (int j = p0 + pb; j <= i; ++j) {
+                T s = M[i * ld + j];
+#pragma unroll
+                for (int q = 0; q < kPB; ++q)
+                    if (q < pb) s -= r[q] * M[j * ld + p0 + q];
+                M[i * ld + j] = s;
+            }
+        }
+        __syncthreads();
+    }
+    return *flag == 0;
+}
+
+// y <- L^-1 y, blocked: lane 0 solves each diagonal block, lanes update the rest.
+template <typename T>
+__device__ void fwd_blocked(const T *M, int K, int ld, T *y, int lane) {
+    for (int p0 = 0; p0 < K; p0 += kPB) {
+        const int pb = K - p0 < kPB ? K - p0 : kPB;
+        if (lane == 0) {
+            for (int i = 0; i < pb; ++i) {
+                T s = y[p0 + i];
+                for (int q = 0; q < i; ++q) s -= M[(p0 + i) * ld + p0 + q] * y[p0 + q];
+                y[p0 + i] = s / M[(p0 + i) * ld + p0 + i];
+            }
+        }
+        __syncthreads();
+        const int i = p0 + pb + lane;
+        if (i < K) {
+            T s = y[i];
+            for (int q = 0; q < pb; ++q) s -= M[i * ld + p0 + q] * y[p0 + q];
+            y[i] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// x <- L^-T x, blocked from the last panel backwards.
+template <typename T>
+__device__ void bwd_blocked(const T *M, int K, int ld, T *x, int lane) {
+    const int last = ((K - 1) / kPB) * kPB;
+    for (int p0 = last; p0 >= 0; p0 -= kPB) {
+        const int pb = K - p0 < kPB ? K - p0 : kPB;
+        if (lane == 0) {
+            for (int i = pb - 1; i >= 0; --i) {
+                T s = x[p0 + i];
+                for (int q = i + 1; q < pb; ++q) s -= M[(p0 + q) * ld + p0 + i] * x[p0 + q];
+                x[p0 + i] = s / M[(p0 + i) * ld + p0 + i];
+            }
+        }
+        __syncthreads();
+        if (lane < p0) {
+            T s = x[lane];
+            for (int q = 0; q < pb; ++q) s -= M[(p0 + q) * ld + lane] * x[p0 + q];
+            x[lane] = s;
+        }
+        __syncthreads();
+    }
+}
+
 __device__ __forceinline__ void unrank_tri(int q, int &r, int &c) {
     r = 0;
     while ((r + 1) * (r + 2) / 2 <= q) ++r;
@@ -464,7 +624,99 @@ template <typename T> __device__ __forceinline__ T to_acc(uint16_t v) { return (
 // --------------------------------------------------------------------------
 // k_update_wave: one wavefront per entity, any K <= KP.
 // --------------------------------------------------------------------------
-template <int KP, int P>
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+
+// MFMA Gram and right-hand side of the observed entries [b0, b1) of one
+// entity (BF16 factors of stride ks): on return, accumulator v of lane l holds
+// G[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] of the blocks G00 (c00), G10
+// (c10) and G11 (c11) (KP = 64), and hlo / hhi the lane's partial h[l % 32] /
+// h[32 + l % 32] (add lanes l and l ^ 32).
+template <int KP>
+__device__ __forceinline__ void mfma_gram(const uint16_t *other, int ks, const int32_t *idx,
+                                          const float *val, int64_t b0, int64_t b1, int lane,
+                                          f32x16_t &c00, f32x16_t &c10, f32x16_t &c11, float &hlo,
+                                          float &hhi) {
+    const int col = lane & 31;
+    const int kg = (lane >> 5) * 8;
+    for (int64_t c0 = b0; c0 < b1; c0 += 16) {
+        u16x8_t lo, hi;
+        float rr[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t e = c0 + kg + j;
+            unsigned short vlo = 0, vhi = 0;
+            float r = 0.0f;
+            if (e < b1) {
+                const uint16_t *row = other + (int64_t)idx[e] * ks;
+                vlo = row[col];
+                if constexpr (KP == 64) vhi = row[32 + col];
+                r = val[e];
+            }
+            lo[j] = vlo;
+            hi[j] = vhi;
+            rr[j] = r;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            hlo += rr[j] * bf16_to_f32(lo[j]);
+            if constexpr (KP == 64) hhi += rr[j] * bf16_to_f32(hi[j]);
+        }
+        const bf16x8_t blo = __builtin_bit_cast(bf16x8_t, lo);
+        c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(blo, blo, c00, 0, 0, 0);
+        if constexpr (KP == 64) {
+            const bf16x8_t bhi = __builtin_bit_cast(bf16x8_t, hi);
+            c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, blo, c10, 0, 0, 0);
+            c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, bhi, c11, 0, 0, 0);
+        }
+    }
+    hlo += __shfl_xor(hlo, 32);
+    hhi += __shfl_xor(hhi, 32);
+}
+
+// Store the accumulators of mfma_gram: lower blocks of G at dst[row * ld + col],
+// h at rhs[0..KP).
+template <int KP, typename T>
+__device__ __forceinline__ void store_gram(T *dst, int ld, T *rhs, int lane, const f32x16_t &c00,
+                                           const f32x16_t &c10, const f32x16_t &c11, float hlo,
+                                           float hhi) {
+    const int col = lane & 31;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int row = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        dst[row * ld + col] = (T)c00[v];
+        if constexpr (KP == 64) {
+            dst[(32 + row) * ld + col] = (T)c10[v];
+            dst[(32 + row) * ld + 32 + col] = (T)c11[v];
+        }
+    }
+    if (lane < 32) {
+        rhs[col] = (T)hlo;
+        if constexpr (KP == 64) rhs[32 + col] = (T)hhi;
+    }
+}
+
+// Partial Gram of one heavy-entity segment per wavefront.
+template <int KP>
+__global__ __launch_bounds__(64) void k_gram_part(const GramPartArgs a) {
+    const SegItem sg = a.segs[blockIdx.x];
+    const SideDesc &sd = a.sides[sg.side];
+    const uint16_t *other = reinterpret_cast<const uint16_t *>(a.other) + sd.other_off * a.ks_other;
+    f32x16_t c00 = {}, c10 = {}, c11 = {};
+    float hlo = 0.0f, hhi = 0.0f;
+    mfma_gram<KP>(other, a.ks_other, a.idx, reinterpret_cast<const float *>(a.val), sg.begin, sg.end,
+                  threadIdx.x, c00, c10, c11, hlo, hhi);
+    float *dst = a.gpart + (int64_t)sg.slot * (KP * KP + KP);
+    store_gram<KP, float>(dst, KP, dst + KP * KP, threadIdx.x, c00, c10, c11, hlo, hhi);
+}
+
+// MF: accumulate the Gram with v_mfma_f32_32x32x16_bf16 (BF16 state, KP = 32
+// or 64).  Lane l loads component l mod 32 (and 32 + l mod 32) of the factor
+// rows of 8 of every 16 observed entries: the same register is the A operand
+// (rows of W^T) and the B operand (columns of W), and the 32x32 FP32
+// accumulators hold G = W^T W (blocks G00, G10, G11 when KP = 64).
+template <int KP, int P, bool MF>
 __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     using Tacc = typename PrecT<P>::acc;
     using Tw = typename PrecT<P>::w;
@@ -486,6 +738,12 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     const int K = a.K;
     const int nitems = a.nitems_dev ? *a.nitems_dev : a.nitems;
     const int ti = lane >> 3, tj = lane & 7;
+    uint32_t t_sw = a.t;
+    void *sample = a.sample;
+    if (a.ss) {
+        t_sw = a.ss->t;
+        sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
+    }
     const Tw *otherb = reinterpret_cast<const Tw *>(a.other);
     const Tv *val = reinterpret_cast<const Tv *>(a.val);
 
@@ -497,73 +755,112 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
         const int64_t p1 = a.ptr[sd.ptr_off + n + 1];
         const Tw *other = otherb + sd.other_off * a.ks_other;
 
-        Tacc acc[TL][TL];
-        Tacc hacc[TL];
-#pragma unroll
-        for (int i = 0; i < TL; ++i) {
-            hacc[i] = 0;
-#pragma unroll
-            for (int j = 0; j < TL; ++j) acc[i][j] = 0;
-        }
-        for (int64_t c0 = p0; c0 < p1; c0 += CH) {
-            const int nc = (int)((p1 - c0) < CH ? (p1 - c0) : CH);
+        if constexpr (MF) {
+            const int2 sp = a.splits ? a.splits[it] : make_int2(0, 0);
             __syncthreads();
-            for (int q = lane; q < CH * KP; q += 64) {
-                const int nz = q / KP, k = q - nz * KP;
-                Tacc v = 0;
-                if (nz < nc && k < K) v = to_acc<Tacc>(other[(int64_t)a.idx[c0 + nz] * a.ks_other + k]);
-                sw[q] = v;
+            if (sp.y > 0) {
+                // heavy entity: sum the segments' partial Grams in segment order
+                constexpr int PS = KP * KP + KP;
+                const float *base = a.gpart + (int64_t)sp.x * PS;
+                for (int q = lane; q < KP * KP + KP; q += 64) {
+                    const int ra = q / KP, cb = q - ra * KP;
+                    if (q < KP * KP && (cb > ra || (KP == 64 && ra < 32 && cb >= 32))) continue;
+                    float v = 0.0f;
+                    for (int g2 = 0; g2 < sp.y; ++g2) v += base[(int64_t)g2 * PS + q];
+                    if (q < KP * KP) sA[ra * LD + cb] = v;
+                    else sh[q - KP * KP] = v;
+                }
+            } else {
+                f32x16_t c00 = {}, c10 = {}, c11 = {};
+                float hlo = 0.0f, hhi = 0.0f;
+                mfma_gram<KP>(reinterpret_cast<const uint16_t *>(other), a.ks_other, a.idx,
+                              reinterpret_cast<const float *>(val), p0, p1, lane, c00, c10, c11, hlo, hhi);
+                store_gram<KP, Tacc>(sA, LD, sh, lane, c00, c10, c11, hlo, hhi);
             }
-            if (lane < CH) sr[lane] = lane < nc ? (Tacc)val[c0 + lane] : (Tacc)0;
             __syncthreads();
-            for (int nz = 0; nz < nc; ++nz) {
-                Tacc wi[TL], wj[TL];
-#pragma unroll
-                for (int i = 0; i < TL; ++i) {
-                    wi[i] = sw[nz * KP + ti * TL + i];
-                    wj[i] = sw[nz * KP + tj * TL + i];
-                }
-#pragma unroll
-                for (int i = 0; i < TL; ++i)
-#pragma unroll
-                    for (int j = 0; j < TL; ++j) acc[i][j] += wi[i] * wj[j];
-                if (tj == 0) {
-                    const Tacc r = sr[nz];
-#pragma unroll
-                    for (int i = 0; i < TL; ++i) hacc[i] += r * wi[i];
-                }
-            }
-        }
-        __syncthreads();
-
-        const Tacc tau = (Tacc)(*sd.tau);
-        const double *pr = sd.per_row ? sd.prior + (int64_t)n * a.prow : sd.prior;
-        const double *pv = sd.per_row ? pr + K * (K + 1) / 2 : pr + K * K + K;
-#pragma unroll
-        for (int i = 0; i < TL; ++i) {
-#pragma unroll
-            for (int j = 0; j < TL; ++j) {
-                const int ra = ti * TL + i, cb = tj * TL + j;
-                Tacc v;
-                if (ra < K && cb < K) {
-                    const double p = sd.per_row ? pr[ra >= cb ? tri(ra, cb) : tri(cb, ra)] : pr[ra * K + cb];
-                    v = (Tacc)p + tau * acc[i][j];
+            const Tacc tau = (Tacc)(*sd.tau);
+            const double *pr = sd.per_row ? sd.prior + (int64_t)n * a.prow : sd.prior;
+            const double *pv = sd.per_row ? pr + K * (K + 1) / 2 : pr + K * K + K;
+            for (int q = lane; q < KP * KP; q += 64) {
+                const int ra = q / KP, cb = q - ra * KP;
+                if (cb > ra) continue;
+                if (ra < K) {
+                    const double p = sd.per_row ? pr[tri(ra, cb)] : pr[ra * K + cb];
+                    sA[ra * LD + cb] = (Tacc)p + tau * sA[ra * LD + cb];
                 } else {
-                    v = (Tacc)(ra == cb);
+                    sA[ra * LD + cb] = (Tacc)(ra == cb);
                 }
-                sA[ra * LD + cb] = v;
             }
-        }
-        if (tj == 0) {
-#pragma unroll
+            for (int q = lane; q < KP; q += 64) sh[q] = q < K ? (Tacc)pv[q] + tau * sh[q] : (Tacc)0;
+        } else {
+            Tacc acc[TL][TL];
+            Tacc hacc[TL];
+    #pragma unroll
             for (int i = 0; i < TL; ++i) {
-                const int ra = ti * TL + i;
-                sh[ra] = ra < K ? (Tacc)pv[ra] + tau * hacc[i] : (Tacc)0;
+                hacc[i] = 0;
+    #pragma unroll
+                for (int j = 0; j < TL; ++j) acc[i][j] = 0;
+            }
+            for (int64_t c0 = p0; c0 < p1; c0 += CH) {
+                const int nc = (int)((p1 - c0) < CH ? (p1 - c0) : CH);
+                __syncthreads();
+                for (int q = lane; q < CH * KP; q += 64) {
+                    const int nz = q / KP, k = q - nz * KP;
+                    Tacc v = 0;
+                    if (nz < nc && k < K) v = to_acc<Tacc>(other[(int64_t)a.idx[c0 + nz] * a.ks_other + k]);
+                    sw[q] = v;
+                }
+                if (lane < CH) sr[lane] = lane < nc ? (Tacc)val[c0 + lane] : (Tacc)0;
+                __syncthreads();
+                for (int nz = 0; nz < nc; ++nz) {
+                    Tacc wi[TL], wj[TL];
+    #pragma unroll
+                    for (int i = 0; i < TL; ++i) {
+                        wi[i] = sw[nz * KP + ti * TL + i];
+                        wj[i] = sw[nz * KP + tj * TL + i];
+                    }
+    #pragma unroll
+                    for (int i = 0; i < TL; ++i)
+    #pragma unroll
+                        for (int j = 0; j < TL; ++j) acc[i][j] += wi[i] * wj[j];
+                    if (tj == 0) {
+                        const Tacc r = sr[nz];
+    #pragma unroll
+                        for (int i = 0; i < TL; ++i) hacc[i] += r * wi[i];
+                    }
+                }
+            }
+            __syncthreads();
+
+            const Tacc tau = (Tacc)(*sd.tau);
+            const double *pr = sd.per_row ? sd.prior + (int64_t)n * a.prow : sd.prior;
+            const double *pv = sd.per_row ? pr + K * (K + 1) / 2 : pr + K * K + K;
+    #pragma unroll
+            for (int i = 0; i < TL; ++i) {
+    #pragma unroll
+                for (int j = 0; j < TL; ++j) {
+                    const int ra = ti * TL + i, cb = tj * TL + j;
+                    Tacc v;
+                    if (ra < K && cb < K) {
+                        const double p = sd.per_row ? pr[ra >= cb ? tri(ra, cb) : tri(cb, ra)] : pr[ra * K + cb];
+                        v = (Tacc)p + tau * acc[i][j];
+                    } else {
+                        v = (Tacc)(ra == cb);
+                    }
+                    sA[ra * LD + cb] = v;
+                }
+            }
+            if (tj == 0) {
+    #pragma unroll
+                for (int i = 0; i < TL; ++i) {
+                    const int ra = ti * TL + i;
+                    sh[ra] = ra < K ? (Tacc)pv[ra] + tau * hacc[i] : (Tacc)0;
+                }
             }
         }
         if (lane * 4 < K) {
             Tacc z[4];
-            normals4((uint32_t)n, a.t, sd.c2, (uint32_t)lane, a.k0, a.k1, z);
+            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)lane, a.k0, a.k1, z);
 #pragma unroll
             for (int c = 0; c < 4; ++c)
                 if (4 * lane + c < K) sz[4 * lane + c] = z[c];
@@ -571,7 +868,7 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
         __syncthreads();
         if (lane < KP) sd0[lane] = sA[lane * LD + lane];
         __syncthreads();
-        const bool ok = chol_lds<Tacc>(sA, K, LD, (Tacc)a.theta, sd0, lane, &sflag);
+        const bool ok = chol_blocked<Tacc>(sA, K, LD, (Tacc)a.theta, sd0, lane, &sflag);
         if (!ok) {
             if (lane == 0) {
                 if (a.fb_list) {
@@ -584,59 +881,84 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             }
             continue;
         }
-        fwd_lds<Tacc>(sA, K, LD, sh, lane);
+        fwd_blocked<Tacc>(sA, K, LD, sh, lane);
         if (lane < K) sh[lane] += sz[lane];
         __syncthreads();
-        bwd_lds<Tacc>(sA, K, LD, sh, lane);
+        bwd_blocked<Tacc>(sA, K, LD, sh, lane);
         const Tacc xv = lane < K ? sh[lane] : (Tacc)0;
         Ts *self = reinterpret_cast<Ts *>(a.self);
         if (lane < a.ks_self) self[(sd.self_off + n) * a.ks_self + lane] = elem_from<Ts>((double)xv);
-        if (a.sample && lane < a.ks_sample)
-            reinterpret_cast<Tp *>(a.sample)[(sd.sample_off + n) * a.ks_sample + lane] = (Tp)xv;
+        if (sample && lane < a.ks_sample)
+            reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + lane] = (Tp)xv;
+        if (a.sse_col) {
+            // residual SSE of this column with the new w as stored (FP64)
+            __syncthreads();
+            if (lane < KP) sz[lane] = lane < K ? (Tacc)elem_to_d(elem_from<Ts>((double)xv)) : (Tacc)0;
+            __syncthreads();
+            double acc = 0.0;
+            for (int64_t e2 = p0 + lane; e2 < p1; e2 += 64) {
+                const Tw *xr = other + (int64_t)a.idx[e2] * a.ks_other;
+                Tacc dot = 0;
+                for (int k = 0; k < K; ++k) dot += sz[k] * (Tacc)elem_to_d(xr[k]);
+                const double res = (double)((Tacc)val[e2] - dot);
+                acc += res * res;
+            }
+            for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+            if (lane < 4) a.sse_col[4 * (sd.self_off + n) + lane] = lane == 0 ? acc : 0.0;
+        }
         __syncthreads();
     }
 }
 
 // --------------------------------------------------------------------------
-// k_sse: sum of squared residuals of each row tile, fixed-order reduction.
+// k_sse: residual SSE of every column of a column tile (the same per-column
+// slots the fused column pass writes), for a tau step on its own.
 // --------------------------------------------------------------------------
 template <int KC, int P>
 __global__ __launch_bounds__(256) void k_sse(const SseArgs a) {
-    using Tacc = typename PrecT<P>::acc;
     using Ts = typename PrecT<P>::s;
     using Tv = typename PrecT<P>::v;
     constexpr int KS = ks_of<Ts>(KC);
-    __shared__ double red[256];
     const Tile tl = a.tiles[blockIdx.x];
     const int G = tl.G;
     const int grp = threadIdx.x / G;
+    const bool wide = G > 64;
+    const int Gw = G < 64 ? G : 64;
     const int gl = threadIdx.x & (G - 1);
-    double s = 0.0;
-    if (grp < tl.count) {
-        const SideDesc &sd = a.sides[tl.side];
-        const int n = a.ord[tl.start + grp];
-        const int64_t p0 = a.ptr[sd.ptr_off + n], p1 = a.ptr[sd.ptr_off + n + 1];
-        const Ts *W = reinterpret_cast<const Ts *>(a.W) + sd.other_off * KS;
-        const Tv *val = reinterpret_cast<const Tv *>(a.val);
+    if (grp >= tl.count) return;
+    const SideDesc &sd = a.sides[tl.side];
+    const int n = a.ord[tl.start + grp];
+    const int64_t p0 = a.ptr[sd.ptr_off + n], p1 = a.ptr[sd.ptr_off + n + 1];
+    const Ts *Xs = reinterpret_cast<const Ts *>(a.X) + sd.other_off * KS;
+    const Tv *val = reinterpret_cast<const Tv *>(a.val);
+    using Tacc = typename PrecT<P>::acc;
+    Tacc wd[KS];
+    load_row<Tacc, KS>(reinterpret_cast<const Ts *>(a.W) + (sd.self_off + n) * KS, wd);
+    double acc = 0.0;
+    for (int64_t e = p0 + gl; e < p1; e += G) {
         Tacc xr[KS];
-        load_row<Tacc, KS>(reinterpret_cast<const Ts *>(a.X) + (sd.self_off + n) * KS, xr);
-        for (int64_t e = p0 + gl; e < p1; e += G) {
-            Tacc w[KS];
-            load_row<Tacc, KS>(W + (int64_t)a.idx[e] * KS, w);
-            Tacc pred = 0;
+        load_row<Tacc, KS>(Xs + (int64_t)a.idx[e] * KS, xr);
+        Tacc dot = 0;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) pred += xr[k] * w[k];
-            const double res = (double)((Tacc)val[e] - pred);
-            s += res * res;
+        for (int i = 0; i < KS; ++i) dot += wd[i] * xr[i];
+        const double res = (double)((Tacc)val[e] - dot);
+        acc += res * res;
+    }
+    for (int m = 1; m < Gw; m <<= 1) acc += __shfl_xor(acc, m);
+    double *slot = a.sse_col + 4 * (sd.self_off + n);
+    if (!wide) {
+        if (gl == 0) {
+            slot[0] = acc;
+            slot[1] = 0.0;
+            slot[2] = 0.0;
+            slot[3] = 0.0;
         }
+    } else if ((threadIdx.x & 63) == 0) {
+        const int wv = (threadIdx.x >> 6) - ((grp * G) >> 6);
+        slot[wv] = acc;
+        if (wv == 0)
+            for (int u = G >> 6; u < 4; ++u) slot[u] = 0.0;
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.part[a.part_base + blockIdx.x] = red[0];
 }
 
 // --------------------------------------------------------------------------
@@ -655,7 +977,7 @@ __global__ __launch_bounds__(256) void k_stats(const StatsArgs a) {
     __shared__ short pr_a[2144], pr_b[2144];
     const StatsJob jb = a.jobs[blockIdx.x];
     const SideDesc &sd = a.sides[jb.side];
-    const Ts *X = reinterpret_cast<const Ts *>(a.X) + sd.self_off * a.ks;
+    const Ts *X = reinterpret_cast<const Ts *>(jb.side < a.nrow_sides ? a.X : a.W) + sd.self_off * a.ks;
     const int K = a.K;
     const int npair = K + K * (K + 1) / 2;
     const int t = threadIdx.x;
@@ -779,12 +1101,13 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
     const HyperJob jb = a.jobs[blockIdx.x];
     const int lane = threadIdx.x;
     const int K = a.K;
+    const uint32_t t_sw = a.ss ? a.ss->t : a.t;
     if (jb.kind == 2) {
         if (lane == 0) {
             const double s = a.sse_part[jb.part_begin];
             const double shape = a.a0 + 0.5 * (double)jb.n;
             const double rate = a.b0 + 0.5 * s;
-            *jb.out = gamma_draw(a.k0, a.k1, 0u, a.t, counter_word(jb.block, kTau), shape) / rate;
+            *jb.out = gamma_draw(a.k0, a.k1, 0u, t_sw, counter_word(jb.block, kTau), shape) / rate;
         }
         return;
     }
@@ -837,11 +1160,11 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
     __syncthreads();
     if (lane < K)
         M2[lane * LD + lane] =
-            sqrt(2.0 * gamma_draw(a.k0, a.k1, (uint32_t)(lane + 1), a.t, c2, 0.5 * (nu_s - lane)));
+            sqrt(2.0 * gamma_draw(a.k0, a.k1, (uint32_t)(lane + 1), t_sw, c2, 0.5 * (nu_s - lane)));
     const int noff = K * (K - 1) / 2;
     for (int g = lane; 4 * g < noff; g += 64) {
         double z[4];
-        normals4(0u, a.t, c2, (uint32_t)g, a.k0, a.k1, z);
+        normals4(0u, t_sw, c2, (uint32_t)g, a.k0, a.k1, z);
         for (int c = 0; c < 4; ++c) {
             const int q = 4 * g + c;
             if (q < noff) {
@@ -875,7 +1198,7 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
     ok = chol_lds<double>(M2, K, LD, 0.0, nullptr, lane, &flag) && ok;
     if (lane * 4 < K) {
         double z[4];
-        normals4((uint32_t)(K + 1), a.t, c2, (uint32_t)lane, a.k0, a.k1, z);
+        normals4((uint32_t)(K + 1), t_sw, c2, (uint32_t)lane, a.k0, a.k1, z);
         for (int c = 0; c < 4; ++c)
             if (4 * lane + c < K) zz[4 * lane + c] = z[c];
     }
@@ -1167,6 +1490,20 @@ __global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
     }
 }
 
+// End of a sweep: next sweep index and its sample slot (kept when
+// t >= burnin, (t - burnin) % thin == 0 and the store is not full).
+__global__ void k_advance(SweepState *ss, int32_t *fb_counts) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    fb_counts[0] = 0;   // fallback queues of the row and column passes
+    fb_counts[1] = 0;
+    SweepState s = *ss;
+    if (s.slot >= 0) s.kept += 1;
+    s.t += 1;
+    const bool keep = (int64_t)s.t >= s.burnin && ((int64_t)s.t - s.burnin) % s.thin == 0 && s.kept < s.max_kept;
+    s.slot = keep ? s.kept : -1;
+    *ss = s;
+}
+
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -1221,12 +1558,13 @@ hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t
 
 template <int KP>
 static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    constexpr bool kMF = KP >= 32;   // BF16 state: Gram on MFMA
     switch (prec) {
-    case kP64: hipLaunchKernelGGL((k_update_wave<KP, kP64>), dim3(grid), dim3(64), 0, s, a); break;
-    case kP32: hipLaunchKernelGGL((k_update_wave<KP, kP32>), dim3(grid), dim3(64), 0, s, a); break;
-    case kPBF: hipLaunchKernelGGL((k_update_wave<KP, kPBF>), dim3(grid), dim3(64), 0, s, a); break;
-    case kPFB32: hipLaunchKernelGGL((k_update_wave<KP, kPFB32>), dim3(grid), dim3(64), 0, s, a); break;
-    case kPFB16: hipLaunchKernelGGL((k_update_wave<KP, kPFB16>), dim3(grid), dim3(64), 0, s, a); break;
+    case kP64: hipLaunchKernelGGL((k_update_wave<KP, kP64, false>), dim3(grid), dim3(64), 0, s, a); break;
+    case kP32: hipLaunchKernelGGL((k_update_wave<KP, kP32, false>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPBF: hipLaunchKernelGGL((k_update_wave<KP, kPBF, kMF>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPFB32: hipLaunchKernelGGL((k_update_wave<KP, kPFB32, false>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPFB16: hipLaunchKernelGGL((k_update_wave<KP, kPFB16, false>), dim3(grid), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1265,6 +1603,17 @@ hipError_t launch_sse(int32_t kc, int32_t prec, const SseArgs &a, int32_t ntiles
     case 64: return sse_kc<64>(prec, a, ntiles, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_gram_part(int32_t kp, const GramPartArgs &a, hipStream_t s) {
+    if (a.nseg <= 0) return hipSuccess;
+    if (kp == 32)
+        hipLaunchKernelGGL(k_gram_part<32>, dim3(a.nseg), dim3(64), 0, s, a);
+    else if (kp == 64)
+        hipLaunchKernelGGL(k_gram_part<64>, dim3(a.nseg), dim3(64), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s) {
@@ -1321,6 +1670,11 @@ hipError_t launch_agg(const AggArgs &a, hipStream_t s) {
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_predict, dim3(grid_for(a.n, 256, 65536)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(SweepState *ss, int32_t *fb_counts, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ss, fb_counts);
     return hipGetLastError();
 }
 

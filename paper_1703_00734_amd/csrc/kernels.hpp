@@ -37,8 +37,10 @@ struct UpdArgs {
     int32_t ks_other;
     void *self;               // updated factors (state precision)
     int32_t ks_self;
-    void *sample;             // this sweep's sample slot (null when not kept)
+    void *sample;             // this sweep's sample slot (null when not kept), or with
+                              // `ss` set: the sample store, slot taken from ss
     int32_t ks_sample;
+    const SweepState *ss;     // when set, t and the sample slot come from here
     int32_t K;
     int32_t prow;             // doubles per moment-matched row
     uint32_t t;               // sweep index (Philox c1)
@@ -48,26 +50,46 @@ struct UpdArgs {
     int2 *fb_list;
     int32_t *fb_total;        // running count of rows sent to the fallback
     int32_t *nonpd;           // FP64 Cholesky failures
+    double *sse_col;          // column pass: per column 4 slots of its SSE (null: skip)
+    const int2 *splits;       // per item (first partial slot, count); count 0: not split
+    const float *gpart;       // partial Grams + right-hand sides (KP*KP + KP floats each)
 };
 
+// Partial Grams of heavy-entity segments (BF16 state, MFMA).
+struct GramPartArgs {
+    const SegItem *segs;
+    int32_t nseg;
+    const SideDesc *sides;
+    const int32_t *idx;
+    const void *val;
+    const void *other;
+    int32_t ks_other;
+    float *gpart;
+};
+
+// Residual sums of squares per column: SSE_d = sum_n (r_nd - x_n^T w_d)^2
+// over the column's observed entries, squares summed in FP64, written to 4
+// slots per column (one per wave of a group; unused slots zero).
 struct SseArgs {
-    const Tile *tiles;        // CSR row tiles grouped by block (tile.side = block in stage)
-    const SideDesc *sides;    // row sides (self = X, other = W)
+    const Tile *tiles;        // CSC column tiles
+    const SideDesc *sides;    // column sides (self = W, other = X)
     const int32_t *ord;
     const int64_t *ptr;
     const int32_t *idx;
     const void *val;
-    const void *X;            // row factors (storage precision)
-    const void *W;            // column factors (storage precision)
+    const void *X;            // row factors (state precision)
+    const void *W;            // column factors (state precision)
     int32_t ks;
-    double *part;             // one partial per tile ...
-    int32_t part_base;        // ... at part[part_base + tile]
+    int32_t K;
+    double *sse_col;
 };
 
 struct StatsArgs {
     const StatsJob *jobs;
     const SideDesc *sides;
-    const void *X;            // factors of the side (storage precision)
+    const void *X;            // row factors (sides < nrow_sides)
+    const void *W;            // column factors (sides >= nrow_sides)
+    int32_t nrow_sides;
     int32_t ks;
     int32_t K;
     double *part;             // njobs x (K + K(K+1)/2)
@@ -90,6 +112,7 @@ struct HyperArgs {
     double beta0, nu0, a0, b0;
     int32_t K;
     uint32_t t, k0, k1;
+    const SweepState *ss;     // when set, t comes from here
     int32_t *nonpd;
 };
 
@@ -141,6 +164,7 @@ hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t
 hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid,
                               hipStream_t s);
 hipError_t launch_sse(int32_t kc, int32_t prec, const SseArgs &a, int32_t ntiles, hipStream_t s);
+hipError_t launch_gram_part(int32_t kp, const GramPartArgs &a, hipStream_t s);
 hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s);
 hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s);
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
@@ -149,5 +173,6 @@ hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
 hipError_t launch_agg(const AggArgs &a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_advance(SweepState *ss, int32_t *fb_counts, hipStream_t s);
 
 }  // namespace bmf

@@ -57,6 +57,30 @@ def test_single_step_update(precision, K, which):
     assert s["nonpd_rows"] == 0
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+@pytest.mark.parametrize("K", [32, 64])
+def test_single_step_heavy_columns(precision, K):
+    """Columns with several thousand entries: on the MFMA path they are split
+    into segments whose partial Grams are summed before the factorisation."""
+    print("case heavy", precision, K, flush=True)
+    d = small_data(K, seed=40 + K, N=6000, D=40, nnz=90000, empty_rows=0)
+    g, o = pair(d, K, precision)
+    g.pp_stage(1, 0)
+    o.begin_stage(1)
+    blk = o.blocks[0]
+    assert np.diff(blk["csc_ptr"]).max() > 2048              # split into segments
+    st = random_state(np.random.default_rng(200 + K), blk["R"], blk["C"], K, scale=0.3)
+    load_state(g, o, 0, st)
+    g.step(0, "cols", 4)
+    o.update_cols(blk, 4)
+    draw = g.get_draw(0, 1)
+    tr = cond_precision_trace(blk, "cols", K, blk["tau"], blk["hw"][0])
+    rel = rel_err_rows(draw, blk["W"], tr, K)
+    print("draw vs oracle: max rel", rel.max(), "median", np.median(rel))
+    assert rel.max() <= TOL[precision]
+    assert np.array_equal(g.get_state(0)["W"], round_state(draw, precision))
+
+
 @pytest.mark.parametrize("K", [2, 10, 33, 64])
 @pytest.mark.parametrize("side", ["hyper_x", "hyper_w"])
 def test_normal_wishart_draw(K, side):
@@ -118,7 +142,8 @@ def test_batched_equals_per_block_and_is_deterministic(precision):
     d = small_data(K, seed=6)
     runs = []
     for batched in (True, False, True):
-        g, _ = pair(d, K, precision, I=2, J=2, order="random", batched=batched, max_kept=2)
+        g, _ = pair(d, K, precision, I=2, J=2, order="random", batched=batched, max_kept=2,
+                    lane_nnz=16)
         g.pp_stage(1, 3)
         runs.append([g.get_state(0)[k] for k in ("X", "W", "tau")])
         g.close()
@@ -126,6 +151,36 @@ def test_batched_equals_per_block_and_is_deterministic(precision):
         assert np.array_equal(a, b)
     for a, b in zip(runs[0], runs[2]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_graph_replays_match_eager_sweeps(precision):
+    """Sweeps replayed from the captured graph, with eager copies and
+    synchronisations between replays, equal eagerly launched sweeps bit for bit,
+    replay after replay."""
+    K = 10
+    d = small_data(K, seed=8)
+    g, _ = pair(d, K, precision, I=2, J=2, order="random", lane_nnz=16, max_kept=6, burnin=2)
+    e, _ = pair(d, K, precision, I=2, J=2, order="random", lane_nnz=16, max_kept=6, burnin=2)
+    e.enable_timing(True)                    # per-launch events: eager sweeps
+    g.gibbs_sweep(0)
+    e.gibbs_sweep(0)
+    for rep in range(5):
+        g.gibbs_sweep(1)
+        e.gibbs_sweep(1)
+        for b in (0,):
+            sg, se = g.get_state(b), e.get_state(b)
+            for key in ("X", "W", "tau"):
+                assert np.array_equal(sg[key], se[key]), (rep, key)
+            assert np.array_equal(sg["hx"][0], se["hx"][0])
+    g.pp_stage(2, 3)
+    e.pp_stage(2, 3)
+    for b in range(4):
+        if g.block_info(b)["stage"] == 2:
+            sg, se = g.get_state(b), e.get_state(b)
+            assert np.array_equal(sg["X"], se["X"]) and np.array_equal(sg["W"], se["W"])
+    for b in (1, 2):
+        np.testing.assert_array_equal(g.get_mm(0, 0)[0], e.get_mm(0, 0)[0])
 
 
 def test_fp64_chain_tracks_oracle_1x1():
