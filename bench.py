@@ -36,6 +36,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-rmse", action="store_true", help="skip the equal-RMSE chains")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run 5 device-to-device copies of MIB MiB (to scale the HBM "
+                        "traffic counters), then exit")
     return p.parse_args()
 
 
@@ -167,6 +170,15 @@ def main():
     import torch
     import synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.copy_calibration > 0:
+        n = a.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": n, "copies": 5}))
+        return
     cfg = dict(synth.CONFIGS[a.config])
     d = synth.config(a.config, seed=a.seed)
     K = d["K"]

@@ -39,6 +39,9 @@ const char *kKNames[kNumK] = {"update_rows", "update_cols", "gram_segments", "up
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+struct Layout;
+int64_t kHyPacked(const Layout &L);
+
 // Sizes of everything the device holds, computable from the configuration.
 struct Layout {
     int32_t K = 0, kc = 0, prec = 0, ks_m = 0, ks_p = 0, prow = 0, hy = 0, npair = 0;
@@ -54,6 +57,9 @@ struct Layout {
     bool mfma = false;
 };
 
+// Offset (doubles) of the packed prior row inside a hyperparameter slot.
+int64_t kHyPacked(const Layout &L) { return (int64_t)L.K * L.K + 2 * L.K; }
+
 bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L = Layout();
     L.K = c.K;
@@ -66,7 +72,7 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.ks_m = stride_for(L.kc, (int32_t)L.ss);
     L.ks_p = stride_for(L.kc, (int32_t)L.sp);
     L.prow = c.K * (c.K + 1) / 2 + 2 * c.K;
-    L.hy = c.K * c.K + 2 * c.K;
+    L.hy = c.K * c.K + 2 * c.K + L.prow;   // [Lambda, mu, Lambda mu, packed row]
     L.npair = c.K + c.K * (c.K + 1) / 2;
     L.nb = (int64_t)c.I * c.J;
     L.E_r = (int64_t)c.J * c.N;
@@ -219,7 +225,8 @@ struct bmf_ctx {
     bool bf() const { return cfg.precision == BMF_PREC_BF16; }
     bool fp64() const { return cfg.precision == BMF_PREC_FP64; }
     int32_t prec() const { return cfg.precision == BMF_PREC_FP64 ? kP64 : (bf() ? kPBF : kP32); }
-    bool reg() const { return L.kc <= 16; }
+    // register kernel for K <= 16 (FP64: K <= 12), wavefront kernels above
+    bool reg() const { return L.kc <= (cfg.precision == BMF_PREC_FP64 ? 12 : 16); }
 };
 
 namespace {
@@ -369,7 +376,7 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         r.other_off = c->w_off[b];
         r.sample_off = soff;
         soff += B.R;
-        r.prior = xp ? mm + c->x_off[B.i * J + 0] * L.prow : hyper + ((int64_t)b * 2 + 0) * L.hy;
+        r.prior = xp ? mm + c->x_off[B.i * J + 0] * L.prow : hyper + ((int64_t)b * 2 + 0) * L.hy + kHyPacked(L);
         r.tau = tau + b;
         r.n = (int32_t)B.R;
         r.per_row = xp;
@@ -381,7 +388,7 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         q.other_off = c->x_off[b];
         q.sample_off = soff;
         soff += B.C;
-        q.prior = wp ? mm + (L.E_r + c->w_off[0 * J + B.j]) * L.prow : hyper + ((int64_t)b * 2 + 1) * L.hy;
+        q.prior = wp ? mm + (L.E_r + c->w_off[0 * J + B.j]) * L.prow : hyper + ((int64_t)b * 2 + 1) * L.hy + kHyPacked(L);
         q.tau = tau + b;
         q.n = (int32_t)B.C;
         q.per_row = wp;
@@ -980,7 +987,10 @@ static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
     // hyperparameters (0, I), tau
     const int32_t K = c->cfg.K;
     std::vector<double> hy(L.hy, 0.0);
-    for (int k = 0; k < K; ++k) hy[k * K + k] = 1.0;
+    for (int k = 0; k < K; ++k) {
+        hy[k * K + k] = 1.0;                                    // Lambda = I, mu = 0
+        hy[kHyPacked(L) + k * (k + 1) / 2 + k] = 1.0;          // packed Lambda
+    }
     const double tau0 = c->cfg.sample_tau ? c->cfg.tau_a0 / c->cfg.tau_b0 : c->cfg.tau_fixed;
     for (int32_t b : S.blocks) {
         if ((st = upload(c, L.hyper + ((int64_t)b * 2 + 0) * L.hy * 8, hy.data(), 8 * L.hy))) return st;
@@ -1503,10 +1513,14 @@ bmf_status bmf_set_state(bmf_ctx *c, int32_t b, const double *X, const double *W
             const double *mu = Lam + K * K;
             std::copy(Lam, Lam + K * K, h.begin() + side * L.hy);
             std::copy(mu, mu + K, h.begin() + side * L.hy + K * K);
+            double *pk = h.data() + side * L.hy + kHyPacked(L);
             for (int a = 0; a < K; ++a) {
                 double s = 0.0;
                 for (int q = 0; q < K; ++q) s += Lam[a * K + q] * mu[q];
                 h[side * L.hy + K * K + K + a] = s;
+                pk[K * (K + 1) / 2 + a] = s;
+                pk[K * (K + 1) / 2 + K + a] = mu[a];
+                for (int q = 0; q <= a; ++q) pk[a * (a + 1) / 2 + q] = Lam[a * K + q];
             }
         }
         HIPCHK(c, hipMemcpy(c->base + L.hyper + (int64_t)b * 2 * L.hy * 8, h.data(), 16 * L.hy, hipMemcpyHostToDevice));

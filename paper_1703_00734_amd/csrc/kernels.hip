@@ -306,10 +306,12 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
         if (!active) return;
     }
 
-    // A = P + tau G, h = P m + tau hs (identity padding beyond K)
+    // A = P + tau G, h = P m + tau hs (identity padding beyond K); the prior is
+    // a packed row [P lower (row-major), P m, m]: the side's own row when
+    // propagated, the shared Normal-Wishart prior otherwise
     const Tacc tau = (Tacc)(*sd.tau);
-    if (sd.per_row) {
-        const double *pr = sd.prior + (int64_t)n * a.prow;
+    {
+        const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
         const double *eta = pr + K * (K + 1) / 2;
 #pragma unroll
         for (int i = 0; i < KC; ++i) {
@@ -317,16 +319,6 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
             for (int j = 0; j <= i; ++j)
                 g[tri(i, j)] = (i < K) ? (Tacc)pr[tri(i, j)] + tau * g[tri(i, j)] : (Tacc)(i == j);
             hs[i] = (i < K) ? (Tacc)eta[i] + tau * hs[i] : (Tacc)0;
-        }
-    } else {
-        const double *Lam = sd.prior;
-        const double *Lmu = sd.prior + K * K + K;
-#pragma unroll
-        for (int i = 0; i < KC; ++i) {
-#pragma unroll
-            for (int j = 0; j <= i; ++j)
-                g[tri(i, j)] = (i < K) ? (Tacc)Lam[i * K + j] + tau * g[tri(i, j)] : (Tacc)(i == j);
-            hs[i] = (i < K) ? (Tacc)Lmu[i] + tau * hs[i] : (Tacc)0;
         }
     }
 
@@ -489,126 +481,79 @@ __device__ void bwd_lds(const T *M, int K, int ld, T *x, int lane) {
     }
 }
 
-// Blocked variants for the update kernels: panels of PB = 8 columns.  The
-// diagonal block is factored by lane 0 in registers, the panel below it and
-// the trailing lower triangle are updated lane-parallel (one row per lane),
-// three barriers per panel.  Same pivot test as chol_lds.
-constexpr int kPB = 8;
-
-template <typename T>
-__device__ __forceinline__ void diag_block_factor(T *M, int ld, int p0, int pb, T theta, const T *diag0,
-                                                  int *flag) {
-    T a[kPB][kPB];
-#pragma unroll
-    for (int i = 0; i < kPB; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j)
-            a[i][j] = (i < pb) ? M[(p0 + i) * ld + p0 + j] : (T)(i == j);
-#pragma unroll
-    for (int i = 0; i < kPB; ++i) {
-#pragma unroll
-        for (int j = 0; j <= i; ++j) {
-            T s = a[i][j];
-#pragma unroll
-            for (int q = 0; q < j; ++q) s -= a[i][q] * a[j][q];
-            if (i == j) {
-                const bool bad = i < pb && ((theta > (T)0) ? !(s > theta * diag0[p0 + i]) : !(s > (T)0));
-                if (bad) *flag = 1;
-                a[i][i] = sqrt(s > (T)0 ? s : (T)1);
-            } else {
-                a[i][j] = s / a[j][j];
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < kPB; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j)
-            if (i < pb) M[(p0 + i) * ld + p0 + j] = a[i][j];
+// Broadcast of lane `src`'s value to the whole wavefront (src uniform).
+__device__ __forceinline__ float wave_bcast(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+__device__ __forceinline__ double wave_bcast(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T>
-__device__ bool chol_blocked(T *M, int K, int ld, T theta, const T *diag0, int lane, int *flag) {
-    if (lane == 0) *flag = 0;
+// Factor A = L L^T and solve x = L^-T (L^-1 h + z) in registers, one matrix row
+// per lane (KP <= 64 lanes).  Step k of the right-looking factorisation
+// broadcasts the pivot and column k (v_readlane) and each lane updates its
+// own row; the forward solve keeps row ownership, the backward solve column
+// ownership (L transposed once through LDS).  In: sA (lower, KP x KP with
+// identity padding), sh = h, sz = z (zero beyond K), diag0 = diag(A).  Out:
+// sh = x.  Returns false when a pivot fails the test of chol_lds.  All 64
+// lanes call it.
+template <int KP, typename T>
+__device__ bool factor_solve_regs(T *sA, int ld, T *sh, const T *sz, const T *diag0, T *sinv,
+                                  T theta, int K, int lane) {
+    const bool own = lane < KP;
+    T r[KP];
+#pragma unroll
+    for (int j = 0; j < KP; ++j) r[j] = (own && j <= lane) ? sA[lane * ld + j] : (T)0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        const T dk = wave_bcast(r[k], k);
+        bad = bad || (k < K && ((theta > (T)0) ? !(dk > theta * diag0[k]) : !(dk > (T)0)));
+        const T lkk = sqrt(dk > (T)0 ? dk : (T)1);
+        const T inv = (T)1 / lkk;
+        if (lane == 0) sinv[k] = inv;
+        r[k] = (lane > k) ? r[k] * inv : (lane == k ? lkk : r[k]);
+#pragma unroll
+        for (int j = k + 1; j < KP; ++j) {
+            const T ljk = wave_bcast(r[k], j);
+            r[j] = (lane >= j) ? r[j] - r[k] * ljk : r[j];
+        }
+    }
     __syncthreads();
-    for (int p0 = 0; p0 < K; p0 += kPB) {
-        const int pb = K - p0 < kPB ? K - p0 : kPB;
-        if (lane == 0) diag_block_factor<T>(M, ld, p0, pb, theta, diag0, flag);
-        __syncthreads();
-        const int i = p0 + pb + lane;
-        if (i < K) {
-            // panel row i: L[i][p0 + j] = (A[i][p0 + j] - sum_{q<j} L[i][p0+q] L[p0+j][p0+q]) / L[p0+j][p0+j]
-            T r[kPB];
+    // forward: y = L^-1 h, then v = y + z
+    T acc = own ? sh[lane] : (T)0;
+    T y = (T)0;
 #pragma unroll
-            for (int j = 0; j < kPB; ++j) {
-                if (j < pb) {
-                    T s = M[i * ld + p0 + j];
+    for (int q = 0; q < KP; ++q) {
+        const T yq = wave_bcast(acc, q) * sinv[q];
+        if (lane == q) y = yq;
+        acc = (lane > q) ? acc - r[q] * yq : acc;
+    }
+    const T v = (lane < K) ? y + sz[lane] : (T)0;
+    // L^T by columns: lane i takes column i of L
 #pragma unroll
-                    for (int q = 0; q < j; ++q) s -= r[q] * M[(p0 + j) * ld + p0 + q];
-                    r[j] = s / M[(p0 + j) * ld + p0 + j];
-                    M[i * ld + p0 + j] = r[j];
-                } else {
-                    r[j] = (T)0;
-                }
-            }
-            // trailing update of row i: A[i][j] -= sum_q L[i][p0+q] L[j][p0+q], p0+pb <= j <= i
-            for (int j = p0 + pb; j <= i; ++j) {
-                T s = M[i * ld + j];
+    for (int j = 0; j < KP; ++j)
+        if (own && j <= lane) sA[lane * ld + j] = r[j];
+    __syncthreads();
+    T c[KP];
 #pragma unroll
-                for (int q = 0; q < kPB; ++q)
-                    if (q < pb) s -= r[q] * M[j * ld + p0 + q];
-                M[i * ld + j] = s;
-            }
-        }
-        __syncthreads();
+    for (int q = 0; q < KP; ++q) c[q] = (own && q >= lane) ? sA[q * ld + lane] : (T)0;
+    // backward: x = L^-T v
+    acc = v;
+    T x = (T)0;
+#pragma unroll
+    for (int q = KP - 1; q >= 0; --q) {
+        const T xq = wave_bcast(acc, q) * sinv[q];
+        if (lane == q) x = xq;
+        acc = (lane < q) ? acc - c[q] * xq : acc;
     }
-    return *flag == 0;
-}
-
-// y <- L^-1 y, blocked: lane 0 solves each diagonal block, lanes update the rest.
-template <typename T>
-__device__ void fwd_blocked(const T *M, int K, int ld, T *y, int lane) {
-    for (int p0 = 0; p0 < K; p0 += kPB) {
-        const int pb = K - p0 < kPB ? K - p0 : kPB;
-        if (lane == 0) {
-            for (int i = 0; i < pb; ++i) {
-                T s = y[p0 + i];
-                for (int q = 0; q < i; ++q) s -= M[(p0 + i) * ld + p0 + q] * y[p0 + q];
-                y[p0 + i] = s / M[(p0 + i) * ld + p0 + i];
-            }
-        }
-        __syncthreads();
-        const int i = p0 + pb + lane;
-        if (i < K) {
-            T s = y[i];
-            for (int q = 0; q < pb; ++q) s -= M[i * ld + p0 + q] * y[p0 + q];
-            y[i] = s;
-        }
-        __syncthreads();
-    }
-}
-
-// x <- L^-T x, blocked from the last panel backwards.
-template <typename T>
-__device__ void bwd_blocked(const T *M, int K, int ld, T *x, int lane) {
-    const int last = ((K - 1) / kPB) * kPB;
-    for (int p0 = last; p0 >= 0; p0 -= kPB) {
-        const int pb = K - p0 < kPB ? K - p0 : kPB;
-        if (lane == 0) {
-            for (int i = pb - 1; i >= 0; --i) {
-                T s = x[p0 + i];
-                for (int q = i + 1; q < pb; ++q) s -= M[(p0 + q) * ld + p0 + i] * x[p0 + q];
-                x[p0 + i] = s / M[(p0 + i) * ld + p0 + i];
-            }
-        }
-        __syncthreads();
-        if (lane < p0) {
-            T s = x[lane];
-            for (int q = 0; q < pb; ++q) s -= M[(p0 + q) * ld + lane] * x[p0 + q];
-            x[lane] = s;
-        }
-        __syncthreads();
-    }
+    __syncthreads();
+    if (own) sh[lane] = x;
+    __syncthreads();
+    return !bad;
 }
 
 __device__ __forceinline__ void unrank_tri(int q, int &r, int &c) {
@@ -640,35 +585,48 @@ __device__ __forceinline__ void mfma_gram(const uint16_t *other, int ks, const i
                                           float &hhi) {
     const int col = lane & 31;
     const int kg = (lane >> 5) * 8;
-    for (int64_t c0 = b0; c0 < b1; c0 += 16) {
-        u16x8_t lo, hi;
-        float rr[8];
+    // two chunks of 16 entries per iteration: all index loads, then all factor
+    // loads, then the MFMAs, so both chunks' gathers are in flight together
+    for (int64_t c0 = b0; c0 < b1; c0 += 32) {
+        int32_t d[2][8];
+        float rr[2][8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t e = c0 + kg + j;
-            unsigned short vlo = 0, vhi = 0;
-            float r = 0.0f;
-            if (e < b1) {
-                const uint16_t *row = other + (int64_t)idx[e] * ks;
-                vlo = row[col];
-                if constexpr (KP == 64) vhi = row[32 + col];
-                r = val[e];
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t e = c0 + 16 * u + kg + j;
+                const bool ok = e < b1;
+                d[u][j] = ok ? idx[e] : -1;
+                rr[u][j] = ok ? val[e] : 0.0f;
             }
-            lo[j] = vlo;
-            hi[j] = vhi;
-            rr[j] = r;
-        }
+        u16x8_t lo[2], hi[2];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            hlo += rr[j] * bf16_to_f32(lo[j]);
-            if constexpr (KP == 64) hhi += rr[j] * bf16_to_f32(hi[j]);
-        }
-        const bf16x8_t blo = __builtin_bit_cast(bf16x8_t, lo);
-        c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(blo, blo, c00, 0, 0, 0);
-        if constexpr (KP == 64) {
-            const bf16x8_t bhi = __builtin_bit_cast(bf16x8_t, hi);
-            c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, blo, c10, 0, 0, 0);
-            c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, bhi, c11, 0, 0, 0);
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                unsigned short vlo = 0, vhi = 0;
+                if (d[u][j] >= 0) {
+                    const uint16_t *row = other + (int64_t)d[u][j] * ks;
+                    vlo = row[col];
+                    if constexpr (KP == 64) vhi = row[32 + col];
+                }
+                lo[u][j] = vlo;
+                hi[u][j] = vhi;
+            }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                hlo += rr[u][j] * bf16_to_f32(lo[u][j]);
+                if constexpr (KP == 64) hhi += rr[u][j] * bf16_to_f32(hi[u][j]);
+            }
+            const bf16x8_t blo = __builtin_bit_cast(bf16x8_t, lo[u]);
+            c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(blo, blo, c00, 0, 0, 0);
+            if constexpr (KP == 64) {
+                const bf16x8_t bhi = __builtin_bit_cast(bf16x8_t, hi[u]);
+                c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, blo, c10, 0, 0, 0);
+                c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, bhi, c11, 0, 0, 0);
+            }
         }
     }
     hlo += __shfl_xor(hlo, 32);
@@ -727,12 +685,12 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     constexpr int CH = 32;
     constexpr int LD = KP + 1;
     __shared__ Tacc sA[KP * LD];
-    __shared__ Tacc sw[CH * KP];
-    __shared__ Tacc sr[CH];
+    __shared__ Tacc sw[MF ? 1 : CH * KP];
+    __shared__ Tacc sr[MF ? 1 : CH];
     __shared__ Tacc sh[KP];
     __shared__ Tacc sz[KP];
     __shared__ Tacc sd0[KP];
-    __shared__ int sflag;
+    __shared__ Tacc sinv[KP];
 
     const int lane = threadIdx.x;
     const int K = a.K;
@@ -779,17 +737,21 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             }
             __syncthreads();
             const Tacc tau = (Tacc)(*sd.tau);
-            const double *pr = sd.per_row ? sd.prior + (int64_t)n * a.prow : sd.prior;
-            const double *pv = sd.per_row ? pr + K * (K + 1) / 2 : pr + K * K + K;
-            for (int q = lane; q < KP * KP; q += 64) {
-                const int ra = q / KP, cb = q - ra * KP;
-                if (cb > ra) continue;
-                if (ra < K) {
-                    const double p = sd.per_row ? pr[tri(ra, cb)] : pr[ra * K + cb];
-                    sA[ra * LD + cb] = (Tacc)p + tau * sA[ra * LD + cb];
-                } else {
-                    sA[ra * LD + cb] = (Tacc)(ra == cb);
-                }
+            const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
+            const double *pv = pr + K * (K + 1) / 2;
+            // packed lower prior, lanes over consecutive entries (coalesced)
+            const int npk = K * (K + 1) / 2;
+            for (int q = lane; q < npk; q += 64) {
+                int ra = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+                while (ra * (ra + 1) / 2 > q) --ra;
+                while ((ra + 1) * (ra + 2) / 2 <= q) ++ra;
+                const int cb = q - ra * (ra + 1) / 2;
+                sA[ra * LD + cb] = (Tacc)pr[q] + tau * sA[ra * LD + cb];
+            }
+            // identity padding rows K..KP-1
+            for (int q = lane; q < (KP - K) * KP; q += 64) {
+                const int ra = K + q / KP, cb = q % KP;
+                if (cb <= ra) sA[ra * LD + cb] = (Tacc)(ra == cb);
             }
             for (int q = lane; q < KP; q += 64) sh[q] = q < K ? (Tacc)pv[q] + tau * sh[q] : (Tacc)0;
         } else {
@@ -833,8 +795,8 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             __syncthreads();
 
             const Tacc tau = (Tacc)(*sd.tau);
-            const double *pr = sd.per_row ? sd.prior + (int64_t)n * a.prow : sd.prior;
-            const double *pv = sd.per_row ? pr + K * (K + 1) / 2 : pr + K * K + K;
+            const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
+            const double *pv = pr + K * (K + 1) / 2;
     #pragma unroll
             for (int i = 0; i < TL; ++i) {
     #pragma unroll
@@ -842,7 +804,7 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
                     const int ra = ti * TL + i, cb = tj * TL + j;
                     Tacc v;
                     if (ra < K && cb < K) {
-                        const double p = sd.per_row ? pr[ra >= cb ? tri(ra, cb) : tri(cb, ra)] : pr[ra * K + cb];
+                        const double p = pr[ra >= cb ? tri(ra, cb) : tri(cb, ra)];
                         v = (Tacc)p + tau * acc[i][j];
                     } else {
                         v = (Tacc)(ra == cb);
@@ -865,10 +827,11 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             for (int c = 0; c < 4; ++c)
                 if (4 * lane + c < K) sz[4 * lane + c] = z[c];
         }
+        if (lane >= K && lane < KP) sz[lane] = (Tacc)0;
         __syncthreads();
         if (lane < KP) sd0[lane] = sA[lane * LD + lane];
         __syncthreads();
-        const bool ok = chol_blocked<Tacc>(sA, K, LD, (Tacc)a.theta, sd0, lane, &sflag);
+        const bool ok = factor_solve_regs<KP, Tacc>(sA, LD, sh, sz, sd0, sinv, (Tacc)a.theta, K, lane);
         if (!ok) {
             if (lane == 0) {
                 if (a.fb_list) {
@@ -881,10 +844,6 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             }
             continue;
         }
-        fwd_blocked<Tacc>(sA, K, LD, sh, lane);
-        if (lane < K) sh[lane] += sz[lane];
-        __syncthreads();
-        bwd_blocked<Tacc>(sA, K, LD, sh, lane);
         const Tacc xv = lane < K ? sh[lane] : (Tacc)0;
         Ts *self = reinterpret_cast<Ts *>(a.self);
         if (lane < a.ks_self) self[(sd.self_off + n) * a.ks_self + lane] = elem_from<Ts>((double)xv);
@@ -1210,10 +1169,18 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
         outL[K * K + lane] = m;
     }
     __syncthreads();
+    double *packed = outL + K * K + 2 * K;      // [Lambda packed lower, Lambda mu, mu]
     if (lane < K) {
         double s = 0.0;
         for (int c = 0; c < K; ++c) s += M1[lane * LD + c] * sx[c];
         outL[K * K + K + lane] = s;
+        packed[K * (K + 1) / 2 + lane] = s;
+        packed[K * (K + 1) / 2 + K + lane] = sx[lane];
+    }
+    for (int q = lane; q < K * (K + 1) / 2; q += 64) {
+        int r, c;
+        unrank_tri(q, r, c);
+        packed[q] = M1[r * LD + c];
     }
     if (!ok && lane == 0) atomicAdd(a.nonpd, 1);
 }
@@ -1534,7 +1501,11 @@ static inline int grid_for(int64_t work, int per, int cap) {
 template <int KC>
 static hipError_t upd_reg_kc(int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {
     switch (prec) {
-    case kP64: hipLaunchKernelGGL((k_update_reg<KC, kP64>), dim3(ntiles), dim3(256), 0, s, a); break;
+    case kP64:
+        // FP64 above K = 12 exceeds the register file; the wavefront kernel serves it
+        if constexpr (KC > 12) return hipErrorInvalidValue;
+        else hipLaunchKernelGGL((k_update_reg<KC, kP64>), dim3(ntiles), dim3(256), 0, s, a);
+        break;
     case kP32: hipLaunchKernelGGL((k_update_reg<KC, kP32>), dim3(ntiles), dim3(256), 0, s, a); break;
     case kPBF: hipLaunchKernelGGL((k_update_reg<KC, kPBF>), dim3(ntiles), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
