@@ -11,6 +11,7 @@ after burn-in are reported.
 Prints one JSON line.  `--gpus N` with N > 1 is not supported (one GPU).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +37,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-rmse", action="store_true", help="skip the equal-RMSE chains")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--batched-only", action="store_true",
+                   help="skip the plain FP32 arm (for profiler runs)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run 5 device-to-device copies of MIB MiB (to scale the HBM "
                         "traffic counters), then exit")
@@ -50,6 +53,38 @@ def algorithmic_bytes(kind, M, n, K, state_bytes, kept):
     if kept:
         b += n * K * 4
     return b
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1703_00734_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kclass, config, precision):
+    """HBM bytes per launch of an update pass, from the rocprofv3 FETCH_SIZE and
+    WRITE_SIZE counter passes summarised under profiles/ (each counter scaled by
+    what it reads for a device copy of known size).  None when no summary covers
+    this pass, or when the kernel sources have changed since the counters were
+    taken."""
+    want = kernel_sources_hash()
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    for f in sorted(os.listdir(d)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record: "):
+                    continue
+                r = json.loads(line[len("traffic-record: "):])
+                if (r["kclass"] == kclass and r["config"] == config and r["precision"] == precision
+                        and r["sources"] == want):
+                    return r["hbm_bytes_per_launch"]
+    return None
 
 
 def stages_of(cfg):
@@ -187,7 +222,7 @@ def main():
     arms["batched_" + main_prec] = run_arm(d, cfg, main_prec, True, a.steps, a.warmup,
                                            not a.no_rmse, 101)
     print("arm batched %s done" % main_prec, file=sys.stderr, flush=True)
-    if main_prec != "fp64":
+    if main_prec != "fp64" and not a.batched_only:
         arms["plain_fp32"] = run_arm(d, cfg, "fp32", False, a.steps, a.warmup, not a.no_rmse, 101)
         print("arm plain fp32 done", file=sys.stderr, flush=True)
     stages = stages_of(cfg)
@@ -209,7 +244,8 @@ def main():
         avg_ms = tot_ms / launches
         ach = per_launch / (avg_ms / 1000.0) / 1e9
         roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None, avg_launch_ms=avg_ms,
+                    frac=ach / HBM_PEAK_GBS,
+                    traffic=measured_traffic(dom, a.config, main_prec), avg_launch_ms=avg_ms,
                     algorithmic_bytes_per_launch=per_launch)
     out = {
         "metric": METRIC,

@@ -10,14 +10,16 @@
 // propagated moment-matched per-row prior of PP stages 2-3 (eq. stage2a-stage3).
 //
 // Two update kernels:
-//   * k_update_reg<KC>: K <= 16.  G lanes per entity (G a power of two <= 64,
+//   * k_update_reg<KC>: K <= 16.  G lanes per entity (G a power of two <= 256,
 //     chosen per degree), each lane accumulating the full packed Gram and
 //     right-hand side in registers over a strided share of Omega_n; a
-//     butterfly reduction leaves the exact same sums in every lane of the
-//     group, which then factor and solve redundantly in registers.
-//   * k_update_wave<KP>: K <= 64, one wavefront per entity, factors staged in
-//     LDS, 8x8 lane grid of register tiles for the Gram, and a
-//     column-parallel Cholesky and triangular solves in LDS.  Also runs the
+//     butterfly reduction (DPP and lane swaps) leaves the exact same sums in
+//     every lane of the group, which then factor and solve redundantly in
+//     registers.
+//   * k_update_wave<KP>: K <= 64, one wavefront per entity.  The Gram is
+//     accumulated on MFMA (BF16 state, KP >= 32) or as an 8x8 lane grid of
+//     register tiles; the Cholesky factor and both triangular solves run in
+//     registers, one matrix row per lane, with lane broadcasts.  Also runs the
 //     FP64 redo of rows whose FP32 pivot test failed.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -86,6 +88,64 @@ __device__ double gamma_draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
         if (log(unif_d(o[2])) < 0.5 * z * z + d - d * v + d * log(v)) return d * v * boost;
     }
     return d * boost;
+}
+
+// --------------------------------------------------------------------------
+// butterfly sums inside a wavefront without the LDS crossbar
+// --------------------------------------------------------------------------
+// Step M of a butterfly over aligned groups of 2M lanes, for groups of M lanes
+// that already hold one value each: M = 1, 2 pair lanes inside a quad (DPP
+// quad_perm), M = 4, 8 mirror the 8- or 16-lane row (DPP row_half_mirror,
+// row_mirror: lane i meets lane 2M-1-i, which holds what lane i^M holds), and
+// M = 16, 32 swap rows between two registers (v_permlane16_swap /
+// v_permlane32_swap).  Every lane of a group ends with the same two addends, so
+// the group holds bitwise identical sums: the tree is that of the xor
+// butterfly.
+template <int M> __device__ __forceinline__ int dpp_partner(int v) {
+    if constexpr (M == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (M == 4) return __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    else return __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+}
+template <int M> __device__ __forceinline__ float bfly_step(float v) {
+    const int b = __float_as_int(v);
+    if constexpr (M < 16) {
+        return v + __int_as_float(dpp_partner<M>(b));
+    } else {
+        const auto s = M == 16 ? __builtin_amdgcn_permlane16_swap(b, b, false, false)
+                               : __builtin_amdgcn_permlane32_swap(b, b, false, false);
+        return __int_as_float(s[0]) + __int_as_float(s[1]);
+    }
+}
+template <int M> __device__ __forceinline__ double bfly_step(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = (int)(b & 0xFFFFFFFFll), hi = (int)(b >> 32);
+    auto join = [](int l, int h) { return __longlong_as_double(((long long)h << 32) | (unsigned int)l); };
+    if constexpr (M < 16) {
+        return v + join(dpp_partner<M>(lo), dpp_partner<M>(hi));
+    } else {
+        const auto sl = M == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                                : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto sh = M == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                                : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return join(sl[0], sh[0]) + join(sl[1], sh[1]);
+    }
+}
+// Sums over aligned groups of Gw lanes (Gw a power of two <= 64, uniform over
+// the wavefront); every lane of a group ends with the group's sum.
+template <typename T, int N>
+__device__ __forceinline__ void group_sum(T (&v)[N], int Gw) {
+#define BMF_BFLY_STEP(M)                                          \
+    if (Gw > M) {                                                 \
+        _Pragma("unroll") for (int q = 0; q < N; ++q) v[q] = bfly_step<M>(v[q]); \
+    }
+    BMF_BFLY_STEP(1) BMF_BFLY_STEP(2) BMF_BFLY_STEP(4) BMF_BFLY_STEP(8) BMF_BFLY_STEP(16) BMF_BFLY_STEP(32)
+#undef BMF_BFLY_STEP
+}
+template <typename T> __device__ __forceinline__ T group_sum1(T v, int Gw) {
+    T a[1] = {v};
+    group_sum(a, Gw);
+    return a[0];
 }
 
 // --------------------------------------------------------------------------
@@ -198,7 +258,9 @@ __device__ __forceinline__ void store_row(uint16_t *p, const Tacc (&x)[KC], int 
 // --------------------------------------------------------------------------
 // k_update_reg: K <= KC <= 16, G lanes per entity, Gram in registers.
 // --------------------------------------------------------------------------
-template <int KC, int P>
+// SSE: the column pass also writes each column's residual sum of squares
+// (a.sse_col), for the tau draw of the same sweep.
+template <int KC, int P, bool SSE>
 __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     using Tacc = typename PrecT<P>::acc;
     using Tw = typename PrecT<P>::w;
@@ -239,14 +301,26 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
 #pragma unroll
     for (int i = 0; i < KC; ++i) hs[i] = 0;
 
-    // two entries per iteration: both gathers are in flight before the FMAs
+    // two entries per iteration: both gathers are in flight before the FMAs,
+    // and the next pair's indices and values are requested before them too
     int64_t e = p0 + gl;
+    int dn0 = 0, dn1 = 0;
+    Tacc rn0 = 0, rn1 = 0;
+    if (e + G < p1) {
+        dn0 = a.idx[e]; dn1 = a.idx[e + G];
+        rn0 = (Tacc)val[e]; rn1 = (Tacc)val[e + G];
+    }
     for (; e + G < p1; e += 2 * G) {
-        const int d0 = a.idx[e], d1 = a.idx[e + G];
-        const Tacc r0 = (Tacc)val[e], r1 = (Tacc)val[e + G];
+        const int d0 = dn0, d1 = dn1;
+        const Tacc r0 = rn0, r1 = rn1;
         Tacc w0[KSW], w1[KSW];
         load_row<Tacc, KSW>(other + (int64_t)d0 * KSW, w0);
         load_row<Tacc, KSW>(other + (int64_t)d1 * KSW, w1);
+        const int64_t en = e + 2 * G;
+        if (en + G < p1) {
+            dn0 = a.idx[en]; dn1 = a.idx[en + G];
+            rn0 = (Tacc)val[en]; rn1 = (Tacc)val[en + G];
+        }
 #pragma unroll
         for (int i = 0; i < KC; ++i) {
             hs[i] += r0 * w0[i];
@@ -273,12 +347,8 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     // butterfly inside the wave: every lane of the group ends with bitwise
     // identical sums
     const int Gw = G < 64 ? G : 64;
-    for (int m = 1; m < Gw; m <<= 1) {
-#pragma unroll
-        for (int q = 0; q < NT; ++q) g[q] += __shfl_xor(g[q], m);
-#pragma unroll
-        for (int i = 0; i < KC; ++i) hs[i] += __shfl_xor(hs[i], m);
-    }
+    group_sum(g, Gw);
+    group_sum(hs, Gw);
     if (wide) {
         // groups spanning several waves: wave sums through LDS, added in wave order
         __shared__ Tacc wsum[4][NT + KC];
@@ -392,14 +462,37 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
         store_row<KC>(self + (sd.self_off + n) * KSS, x, K);
         if (sample) store_row<KC>(reinterpret_cast<Tp *>(sample) + (sd.sample_off + n) * KSP, x, K);
     }
-    if (a.sse_col) {
+    if constexpr (SSE) {
         // residual SSE of this column with the new w as stored: residuals in the
         // pass's arithmetic, squares summed in FP64
         Tacc wd[KC];
 #pragma unroll
         for (int i = 0; i < KC; ++i) wd[i] = i < K ? (Tacc)elem_to_d(elem_from<Ts>((double)x[i])) : (Tacc)0;
+        // four entries per iteration so that four gathers are in flight; the
+        // squares are added in entry order
         double acc = 0.0;
-        for (int64_t e2 = p0 + gl; e2 < p1; e2 += G) {
+        int64_t e2 = p0 + gl;
+        for (; e2 + 3 * G < p1; e2 += 4 * G) {
+            int dd[4];
+            Tacc rv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                dd[u] = a.idx[e2 + u * G];
+                rv[u] = (Tacc)val[e2 + u * G];
+            }
+            Tacc xr[4][KSW];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) load_row<Tacc, KSW>(other + (int64_t)dd[u] * KSW, xr[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                Tacc dot = 0;
+#pragma unroll
+                for (int i = 0; i < KC; ++i) dot += wd[i] * xr[u][i];
+                const double res = (double)(rv[u] - dot);
+                acc += res * res;
+            }
+        }
+        for (; e2 < p1; e2 += G) {
             Tacc xr[KSW];
             load_row<Tacc, KSW>(other + (int64_t)a.idx[e2] * KSW, xr);
             Tacc dot = 0;
@@ -408,7 +501,7 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
             const double res = (double)((Tacc)val[e2] - dot);
             acc += res * res;
         }
-        for (int m = 1; m < Gw; m <<= 1) acc += __shfl_xor(acc, m);
+        acc = group_sum1(acc, Gw);
         double *slot = a.sse_col + 4 * (sd.self_off + n);
         if (!wide) {
             if (gl == 0) {
@@ -493,61 +586,80 @@ __device__ __forceinline__ double wave_bcast(double v, int src) {
 }
 
 // Factor A = L L^T and solve x = L^-T (L^-1 h + z) in registers, one matrix row
-// per lane (KP <= 64 lanes).  Step k of the right-looking factorisation
-// broadcasts the pivot and column k (v_readlane) and each lane updates its
-// own row; the forward solve keeps row ownership, the backward solve column
-// ownership (L transposed once through LDS).  In: sA (lower, KP x KP with
-// identity padding), sh = h, sz = z (zero beyond K), diag0 = diag(A).  Out:
-// sh = x.  Returns false when a pivot fails the test of chol_lds.  All 64
-// lanes call it.
+// per lane (KP <= 64 lanes).  Left-looking: step k forms
+// s_i = a_ik - sum_{p<k} l_ip l_kp in every lane i from its own finished row
+// entries and row k of L read from LDS by broadcast, takes the pivot from lane
+// k (v_readlane) and writes column k of L over column k of A.  Lanes run every
+// step (entries above their diagonal come out as unused values), so the steps
+// need no lane masks.  The forward solve keeps row ownership, the backward
+// solve reads columns of L from LDS.  Row loads are unconditional with selects:
+// per-element lane conditions would each keep an exec mask alive.  In: sA
+// (lower, KP x KP with identity padding), sh = h, sz = z (zero beyond K),
+// diag0 = diag(A).  Out: sh = x; sA holds L in its lower triangle.  Returns
+// false when a pivot fails the test of chol_lds.  All 64 lanes call it.
 template <int KP, typename T>
-__device__ bool factor_solve_regs(T *sA, int ld, T *sh, const T *sz, const T *diag0, T *sinv,
-                                  T theta, int K, int lane) {
+__device__ __forceinline__ bool factor_solve_regs(T *sA, int ld, T *sh, const T *sz,
+                                                  const T *diag0, T *sinv, T theta, int K, int lane) {
+    // an opaque lane index: the masks and LDS addresses derived from it would
+    // otherwise be hoisted out of the caller's item loop and all stay live
+    asm volatile("" : "+v"(lane));
+    // broadcast reads index from an opaque zero so that their constant part
+    // folds into the instruction's offset instead of a hoisted address register
+    int z0 = 0;
+    asm volatile("" : "+v"(z0));
     const bool own = lane < KP;
+    const int row = own ? lane : KP - 1;    // lanes without a row shadow the last one
     T r[KP];
-#pragma unroll
-    for (int j = 0; j < KP; ++j) r[j] = (own && j <= lane) ? sA[lane * ld + j] : (T)0;
     bool bad = false;
+    T myinv = (T)1;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
-        const T dk = wave_bcast(r[k], k);
-        bad = bad || (k < K && ((theta > (T)0) ? !(dk > theta * diag0[k]) : !(dk > (T)0)));
+        // two interleaved partial sums halve the dependent chain
+        T s0 = sA[row * ld + k], s1 = (T)0;
+#pragma unroll
+        for (int p = 0; p < k; ++p) {
+            if (p & 1) s1 -= r[p] * sA[z0 + k * ld + p];
+            else s0 -= r[p] * sA[z0 + k * ld + p];
+        }
+        const T sk = s0 + s1;
+        const T dk = wave_bcast(sk, k);
+        bad = bad || (k < K && ((theta > (T)0) ? !(dk > theta * diag0[z0 + k]) : !(dk > (T)0)));
         const T lkk = sqrt(dk > (T)0 ? dk : (T)1);
         const T inv = (T)1 / lkk;
-        if (lane == 0) sinv[k] = inv;
-        r[k] = (lane > k) ? r[k] * inv : (lane == k ? lkk : r[k]);
-#pragma unroll
-        for (int j = k + 1; j < KP; ++j) {
-            const T ljk = wave_bcast(r[k], j);
-            r[j] = (lane >= j) ? r[j] - r[k] * ljk : r[j];
-        }
+        myinv = lane == k ? inv : myinv;
+        r[k] = lane == k ? lkk : sk * inv;
+        if (own) sA[lane * ld + k] = r[k];
+        __builtin_amdgcn_wave_barrier();
+        // the entry is final: keep the compiler from recomputing it later
+        asm volatile("" : "+v"(r[k]));
     }
+    if (own) sinv[lane] = myinv;
     __syncthreads();
     // forward: y = L^-1 h, then v = y + z
-    T acc = own ? sh[lane] : (T)0;
+    T acc = sh[row];
     T y = (T)0;
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
-        const T yq = wave_bcast(acc, q) * sinv[q];
-        if (lane == q) y = yq;
+        const T yq = wave_bcast(acc, q) * sinv[z0 + q];
+        y = lane == q ? yq : y;
         acc = (lane > q) ? acc - r[q] * yq : acc;
     }
-    const T v = (lane < K) ? y + sz[lane] : (T)0;
+    const T v = (lane < K) ? y + sz[row] : (T)0;
     // L^T by columns: lane i takes column i of L
-#pragma unroll
-    for (int j = 0; j < KP; ++j)
-        if (own && j <= lane) sA[lane * ld + j] = r[j];
     __syncthreads();
     T c[KP];
 #pragma unroll
-    for (int q = 0; q < KP; ++q) c[q] = (own && q >= lane) ? sA[q * ld + lane] : (T)0;
+    for (int q = 0; q < KP; ++q) {
+        const T v2 = sA[q * ld + row];
+        c[q] = q >= lane ? v2 : (T)0;
+    }
     // backward: x = L^-T v
     acc = v;
     T x = (T)0;
 #pragma unroll
     for (int q = KP - 1; q >= 0; --q) {
-        const T xq = wave_bcast(acc, q) * sinv[q];
-        if (lane == q) x = xq;
+        const T xq = wave_bcast(acc, q) * sinv[z0 + q];
+        x = lane == q ? xq : x;
         acc = (lane < q) ? acc - c[q] * xq : acc;
     }
     __syncthreads();
@@ -629,8 +741,8 @@ __device__ __forceinline__ void mfma_gram(const uint16_t *other, int ks, const i
             }
         }
     }
-    hlo += __shfl_xor(hlo, 32);
-    hhi += __shfl_xor(hhi, 32);
+    hlo = bfly_step<32>(hlo);
+    hhi = bfly_step<32>(hhi);
 }
 
 // Store the accumulators of mfma_gram: lower blocks of G at dst[row * ld + col],
@@ -854,15 +966,18 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             __syncthreads();
             if (lane < KP) sz[lane] = lane < K ? (Tacc)elem_to_d(elem_from<Ts>((double)xv)) : (Tacc)0;
             __syncthreads();
+            // one entry per lane, its factor row in 16-byte loads (zero beyond K)
             double acc = 0.0;
             for (int64_t e2 = p0 + lane; e2 < p1; e2 += 64) {
-                const Tw *xr = other + (int64_t)a.idx[e2] * a.ks_other;
+                Tacc xr[KP];
+                load_row<Tacc, KP>(other + (int64_t)a.idx[e2] * a.ks_other, xr);
                 Tacc dot = 0;
-                for (int k = 0; k < K; ++k) dot += sz[k] * (Tacc)elem_to_d(xr[k]);
+#pragma unroll
+                for (int k = 0; k < KP; ++k) dot += sz[k] * xr[k];
                 const double res = (double)((Tacc)val[e2] - dot);
                 acc += res * res;
             }
-            for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m);
+            acc = group_sum1(acc, 64);
             if (lane < 4) a.sse_col[4 * (sd.self_off + n) + lane] = lane == 0 ? acc : 0.0;
         }
         __syncthreads();
@@ -903,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_sse(const SseArgs a) {
         const double res = (double)((Tacc)val[e] - dot);
         acc += res * res;
     }
-    for (int m = 1; m < Gw; m <<= 1) acc += __shfl_xor(acc, m);
+    acc = group_sum1(acc, Gw);
     double *slot = a.sse_col + 4 * (sd.self_off + n);
     if (!wide) {
         if (gl == 0) {
@@ -1498,19 +1613,25 @@ static inline int grid_for(int64_t work, int per, int cap) {
     return (int)g;
 }
 
-template <int KC>
-static hipError_t upd_reg_kc(int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {
+template <int KC, bool SSE>
+static hipError_t upd_reg_kc_sse(int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {
     switch (prec) {
     case kP64:
         // FP64 above K = 12 exceeds the register file; the wavefront kernel serves it
         if constexpr (KC > 12) return hipErrorInvalidValue;
-        else hipLaunchKernelGGL((k_update_reg<KC, kP64>), dim3(ntiles), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_update_reg<KC, kP64, SSE>), dim3(ntiles), dim3(256), 0, s, a);
         break;
-    case kP32: hipLaunchKernelGGL((k_update_reg<KC, kP32>), dim3(ntiles), dim3(256), 0, s, a); break;
-    case kPBF: hipLaunchKernelGGL((k_update_reg<KC, kPBF>), dim3(ntiles), dim3(256), 0, s, a); break;
+    case kP32: hipLaunchKernelGGL((k_update_reg<KC, kP32, SSE>), dim3(ntiles), dim3(256), 0, s, a); break;
+    case kPBF: hipLaunchKernelGGL((k_update_reg<KC, kPBF, SSE>), dim3(ntiles), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int KC>
+static hipError_t upd_reg_kc(int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {
+    return a.sse_col ? upd_reg_kc_sse<KC, true>(prec, a, ntiles, s)
+                     : upd_reg_kc_sse<KC, false>(prec, a, ntiles, s);
 }
 
 hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t ntiles, hipStream_t s) {

@@ -81,6 +81,66 @@ def test_single_step_heavy_columns(precision, K):
     assert np.array_equal(g.get_state(0)["W"], round_state(draw, precision))
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("lane_nnz", [1, 3, 8, 256])
+def test_single_step_every_lane_group_size(precision, lane_nnz):
+    """The register kernel gives an entity G = 1..256 lanes (G the power of two
+    at or above degree / lane_nnz): with lane_nnz = 1 the entities of this data
+    span every G, including groups of several wavefronts.  Rows, then columns,
+    then the tau draw from the per-column residual SSE, against the oracle."""
+    K = 10
+    print("case lanes", precision, lane_nnz, flush=True)
+    d = small_data(K, seed=70, N=2000, D=500, nnz=60000, empty_rows=3)
+    g, o = pair(d, K, precision, lane_nnz=lane_nnz)
+    g.pp_stage(1, 0)
+    o.begin_stage(1)
+    blk = o.blocks[0]
+    assert np.diff(blk["csc_ptr"]).max() > 256                # groups of 256 lanes at lane_nnz 1
+    st = random_state(np.random.default_rng(300 + lane_nnz), blk["R"], blk["C"], K)
+    load_state(g, o, 0, st)
+    for which, t in (("rows", 6), ("cols", 6)):
+        g.step(0, which, t)
+        if which == "rows":
+            o.update_rows(blk, t)
+        else:
+            o.update_cols(blk, t)
+        key = "X" if which == "rows" else "W"
+        draw = g.get_draw(0, 0 if which == "rows" else 1)
+        prior = blk["hx"][0] if which == "rows" else blk["hw"][0]
+        tr = cond_precision_trace(blk, which, K, blk["tau"], prior)
+        rel = rel_err_rows(draw, blk[key], tr, K)
+        print(which, "max rel", rel.max(), flush=True)
+        assert rel.max() <= TOL[precision]
+        assert np.array_equal(g.get_state(0)[key], round_state(draw, precision))
+        # the oracle continues from the library's state (identical values)
+        blk[key] = g.get_state(0)[key]
+    # tau from the per-column SSE kernel
+    g.step(0, "tau", 7)
+    o.tau_draw(blk, 7)
+    assert g.get_state(0)["tau"] == pytest.approx(blk["tau"], rel=1e-9 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("lane_nnz", [1, 256])
+def test_fp64_sweeps_every_lane_group_size(lane_nnz):
+    """Whole FP64 sweeps, where the column pass also sums the residuals of each
+    column for the tau draw (fused SSE), at every lane-group size."""
+    K = 10
+    print("case sweeps lanes", lane_nnz, flush=True)
+    d = small_data(K, seed=71, N=2000, D=500, nnz=60000, empty_rows=3)
+    g, o = pair(d, K, "fp64", lane_nnz=lane_nnz)
+    g.pp_stage(1, 0)
+    o.begin_stage(1)
+    blk = o.blocks[0]
+    st = random_state(np.random.default_rng(400 + lane_nnz), blk["R"], blk["C"], K, scale=0.3)
+    load_state(g, o, 0, st)
+    g.gibbs_sweep(3)
+    o.sweep(3)
+    s = g.get_state(0)
+    np.testing.assert_allclose(s["X"], blk["X"], rtol=1e-8, atol=1e-9)
+    np.testing.assert_allclose(s["W"], blk["W"], rtol=1e-8, atol=1e-9)
+    assert s["tau"] == pytest.approx(blk["tau"], rel=1e-9)
+
+
 @pytest.mark.parametrize("K", [2, 10, 33, 64])
 @pytest.mark.parametrize("side", ["hyper_x", "hyper_w"])
 def test_normal_wishart_draw(K, side):
