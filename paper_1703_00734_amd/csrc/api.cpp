@@ -49,7 +49,7 @@ struct Layout {
     int64_t vs = 0, ss = 0, sp = 0;  // value / state / sample element bytes
     // byte offsets
     int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, ord, X, W, hyper, tau, mu0,
-        W0inv, mm, agg_x, agg_w, sample, probe, sse_col, sse_final, stats_part, stats_final,
+        W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits,
         m_items, m_items2, m_stats, m_hyper, m_mmout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
         p_out, total;
@@ -126,6 +126,7 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.sample = take(L.sp * (int64_t)c.max_kept * L.Emax * L.ks_p);
     L.probe = take(L.sp * L.Emax * L.ks_p);
     L.sse_col = take(8 * 4 * L.E_c);
+    L.colsq = take(8 * L.E_c);
     L.sse_final = take(8 * L.nb);
     L.stats_part = take(8 * L.n_stats_cap * L.npair);
     L.stats_final = take(8 * 2 * L.nb * L.npair);
@@ -646,7 +647,10 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
     StageLists &S = c->S;
     const int32_t nbs = (int32_t)S.blocks.size();
     UpdArgs a = upd_args(c, rows, t, sample, use_ss);
-    if (sse && !rows) a.sse_col = c->dev<double>(L.sse_col);
+    if (sse && !rows) {
+        a.sse_col = c->dev<double>(L.sse_col);
+        a.colsq = c->dev<double>(L.colsq);
+    }
     bmf_status st;
     const int32_t kcls = rows ? kKRows : kKCols;
     // the fallback queue counters start every pass at zero: sweeps reset them in
@@ -1208,6 +1212,7 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     std::vector<double> vd;
     std::vector<float> vf;
     std::vector<int32_t> hord;
+    std::vector<double> colsq((size_t)L.E_c, 0.0);   // per column: sum of squared stored values
     for (int pass = 0; pass < 2; ++pass) {
         hptr.clear();
         hidx.clear();
@@ -1227,6 +1232,19 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
                 if (fp64) vd.push_back(r);
                 else vf.push_back((float)r);
             }
+            if (pass == 1) {
+                // per column, the sum of its squared values as stored (for the
+                // residual SSE of the column pass)
+                for (size_t d = 0; d + 1 < bp.size(); ++d) {
+                    double s = 0.0;
+                    for (int64_t q = bp[d]; q < bp[d + 1]; ++q) {
+                        const double r = (double)cfg->val[be[q]] - c->ybar;
+                        const double rs = fp64 ? r : (double)(float)r;
+                        s += rs * rs;
+                    }
+                    colsq[(size_t)(c->w_off[b] + (int64_t)d)] = s;
+                }
+            }
             std::vector<int32_t> o = degree_order(bp);
             hord.insert(hord.end(), o.begin(), o.end());
             base_nz += B.M;
@@ -1244,6 +1262,7 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
         if ((st = upload(c, L.ord + (pass == 0 ? 0 : 4 * L.E_r), hord.data(), hord.size() * 4))) return st;
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    if ((st = upload(c, L.colsq, colsq.data(), colsq.size() * 8))) return st;
     if ((st = upload(c, L.mu0, c->mu0.data(), 8 * K))) return st;
     if ((st = upload(c, L.W0inv, c->W0inv.data(), 8 * K * K))) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));

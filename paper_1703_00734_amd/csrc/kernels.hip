@@ -43,16 +43,19 @@ __device__ __forceinline__ float unif_f(uint32_t x) { return ((float)(x >> 9) + 
 __device__ __forceinline__ double unif_d(uint32_t x) { return ((double)(x >> 9) + 0.5) * 1.1920928955078125e-7; }
 
 // Four standard normals of counter (c0, c1, c2, g) by two Box-Muller transforms.
+// FP32: the hardware transcendentals (v_log_f32 is log2, v_sin_f32 / v_cos_f32
+// take the angle in turns, so 2 pi u needs no range reduction), each within a
+// few ulp.
 __device__ __forceinline__ void normals4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t g,
                                          uint32_t k0, uint32_t k1, float z[4]) {
     uint32_t o[4];
     philox4x32_10(c0, c1, c2, g, k0, k1, o);
-    const float r1 = sqrtf(-2.0f * logf(unif_f(o[0])));
-    const float r2 = sqrtf(-2.0f * logf(unif_f(o[2])));
-    float s1, co1, s2, co2;
-    sincosf(6.28318530717958647692f * unif_f(o[1]), &s1, &co1);
-    sincosf(6.28318530717958647692f * unif_f(o[3]), &s2, &co2);
-    z[0] = r1 * co1; z[1] = r1 * s1; z[2] = r2 * co2; z[3] = r2 * s2;
+    constexpr float kM2Ln2 = -1.38629436111989061883f;   // -2 ln 2
+    const float r1 = __builtin_amdgcn_sqrtf(kM2Ln2 * __builtin_amdgcn_logf(unif_f(o[0])));
+    const float r2 = __builtin_amdgcn_sqrtf(kM2Ln2 * __builtin_amdgcn_logf(unif_f(o[2])));
+    const float u1 = unif_f(o[1]), u3 = unif_f(o[3]);
+    z[0] = r1 * __builtin_amdgcn_cosf(u1); z[1] = r1 * __builtin_amdgcn_sinf(u1);
+    z[2] = r2 * __builtin_amdgcn_cosf(u3); z[3] = r2 * __builtin_amdgcn_sinf(u3);
 }
 __device__ __forceinline__ void normals4(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t g,
                                          uint32_t k0, uint32_t k1, double z[4]) {
@@ -244,6 +247,41 @@ __device__ __forceinline__ void store_row_bf16(uint16_t *p, const Tacc (&x)[KC],
     }
 }
 
+// The first NW dwords of a factor row (16-byte aligned) in as few loads as
+// possible, kept raw until the FMAs convert them: rows of a later pair can be
+// in flight while the current pair is used.
+template <int NW>
+__device__ __forceinline__ void load_raw(const void *p, uint32_t (&r)[NW]) {
+    const uint4 *q4 = reinterpret_cast<const uint4 *>(p);
+#pragma unroll
+    for (int v = 0; v < NW / 4; ++v) {
+        const uint4 u = q4[v];
+        r[4 * v] = u.x; r[4 * v + 1] = u.y; r[4 * v + 2] = u.z; r[4 * v + 3] = u.w;
+    }
+    constexpr int R = NW % 4, B = NW - R;
+    const uint32_t *q1 = reinterpret_cast<const uint32_t *>(p) + B;
+    if constexpr (R >= 2) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(q1);
+        r[B] = u.x; r[B + 1] = u.y;
+    }
+    if constexpr (R == 1 || R == 3) r[NW - 1] = q1[R - 1];
+}
+template <typename Tw> __host__ __device__ constexpr int raw_words(int kc) {
+    return (kc * (int)sizeof(Tw) + 3) / 4;
+}
+// Element k of a raw row as the arithmetic type.
+template <typename Tacc, typename Tw, int NW>
+__device__ __forceinline__ Tacc raw_elem(const uint32_t (&r)[NW], int k) {
+    if constexpr (sizeof(Tw) == 2) {
+        const uint32_t x = r[k >> 1];
+        return (Tacc)__uint_as_float((k & 1) ? (x & 0xFFFF0000u) : (x << 16));
+    } else if constexpr (sizeof(Tw) == 4) {
+        return (Tacc)__uint_as_float(r[k]);
+    } else {
+        return (Tacc)__hiloint2double((int)r[2 * k + 1], (int)r[2 * k]);
+    }
+}
+
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 
@@ -254,6 +292,17 @@ template <> __device__ __forceinline__ uint16_t elem_from<uint16_t>(double v) { 
 
 template <int KC, typename Tacc>
 __device__ __forceinline__ void store_row(uint16_t *p, const Tacc (&x)[KC], int K) { store_row_bf16<KC>(p, x, K); }
+
+// Pivot of a Cholesky step: l = sqrt(d) and 1 / l.  FP32 takes v_rsq_f32
+// (about 1 ulp); FP64 keeps the correctly rounded operations.
+__device__ __forceinline__ void pivot_of(float d, float &l, float &inv) {
+    inv = __builtin_amdgcn_rsqf(d);
+    l = d * inv;
+}
+__device__ __forceinline__ void pivot_of(double d, double &l, double &inv) {
+    l = sqrt(d);
+    inv = 1.0 / l;
+}
 
 // --------------------------------------------------------------------------
 // k_update_reg: K <= KC <= 16, G lanes per entity, Gram in registers.
@@ -301,48 +350,72 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
 #pragma unroll
     for (int i = 0; i < KC; ++i) hs[i] = 0;
 
-    // two entries per iteration: both gathers are in flight before the FMAs,
-    // and the next pair's indices and values are requested before them too
-    int64_t e = p0 + gl;
-    int dn0 = 0, dn1 = 0;
-    Tacc rn0 = 0, rn1 = 0;
-    if (e + G < p1) {
-        dn0 = a.idx[e]; dn1 = a.idx[e + G];
-        rn0 = (Tacc)val[e]; rn1 = (Tacc)val[e + G];
-    }
-    for (; e + G < p1; e += 2 * G) {
-        const int d0 = dn0, d1 = dn1;
-        const Tacc r0 = rn0, r1 = rn1;
-        Tacc w0[KSW], w1[KSW];
-        load_row<Tacc, KSW>(other + (int64_t)d0 * KSW, w0);
-        load_row<Tacc, KSW>(other + (int64_t)d1 * KSW, w1);
-        const int64_t en = e + 2 * G;
-        if (en + G < p1) {
-            dn0 = a.idx[en]; dn1 = a.idx[en + G];
-            rn0 = (Tacc)val[en]; rn1 = (Tacc)val[en + G];
-        }
+    // Pairs of entries (e, e + G): the factor rows of the next pair are
+    // requested before the FMAs of the current one, the indices and values two
+    // pairs ahead; the FMAs take the entries in order.
+    constexpr int NW = raw_words<Tw>(KC);
+    auto fma_entry = [&](const uint32_t (&wr)[NW], Tacc r) {
+        Tacc w[KC];
 #pragma unroll
-        for (int i = 0; i < KC; ++i) {
-            hs[i] += r0 * w0[i];
-            hs[i] += r1 * w1[i];
-#pragma unroll
-            for (int j = 0; j <= i; ++j) {
-                g[tri(i, j)] += w0[i] * w0[j];
-                g[tri(i, j)] += w1[i] * w1[j];
-            }
-        }
-    }
-    if (e < p1) {
-        const int d = a.idx[e];
-        const Tacc r = (Tacc)val[e];
-        Tacc w[KSW];
-        load_row<Tacc, KSW>(other + (int64_t)d * KSW, w);
+        for (int i = 0; i < KC; ++i) w[i] = raw_elem<Tacc, Tw, NW>(wr, i);
 #pragma unroll
         for (int i = 0; i < KC; ++i) {
             hs[i] += r * w[i];
 #pragma unroll
             for (int j = 0; j <= i; ++j) g[tri(i, j)] += w[i] * w[j];
         }
+    };
+    const int64_t step = 2 * (int64_t)G;
+    int64_t e = p0 + gl;
+    if constexpr (sizeof(Tw) < 8) {
+        uint32_t wa0[NW], wa1[NW];           // rows of the current pair
+        Tacc ra0 = 0, ra1 = 0;
+        int dn0 = 0, dn1 = 0;                // indices / values of the next pair
+        Tacc rn0 = 0, rn1 = 0;
+        if (e + G < p1) {
+            const int d0 = a.idx[e], d1 = a.idx[e + G];
+            ra0 = (Tacc)val[e]; ra1 = (Tacc)val[e + G];
+            load_raw<NW>(other + (int64_t)d0 * KSW, wa0);
+            load_raw<NW>(other + (int64_t)d1 * KSW, wa1);
+        }
+        if (e + step + G < p1) {
+            dn0 = a.idx[e + step]; dn1 = a.idx[e + step + G];
+            rn0 = (Tacc)val[e + step]; rn1 = (Tacc)val[e + step + G];
+        }
+        for (; e + G < p1; e += step) {
+            const int64_t en = e + step;
+            uint32_t wb0[NW], wb1[NW];
+            if (en + G < p1) {
+                load_raw<NW>(other + (int64_t)dn0 * KSW, wb0);
+                load_raw<NW>(other + (int64_t)dn1 * KSW, wb1);
+            }
+            const Tacc rb0 = rn0, rb1 = rn1;
+            if (en + step + G < p1) {
+                dn0 = a.idx[en + step]; dn1 = a.idx[en + step + G];
+                rn0 = (Tacc)val[en + step]; rn1 = (Tacc)val[en + step + G];
+            }
+            fma_entry(wa0, ra0);
+            fma_entry(wa1, ra1);
+#pragma unroll
+            for (int u = 0; u < NW; ++u) { wa0[u] = wb0[u]; wa1[u] = wb1[u]; }
+            ra0 = rb0; ra1 = rb1;
+        }
+    } else {
+        // FP64 rows: one pair in flight (the pipeline would cost occupancy)
+        for (; e + G < p1; e += step) {
+            uint32_t w0r[NW], w1r[NW];
+            const int d0 = a.idx[e], d1 = a.idx[e + G];
+            const Tacc r0 = (Tacc)val[e], r1 = (Tacc)val[e + G];
+            load_raw<NW>(other + (int64_t)d0 * KSW, w0r);
+            load_raw<NW>(other + (int64_t)d1 * KSW, w1r);
+            fma_entry(w0r, r0);
+            fma_entry(w1r, r1);
+        }
+    }
+    if (e < p1) {
+        uint32_t w1r[NW];
+        load_raw<NW>(other + (int64_t)a.idx[e] * KSW, w1r);
+        fma_entry(w1r, (Tacc)val[e]);
     }
     // butterfly inside the wave: every lane of the group ends with bitwise
     // identical sums
@@ -380,8 +453,13 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     // a packed row [P lower (row-major), P m, m]: the side's own row when
     // propagated, the shared Normal-Wishart prior otherwise
     const Tacc tau = (Tacc)(*sd.tau);
+    const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
+    Tacc hraw[SSE ? KC : 1];                // sum r w of the column, for its SSE
+    if constexpr (SSE) {
+#pragma unroll
+        for (int i = 0; i < KC; ++i) hraw[i] = hs[i];
+    }
     {
-        const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
         const double *eta = pr + K * (K + 1) / 2;
 #pragma unroll
         for (int i = 0; i < KC; ++i) {
@@ -403,9 +481,8 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
 #pragma unroll
         for (int p = 0; p < j; ++p) dj -= g[tri(j, p)] * g[tri(j, p)];
         ok = ok && (kFP32 ? (dj > theta * diag) : (dj > (Tacc)0));
-        dj = dj > (Tacc)0 ? dj : (Tacc)1;
-        const Tacc l = sqrt(dj);
-        const Tacc il = (Tacc)1 / l;
+        Tacc l, il;
+        pivot_of(dj > (Tacc)0 ? dj : (Tacc)1, l, il);
         g[tri(j, j)] = l;
         inv[j] = il;
 #pragma unroll
@@ -463,58 +540,37 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
         if (sample) store_row<KC>(reinterpret_cast<Tp *>(sample) + (sd.sample_off + n) * KSP, x, K);
     }
     if constexpr (SSE) {
-        // residual SSE of this column with the new w as stored: residuals in the
-        // pass's arithmetic, squares summed in FP64
-        Tacc wd[KC];
+        // Residual SSE of this column with the new w as stored, from the sums
+        // this pass already holds: sum_e (r_e - w.x_e)^2 = sum r^2 - 2 w.h_raw
+        // + w^T G_raw w, and tau w^T G_raw w = |L^T w|^2 - w^T P w since
+        // A = P + tau G_raw = L L^T.  Products and sums in FP64.
+        if (gl == 0) {
+            Tacc wd[KC];
 #pragma unroll
-        for (int i = 0; i < KC; ++i) wd[i] = i < K ? (Tacc)elem_to_d(elem_from<Ts>((double)x[i])) : (Tacc)0;
-        // four entries per iteration so that four gathers are in flight; the
-        // squares are added in entry order
-        double acc = 0.0;
-        int64_t e2 = p0 + gl;
-        for (; e2 + 3 * G < p1; e2 += 4 * G) {
-            int dd[4];
-            Tacc rv[4];
+            for (int i = 0; i < KC; ++i) wd[i] = i < K ? (Tacc)elem_to_d(elem_from<Ts>((double)x[i])) : (Tacc)0;
+            double hw = 0.0, lw2 = 0.0, pw = 0.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                dd[u] = a.idx[e2 + u * G];
-                rv[u] = (Tacc)val[e2 + u * G];
+            for (int i = 0; i < KC; ++i) {
+                hw += (double)hraw[i] * (double)wd[i];
+                double u = 0.0;
+#pragma unroll
+                for (int p = i; p < KC; ++p) u += (double)g[tri(p, i)] * (double)wd[p];
+                lw2 += u * u;
             }
-            Tacc xr[4][KSW];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) load_row<Tacc, KSW>(other + (int64_t)dd[u] * KSW, xr[u]);
+            for (int r = 0; r < KC; ++r) {
+                if (r < K) {
+                    double q = 0.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                Tacc dot = 0;
-#pragma unroll
-                for (int i = 0; i < KC; ++i) dot += wd[i] * xr[u][i];
-                const double res = (double)(rv[u] - dot);
-                acc += res * res;
+                    for (int c = 0; c < r; ++c) q += pr[tri(r, c)] * (double)wd[c];
+                    pw += (double)wd[r] * (2.0 * q + pr[tri(r, r)] * (double)wd[r]);
+                }
             }
-        }
-        for (; e2 < p1; e2 += G) {
-            Tacc xr[KSW];
-            load_row<Tacc, KSW>(other + (int64_t)a.idx[e2] * KSW, xr);
-            Tacc dot = 0;
-#pragma unroll
-            for (int i = 0; i < KC; ++i) dot += wd[i] * xr[i];
-            const double res = (double)((Tacc)val[e2] - dot);
-            acc += res * res;
-        }
-        acc = group_sum1(acc, Gw);
-        double *slot = a.sse_col + 4 * (sd.self_off + n);
-        if (!wide) {
-            if (gl == 0) {
-                slot[0] = acc;
-                slot[1] = 0.0;
-                slot[2] = 0.0;
-                slot[3] = 0.0;
-            }
-        } else if ((threadIdx.x & 63) == 0) {
-            const int wv = (threadIdx.x >> 6) - ((grp * G) >> 6);
-            slot[wv] = acc;
-            if (wv == 0)
-                for (int u = G >> 6; u < 4; ++u) slot[u] = 0.0;
+            double *slot = a.sse_col + 4 * (sd.self_off + n);
+            slot[0] = a.colsq[sd.self_off + n] - 2.0 * hw + (lw2 - pw) / (double)tau;
+            slot[1] = 0.0;
+            slot[2] = 0.0;
+            slot[3] = 0.0;
         }
     }
 }
@@ -585,56 +641,92 @@ __device__ __forceinline__ double wave_bcast(double v, int src) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Factor A = L L^T and solve x = L^-T (L^-1 h + z) in registers, one matrix row
-// per lane (KP <= 64 lanes).  Left-looking: step k forms
-// s_i = a_ik - sum_{p<k} l_ip l_kp in every lane i from its own finished row
-// entries and row k of L read from LDS by broadcast, takes the pivot from lane
-// k (v_readlane) and writes column k of L over column k of A.  Lanes run every
-// step (entries above their diagonal come out as unused values), so the steps
-// need no lane masks.  The forward solve keeps row ownership, the backward
-// solve reads columns of L from LDS.  Row loads are unconditional with selects:
-// per-element lane conditions would each keep an exec mask alive.  In: sA
-// (lower, KP x KP with identity padding), sh = h, sz = z (zero beyond K),
-// diag0 = diag(A).  Out: sh = x; sA holds L in its lower triangle.  Returns
-// false when a pivot fails the test of chol_lds.  All 64 lanes call it.
+// Left-looking Cholesky A = L L^T with one matrix row per lane (KP <= 64
+// lanes): step k forms s_i = a_ik - sum_{p<k} l_ip l_kp in every lane i from
+// its own finished row entries and row k of L, read from LDS by broadcast
+// 16-byte loads, takes the pivot from lane k (v_readlane) and writes l_ik to
+// sL (row stride ldl, a multiple of 16 bytes).  Lanes run every step (entries
+// above their diagonal come out as unused values), so the steps need no lane
+// masks.  In: sA (lower, row stride ld, KP x KP with identity padding; sL may
+// overlay sA: every row of A is read before the first write), diag0 = diag(A).
+// Out: r = the lane's row of L, sinv[i] = 1 / l_ii.  Returns false in every
+// lane when a pivot is not above theta times its diagonal entry (theta = 0:
+// not positive).  lane and z0 (0, a multiple of 16) come opaque from the
+// caller: values derived from them must not be hoisted out of its loops.
 template <int KP, typename T>
-__device__ __forceinline__ bool factor_solve_regs(T *sA, int ld, T *sh, const T *sz,
-                                                  const T *diag0, T *sinv, T theta, int K, int lane) {
-    // an opaque lane index: the masks and LDS addresses derived from it would
-    // otherwise be hoisted out of the caller's item loop and all stay live
-    asm volatile("" : "+v"(lane));
-    // broadcast reads index from an opaque zero so that their constant part
-    // folds into the instruction's offset instead of a hoisted address register
-    int z0 = 0;
-    asm volatile("" : "+v"(z0));
+__device__ __forceinline__ bool chol_rows(const T *sA, int ld, T *sL, int ldl, const T *diag0, T *sinv,
+                                          T theta, int lane, int z0, T (&r)[KP]) {
     const bool own = lane < KP;
     const int row = own ? lane : KP - 1;    // lanes without a row shadow the last one
-    T r[KP];
-    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        const T v = sA[row * ld + j];
+        r[j] = j <= lane ? v : (T)0;
+        asm volatile("" : "+v"(r[j]));      // select now, not at first use
+    }
+    const T d0 = diag0[row];
+    __syncthreads();                        // all of A read before L overlays it
+    int mybad = 0;
     T myinv = (T)1;
 #pragma unroll
     for (int k = 0; k < KP; ++k) {
         // two interleaved partial sums halve the dependent chain
-        T s0 = sA[row * ld + k], s1 = (T)0;
+        T s0 = r[k], s1 = (T)0;
+        const T *lk = sL + z0 + k * ldl;
 #pragma unroll
         for (int p = 0; p < k; ++p) {
-            if (p & 1) s1 -= r[p] * sA[z0 + k * ld + p];
-            else s0 -= r[p] * sA[z0 + k * ld + p];
+            if (p & 1) s1 -= r[p] * lk[p];
+            else s0 -= r[p] * lk[p];
+            // at most 16 broadcast values in flight (register pressure)
+            if ((p & 15) == 15) __builtin_amdgcn_sched_barrier(0);
         }
         const T sk = s0 + s1;
         const T dk = wave_bcast(sk, k);
-        bad = bad || (k < K && ((theta > (T)0) ? !(dk > theta * diag0[z0 + k]) : !(dk > (T)0)));
-        const T lkk = sqrt(dk > (T)0 ? dk : (T)1);
-        const T inv = (T)1 / lkk;
+        // pivot test in the pivot's own lane, against its own diagonal entry;
+        // padding steps see the identity: pivot 1 > theta, always passes
+        mybad = lane == k ? (int)!(sk > theta * d0) : mybad;
+        T lkk, inv;
+        pivot_of(dk > (T)0 ? dk : (T)1, lkk, inv);
         myinv = lane == k ? inv : myinv;
         r[k] = lane == k ? lkk : sk * inv;
-        if (own) sA[lane * ld + k] = r[k];
+        if (own) sL[lane * ldl + k] = r[k];
         __builtin_amdgcn_wave_barrier();
-        // the entry is final: keep the compiler from recomputing it later
-        asm volatile("" : "+v"(r[k]));
+        // the entry is final: keep the compiler from recomputing it later,
+        // and start the next step only after this one
+        asm volatile("" : "+v"(r[k]), "+v"(myinv), "+v"(mybad));
+        __builtin_amdgcn_sched_barrier(0);
     }
     if (own) sinv[lane] = myinv;
+    return __ballot(mybad) == 0;
+}
+
+// Factor A = L L^T and solve x = L^-T (L^-1 h + z) in registers (chol_rows,
+// then a forward solve with row ownership and a backward solve that reads
+// columns of L from LDS).  In: sA (lower, row stride ld, KP x KP with identity
+// padding), sh = h, sz = z (zero beyond K), diag0 = diag(A).  Out: sh = x, L
+// in sL.  Returns false when a pivot fails the test of chol_rows.  All 64
+// lanes call it.
+template <int KP, typename T>
+__device__ __forceinline__ bool factor_solve_regs(const T *sA, int ld, T *sL, int ldl, T *sh,
+                                                  const T *sz, const T *diag0, T *sinv, T theta,
+                                                  int K, int lane) {
+    // an opaque lane index: the masks and LDS addresses derived from it would
+    // otherwise be hoisted out of the caller's item loop and all stay live
+    asm volatile("" : "+v"(lane));
+    // broadcast reads index from an opaque zero (a multiple of 16 elements, so
+    // alignment is still known) so that their constant part folds into the
+    // instruction's offset instead of a hoisted address register
+    int z0 = 0;
+    asm volatile("" : "+v"(z0));
+    z0 &= ~15;
+    const bool own = lane < KP;
+    const int row = own ? lane : KP - 1;
+    T r[KP];
+    const bool ok = chol_rows<KP, T>(sA, ld, sL, ldl, diag0, sinv, theta, lane, z0, r);
     __syncthreads();
+    // each phase compares against a fresh opaque copy of the lane index, so
+    // that no lane mask is shared (and kept live) across phases
+    asm volatile("" : "+v"(lane));
     // forward: y = L^-1 h, then v = y + z
     T acc = sh[row];
     T y = (T)0;
@@ -645,14 +737,16 @@ __device__ __forceinline__ bool factor_solve_regs(T *sA, int ld, T *sh, const T 
         acc = (lane > q) ? acc - r[q] * yq : acc;
     }
     const T v = (lane < K) ? y + sz[row] : (T)0;
+    asm volatile("" : "+v"(lane));
     // L^T by columns: lane i takes column i of L
-    __syncthreads();
     T c[KP];
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
-        const T v2 = sA[q * ld + row];
+        const T v2 = sL[q * ldl + row];
         c[q] = q >= lane ? v2 : (T)0;
+        asm volatile("" : "+v"(c[q]));
     }
+    asm volatile("" : "+v"(lane));
     // backward: x = L^-T v
     acc = v;
     T x = (T)0;
@@ -665,7 +759,7 @@ __device__ __forceinline__ bool factor_solve_regs(T *sA, int ld, T *sh, const T 
     __syncthreads();
     if (own) sh[lane] = x;
     __syncthreads();
-    return !bad;
+    return ok;
 }
 
 __device__ __forceinline__ void unrank_tri(int q, int &r, int &c) {
@@ -795,19 +889,19 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     using Tp = typename PrecT<P>::p;
     constexpr int TL = KP / 8;
     constexpr int CH = 32;
-    constexpr int LD = KP + 1;
-    __shared__ Tacc sA[KP * LD];
+    constexpr int LD = KP + 1;                       // A: odd stride, conflict-free rows
+    constexpr int LDL = KP + 16 / (int)sizeof(Tacc); // L: 16-byte rows for broadcast loads
+    __shared__ __align__(16) Tacc sA[KP * LDL];
     __shared__ Tacc sw[MF ? 1 : CH * KP];
     __shared__ Tacc sr[MF ? 1 : CH];
     __shared__ Tacc sh[KP];
     __shared__ Tacc sz[KP];
     __shared__ Tacc sd0[KP];
     __shared__ Tacc sinv[KP];
+    __shared__ Tacc shraw[KP];                    // sum r w of the entity (column SSE)
 
-    const int lane = threadIdx.x;
     const int K = a.K;
     const int nitems = a.nitems_dev ? *a.nitems_dev : a.nitems;
-    const int ti = lane >> 3, tj = lane & 7;
     uint32_t t_sw = a.t;
     void *sample = a.sample;
     if (a.ss) {
@@ -818,6 +912,12 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     const Tv *val = reinterpret_cast<const Tv *>(a.val);
 
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        // an opaque lane index per item: lane-derived addresses and masks are
+        // recomputed for each item instead of being hoisted out of the loop
+        // and held in registers across all of it
+        int lane = threadIdx.x;
+        asm volatile("" : "+v"(lane));
+        const int ti = lane >> 3, tj = lane & 7;
         const int2 item = a.items[it];
         const SideDesc &sd = a.sides[item.x];
         const int n = item.y;
@@ -851,21 +951,43 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             const Tacc tau = (Tacc)(*sd.tau);
             const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
             const double *pv = pr + K * (K + 1) / 2;
-            // packed lower prior, lanes over consecutive entries (coalesced)
+            // packed lower prior, lanes over consecutive entries (coalesced), all
+            // loads issued before the first use.  Row of entry q: the floor of
+            // (sqrt(8q + 1) - 1) / 2, which is an integer at the start of a row
+            // and at least 2 / (2 row + 3) > 0.015 below the next integer
+            // elsewhere (row < 64), so an approximate square root plus 1e-3
+            // floors to the right row
             const int npk = K * (K + 1) / 2;
-            for (int q = lane; q < npk; q += 64) {
-                int ra = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
-                while (ra * (ra + 1) / 2 > q) --ra;
-                while ((ra + 1) * (ra + 2) / 2 <= q) ++ra;
-                const int cb = q - ra * (ra + 1) / 2;
-                sA[ra * LD + cb] = (Tacc)pr[q] + tau * sA[ra * LD + cb];
+            constexpr int NQ = (KP * (KP + 1) / 2 + 63) / 64;
+            constexpr int CQ = 8;                            // loads in flight per chunk
+#pragma unroll
+            for (int u0 = 0; u0 < NQ; u0 += CQ) {
+                double pq[CQ];
+#pragma unroll
+                for (int u = 0; u < CQ; ++u) {
+                    const int q = lane + 64 * (u0 + u);
+                    pq[u] = (u0 + u < NQ && q < npk) ? pr[q] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < CQ; ++u) {
+                    const int q = lane + 64 * (u0 + u);
+                    if (u0 + u < NQ && q < npk) {
+                        const int ra = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f + 1e-3f);
+                        const int cb = q - ra * (ra + 1) / 2;
+                        sA[ra * LD + cb] = (Tacc)pq[u] + tau * sA[ra * LD + cb];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
             }
             // identity padding rows K..KP-1
             for (int q = lane; q < (KP - K) * KP; q += 64) {
                 const int ra = K + q / KP, cb = q % KP;
                 if (cb <= ra) sA[ra * LD + cb] = (Tacc)(ra == cb);
             }
-            for (int q = lane; q < KP; q += 64) sh[q] = q < K ? (Tacc)pv[q] + tau * sh[q] : (Tacc)0;
+            for (int q = lane; q < KP; q += 64) {
+                shraw[q] = sh[q];
+                sh[q] = q < K ? (Tacc)pv[q] + tau * sh[q] : (Tacc)0;
+            }
         } else {
             Tacc acc[TL][TL];
             Tacc hacc[TL];
@@ -928,6 +1050,7 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     #pragma unroll
                 for (int i = 0; i < TL; ++i) {
                     const int ra = ti * TL + i;
+                    shraw[ra] = hacc[i];
                     sh[ra] = ra < K ? (Tacc)pv[ra] + tau * hacc[i] : (Tacc)0;
                 }
             }
@@ -943,7 +1066,7 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
         __syncthreads();
         if (lane < KP) sd0[lane] = sA[lane * LD + lane];
         __syncthreads();
-        const bool ok = factor_solve_regs<KP, Tacc>(sA, LD, sh, sz, sd0, sinv, (Tacc)a.theta, K, lane);
+        const bool ok = factor_solve_regs<KP, Tacc>(sA, LD, sA, LDL, sh, sz, sd0, sinv, (Tacc)a.theta, K, lane);
         if (!ok) {
             if (lane == 0) {
                 if (a.fb_list) {
@@ -962,23 +1085,30 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
         if (sample && lane < a.ks_sample)
             reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + lane] = (Tp)xv;
         if (a.sse_col) {
-            // residual SSE of this column with the new w as stored (FP64)
+            // Residual SSE of this column with the new w as stored, from the sums
+            // of this pass: sum r^2 - 2 w.h_raw + (|L^T w|^2 - w^T P w) / tau
+            // (A = P + tau G_raw = L L^T), in FP64.
             __syncthreads();
             if (lane < KP) sz[lane] = lane < K ? (Tacc)elem_to_d(elem_from<Ts>((double)xv)) : (Tacc)0;
             __syncthreads();
-            // one entry per lane, its factor row in 16-byte loads (zero beyond K)
+            const double tauv = (double)(Tacc)(*sd.tau);     // the tau that scaled A
             double acc = 0.0;
-            for (int64_t e2 = p0 + lane; e2 < p1; e2 += 64) {
-                Tacc xr[KP];
-                load_row<Tacc, KP>(other + (int64_t)a.idx[e2] * a.ks_other, xr);
-                Tacc dot = 0;
-#pragma unroll
-                for (int k = 0; k < KP; ++k) dot += sz[k] * xr[k];
-                const double res = (double)((Tacc)val[e2] - dot);
-                acc += res * res;
+            if (lane < KP) {
+                // (L^T w)_lane = sum_{p >= lane} L_p,lane w_p (L in sA, row stride LDL)
+                double u = 0.0;
+                for (int p = lane; p < KP; ++p) u += (double)sA[p * LDL + lane] * (double)sz[p];
+                acc = u * u - 2.0 * tauv * (double)shraw[lane] * (double)sz[lane];
+            }
+            // w^T P w over the packed prior (coalesced), off-diagonal entries twice
+            const double *prs = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
+            for (int q = lane; q < K * (K + 1) / 2; q += 64) {
+                const int ra = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f + 1e-3f);
+                const int cb = q - ra * (ra + 1) / 2;
+                acc -= (ra == cb ? 1.0 : 2.0) * prs[q] * (double)sz[ra] * (double)sz[cb];
             }
             acc = group_sum1(acc, 64);
-            if (lane < 4) a.sse_col[4 * (sd.self_off + n) + lane] = lane == 0 ? acc : 0.0;
+            if (lane < 4)
+                a.sse_col[4 * (sd.self_off + n) + lane] = lane == 0 ? a.colsq[sd.self_off + n] + acc / tauv : 0.0;
         }
         __syncthreads();
     }
@@ -1073,9 +1203,21 @@ __global__ __launch_bounds__(256) void k_stats(const StatsArgs a) {
     for (int r0 = 0; r0 < jb.count; r0 += sc) {
         const int nr = min(sc, jb.count - r0);
         __syncthreads();
-        for (int q = t; q < nr * K; q += 256) {
-            const int r = q / K, k = q - r * K;
-            xs[q] = elem_to_d(X[(int64_t)(jb.first + r0 + r) * a.ks + k]);
+        {
+            // all of this thread's loads in flight before the first store
+            constexpr int kPer = kLds / 256;
+            Ts v[kPer];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int q = t + 256 * u;
+                const int r = q / K, k = q - r * K;
+                v[u] = q < nr * K ? X[(int64_t)(jb.first + r0 + r) * a.ks + k] : Ts(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int q = t + 256 * u;
+                if (q < nr * K) xs[q] = elem_to_d(v[u]);
+            }
         }
         __syncthreads();
         if (active) {
@@ -1124,34 +1266,43 @@ __global__ __launch_bounds__(256) void k_stats(const StatsArgs a) {
 // 256)); each slice sums its q's in increasing order, slices are then added
 // in slice order.  Deterministic for a given (count, width).
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce(const ReduceJob *jobs) {
-    __shared__ double red[256];
+// Fixed-order reductions, one job per block: dst[p] = sum over q < count of
+// src[q * width + p].  Q threads per output (Q a power of two) each sum the
+// rows q = s, s + Q, ... with 8 loads in flight; the Q partials are combined
+// by a pairwise tree in LDS.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs) {
+    __shared__ double red[kReduceThreads];
     const ReduceJob jb = jobs[blockIdx.x];
     const int t = threadIdx.x;
-    const int E = jb.width < 256 ? jb.width : 256;
-    const int Q = 256 / E;
-    const int s = t / E;
+    const int E = jb.width < kReduceThreads ? jb.width : kReduceThreads;
+    int Q = 1;
+    while (2 * Q * E <= kReduceThreads) Q *= 2;
+    const int s = t / E, pe = t - s * E;
     for (int base = 0; base < jb.width; base += E) {
-        const int p = base + t % E;
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        const int p = base + pe;
+        double acc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] = 0.0;
         if (s < Q && p < jb.width) {
             int q = s;
-            for (; q + 3 * Q < jb.count; q += 4 * Q) {
-                acc0 += jb.src[(int64_t)q * jb.width + p];
-                acc1 += jb.src[(int64_t)(q + Q) * jb.width + p];
-                acc2 += jb.src[(int64_t)(q + 2 * Q) * jb.width + p];
-                acc3 += jb.src[(int64_t)(q + 3 * Q) * jb.width + p];
+            for (; q + 7 * Q < jb.count; q += 8 * Q) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = jb.src[(int64_t)(q + u * Q) * jb.width + p];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc[u] += v[u];
             }
-            for (; q < jb.count; q += Q) acc0 += jb.src[(int64_t)q * jb.width + p];
+            for (int u = 0; q < jb.count; q += Q, ++u) acc[u & 7] += jb.src[(int64_t)q * jb.width + p];
         }
         __syncthreads();
-        red[t] = (acc0 + acc1) + (acc2 + acc3);
-        __syncthreads();
-        if (t < E && p < jb.width) {
-            double v = 0.0;
-            for (int q = 0; q < Q; ++q) v += red[q * E + t];
-            jb.dst[p] = v;
+        if (s < Q) red[s * E + pe] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        for (int h = Q / 2; h > 0; h /= 2) {
+            __syncthreads();
+            if (s < h) red[s * E + pe] += red[(s + h) * E + pe];
         }
+        __syncthreads();
+        if (s == 0 && p < jb.width) jb.dst[p] = red[pe];
     }
 }
 
@@ -1165,15 +1316,15 @@ __global__ __launch_bounds__(256) void k_reduce(const ReduceJob *jobs) {
 //   A_kl ~ N(0,1)), Lambda = (T A)(T A)^T; mu = mu* + beta*^-1/2 C^-T z with
 //   C C^T = Lambda.  tau ~ Gamma(a0 + M/2, rate b0 + SSE/2).
 // --------------------------------------------------------------------------
+template <int KP>
 __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
-    constexpr int LD = 64;
-    __shared__ double M0[64 * LD];
-    __shared__ double M1[64 * LD];
-    __shared__ double M2[64 * LD];
-    __shared__ double sx[64], xbar[64], mus[64], zz[64];
-    __shared__ int flag;
+    constexpr int LD = KP + 2;                     // doubles; 16-byte rows, few bank conflicts
+    __shared__ __align__(16) double S0[KP * LD];   // W*^-1, then Lambda
+    __shared__ __align__(16) double S1[KP * LD];   // R, then C (rows of the factors)
+    __shared__ __align__(16) double S2[KP * LD];   // Bartlett A, then B = R^-T A
+    __shared__ double sx[KP], mus[KP], dg[KP], sinv[KP], zz[KP];
     const HyperJob jb = a.jobs[blockIdx.x];
-    const int lane = threadIdx.x;
+    int lane = threadIdx.x;
     const int K = a.K;
     const uint32_t t_sw = a.ss ? a.ss->t : a.t;
     if (jb.kind == 2) {
@@ -1185,55 +1336,59 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
         }
         return;
     }
+    asm volatile("" : "+v"(lane));
+    int z0 = 0;
+    asm volatile("" : "+v"(z0));
+    z0 &= ~15;
+    const bool own = lane < KP;
+    const int row = own ? lane : KP - 1;
     const uint32_t c2 = counter_word(jb.block, jb.kind == 0 ? kHyperX : kHyperW);
     const int npair = K + K * (K + 1) / 2;
-    // 1. the side's sums (reduced in fixed order by the statistics kernel)
+    // 1. the side's sums (reduced in fixed order by the statistics kernel) and
+    //    identity padding beyond K
+    for (int q = lane; q < KP * KP; q += 64) {
+        const int r = q / KP, c = q - r * KP;
+        S0[r * LD + c] = (double)(r == c);
+    }
+    __syncthreads();
     for (int p = lane; p < npair; p += 64) {
-        const double s = a.part[(int64_t)jb.part_begin * npair + p];
+        const double v = a.part[(int64_t)jb.part_begin * npair + p];
         if (p < K) {
-            sx[p] = s;
+            sx[p] = v;
         } else {
             int r, c;
             unrank_tri(p - K, r, c);
-            M0[r * LD + c] = s;
-            M0[c * LD + r] = s;
+            S0[r * LD + c] = v;
+            S0[c * LD + r] = v;
         }
     }
     __syncthreads();
     const double N = (double)jb.n;
     const double beta_s = a.beta0 + N, nu_s = a.nu0 + N;
-    if (lane < K) {
-        xbar[lane] = sx[lane] / N;
-        mus[lane] = (a.beta0 * a.mu0[lane] + sx[lane]) / beta_s;
-    }
-    __syncthreads();
-    // 2. W*^-1
+    if (lane < K) mus[lane] = (a.beta0 * a.mu0[lane] + sx[lane]) / beta_s;
+    // 2. W*^-1 = W0^-1 + (sum x x^T - N xbar xbar^T) + beta0 N / beta* (mu0 - xbar)(mu0 - xbar)^T
     const double coef = a.beta0 * N / beta_s;
     for (int q = lane; q < K * K; q += 64) {
         const int r = q / K, c = q - r * K;
-        const double ns = M0[r * LD + c] - N * xbar[r] * xbar[c];
-        M0[r * LD + c] = a.W0inv[r * K + c] + ns + coef * (a.mu0[r] - xbar[r]) * (a.mu0[c] - xbar[c]);
+        const double xr = sx[r] / N, xc = sx[c] / N;
+        const double ns = S0[r * LD + c] - N * xr * xc;
+        S0[r * LD + c] = a.W0inv[r * K + c] + ns + coef * (a.mu0[r] - xr) * (a.mu0[c] - xc);
     }
     __syncthreads();
-    // 3. R = chol(W*^-1)
-    bool ok = chol_lds<double>(M0, K, LD, 0.0, nullptr, lane, &flag);
-    // 4. M1 = R^-1 (lower), column c by lane c
-    for (int c = lane; c < K; c += 64) {
-        for (int i = 0; i < K; ++i) {
-            if (i < c) {
-                M1[i * LD + c] = 0.0;
-            } else {
-                double s = (i == c) ? 1.0 : 0.0;
-                for (int p = c; p < i; ++p) s -= M0[i * LD + p] * M1[p * LD + c];
-                M1[i * LD + c] = s / M0[i * LD + i];
-            }
-        }
+    if (own) dg[lane] = S0[lane * LD + lane];
+    __syncthreads();
+    // 3. R R^T = W*^-1 (rows of R in registers and in S1)
+    double rr[KP];
+    bool ok = chol_rows<KP, double>(S0, LD, S1, LD, dg, sinv, 0.0, lane, z0, rr);
+    // 4. Bartlett factor A (lower) in S2: A_kk^2 ~ chi2(nu* - k) for k < K,
+    //    A_kl ~ N(0, 1) below the diagonal, identity padding
+    for (int q = lane; q < KP * KP; q += 64) {
+        const int r = q / KP, c = q - r * KP;
+        S2[r * LD + c] = (r == c && r >= K) ? 1.0 : 0.0;
     }
-    // 5. Bartlett factor into M2
-    for (int q = lane; q < K * K; q += 64) M2[q / K * LD + q % K] = 0.0;
     __syncthreads();
     if (lane < K)
-        M2[lane * LD + lane] =
+        S2[lane * LD + lane] =
             sqrt(2.0 * gamma_draw(a.k0, a.k1, (uint32_t)(lane + 1), t_sw, c2, 0.5 * (nu_s - lane)));
     const int noff = K * (K - 1) / 2;
     for (int g = lane; 4 * g < noff; g += 64) {
@@ -1244,50 +1399,97 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
             if (q < noff) {
                 int r, cc;
                 unrank_tri(q, r, cc);          // strict lower, row-major: row r+1, column cc
-                M2[(r + 1) * LD + cc] = z[c];
+                S2[(r + 1) * LD + cc] = z[c];
             }
         }
     }
     __syncthreads();
-    // 6. B = T A with T[r][p] = M1[p][r] (p >= r) and A[p][c] = M2[p][c] (p >= c) -> M0
-    for (int q = lane; q < K * K; q += 64) {
-        const int r = q / K, c = q - r * K;
-        double s = 0.0;
-        for (int p = (r > c ? r : c); p < K; ++p) s += M1[p * LD + r] * M2[p * LD + c];
-        M0[r * LD + c] = s;
+    asm volatile("" : "+v"(lane));
+    // 5. B = R^-T A: lane c solves R^T b = (column c of A) from the bottom,
+    //    b_i = (a_ic - sum_{p>i} R_pi b_p) / R_ii, R_pi read by broadcast
+    {
+        double bb[KP];
+#pragma unroll
+        for (int i = KP - 1; i >= 0; --i) {
+            double s0 = S2[i * LD + row], s1 = 0.0;
+#pragma unroll
+            for (int p = i + 1; p < KP; ++p) {
+                if (p & 1) s1 -= S1[z0 + p * LD + i] * bb[p];
+                else s0 -= S1[z0 + p * LD + i] * bb[p];
+            }
+            bb[i] = (s0 + s1) * sinv[z0 + i];
+            asm volatile("" : "+v"(bb[i]));
+        }
+        __syncthreads();                        // every column of A read
+        if (own) {
+#pragma unroll
+            for (int i = 0; i < KP; ++i) S2[i * LD + lane] = bb[i];
+        }
     }
     __syncthreads();
-    // 7. Lambda = B B^T -> M1 and the output
+    asm volatile("" : "+v"(lane));
+    // 6. Lambda = B B^T: lane r takes row r of B and forms row r of Lambda
+    //    against every row of B read by broadcast
     double *outL = jb.out;
-    for (int q = lane; q < K * K; q += 64) {
-        const int r = q / K, c = q - r * K;
-        double s = 0.0;
-        for (int p = 0; p < K; ++p) s += M0[r * LD + p] * M0[c * LD + p];
-        M1[r * LD + c] = s;
-        M2[r * LD + c] = s;
-        outL[q] = s;
+    {
+        double br[KP];
+#pragma unroll
+        for (int c = 0; c < KP; ++c) br[c] = S2[row * LD + c];
+        __syncthreads();
+        for (int s = 0; s < KP; ++s) {
+            const double *bs = S2 + z0 + s * LD;
+            double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < KP; ++c) {
+                if (c & 1) a1 += br[c] * bs[c];
+                else a0 += br[c] * bs[c];
+            }
+            const double v = a0 + a1;
+            if (own) S0[lane * LD + s] = v;
+            if (lane < K && s < K) outL[lane * K + s] = v;
+        }
     }
     __syncthreads();
-    // 8. C = chol(Lambda) in M2; 9. mu = mu* + C^-T z / sqrt(beta*)
-    ok = chol_lds<double>(M2, K, LD, 0.0, nullptr, lane, &flag) && ok;
+    if (own) dg[lane] = S0[lane * LD + lane];
+    __syncthreads();
+    // 7. C C^T = Lambda (rows of C in S1); 8. mu = mu* + C^-T z / sqrt(beta*)
+    ok = chol_rows<KP, double>(S0, LD, S1, LD, dg, sinv, 0.0, lane, z0, rr) && ok;
     if (lane * 4 < K) {
         double z[4];
         normals4((uint32_t)(K + 1), t_sw, c2, (uint32_t)lane, a.k0, a.k1, z);
         for (int c = 0; c < 4; ++c)
             if (4 * lane + c < K) zz[4 * lane + c] = z[c];
     }
+    if (lane >= K && own) zz[lane] = 0.0;
     __syncthreads();
-    bwd_lds<double>(M2, K, LD, zz, lane);
-    if (lane < K) {
-        const double m = mus[lane] + zz[lane] / sqrt(beta_s);
-        sx[lane] = m;
-        outL[K * K + lane] = m;
+    asm volatile("" : "+v"(lane));
+    {
+        // backward solve with columns of C: lane i holds C_qi for q >= i
+        double cc[KP];
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const double v2 = S1[q * LD + row];
+            cc[q] = q >= lane ? v2 : 0.0;
+            asm volatile("" : "+v"(cc[q]));
+        }
+        double acc = zz[row], x = 0.0;
+#pragma unroll
+        for (int q = KP - 1; q >= 0; --q) {
+            const double xq = wave_bcast(acc, q) * sinv[z0 + q];
+            x = lane == q ? xq : x;
+            acc = (lane < q) ? acc - cc[q] * xq : acc;
+        }
+        if (lane < K) {
+            const double m = mus[lane] + x / sqrt(beta_s);
+            sx[lane] = m;
+            outL[K * K + lane] = m;
+        }
     }
     __syncthreads();
     double *packed = outL + K * K + 2 * K;      // [Lambda packed lower, Lambda mu, mu]
     if (lane < K) {
         double s = 0.0;
-        for (int c = 0; c < K; ++c) s += M1[lane * LD + c] * sx[c];
+        for (int c = 0; c < K; ++c) s += S0[lane * LD + c] * sx[c];
         outL[K * K + K + lane] = s;
         packed[K * (K + 1) / 2 + lane] = s;
         packed[K * (K + 1) / 2 + K + lane] = sx[lane];
@@ -1295,7 +1497,7 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
     for (int q = lane; q < K * (K + 1) / 2; q += 64) {
         int r, c;
         unrank_tri(q, r, c);
-        packed[q] = M1[r * LD + c];
+        packed[q] = S0[r * LD + c];
     }
     if (!ok && lane == 0) atomicAdd(a.nonpd, 1);
 }
@@ -1721,13 +1923,20 @@ hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStre
 
 hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(njobs), dim3(256), 0, s, jobs);
+    hipLaunchKernelGGL(k_reduce, dim3(njobs), dim3(kReduceThreads), 0, s, jobs);
     return hipGetLastError();
 }
 
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hyper, dim3(njobs), dim3(64), 0, s, a);
+    if (a.K <= 16)
+        hipLaunchKernelGGL(k_hyper<16>, dim3(njobs), dim3(64), 0, s, a);
+    else if (a.K <= 32)
+        hipLaunchKernelGGL(k_hyper<32>, dim3(njobs), dim3(64), 0, s, a);
+    else if (a.K <= 64)
+        hipLaunchKernelGGL(k_hyper<64>, dim3(njobs), dim3(64), 0, s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -51,6 +51,7 @@ struct UpdArgs {
     int32_t *fb_total;        // running count of rows sent to the fallback
     int32_t *nonpd;           // FP64 Cholesky failures
     double *sse_col;          // column pass: per column 4 slots of its SSE (null: skip)
+    const double *colsq;      // column pass: per column the sum of its squared values
     const int2 *splits;       // per item (first partial slot, count); count 0: not split
     const float *gpart;       // partial Grams + right-hand sides (KP*KP + KP floats each)
 };
