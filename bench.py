@@ -134,6 +134,7 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
         torch.cuda.synchronize()
         g.enable_timing(False)
         row_updates, ratings = g.stage_work()
+        print("bench: stage %d timed, %.4f ms per sweep" % (s, ms), file=sys.stderr, flush=True)
         per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
                             ktimes=g.kernel_times(), row_updates=row_updates, ratings=ratings,
                             schedule=g.schedule())
@@ -145,6 +146,8 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
         t0 = time.perf_counter()
         for s in stages_of(cfg):
             h.pp_stage(s, sweeps)
+            torch.cuda.synchronize()
+            print("bench: chain stage %d done" % s, file=sys.stderr, flush=True)
         p = h.predict(d["test_row"], d["test_col"])
         torch.cuda.synchronize()
         out["chain_wall_s"] = time.perf_counter() - t0
@@ -215,7 +218,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "copies": 5}))
         return
     cfg = dict(synth.CONFIGS[a.config])
-    d = synth.config(a.config, seed=a.seed)
+    say = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
+    say("drawing workload %d" % a.config)
+    d = synth.config(a.config, seed=a.seed, progress=say)
     K = d["K"]
     main_prec = "bf16" if cfg["precision"] in ("fp32", "bf16") else cfg["precision"]
     arms = {}

@@ -365,6 +365,28 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
             for (int j = 0; j <= i; ++j) g[tri(i, j)] += w[i] * w[j];
         }
     };
+    // BF16 rows: component i of the pair packed as (w0_i, w1_i) so that one
+    // v_dot2c_f32_bf16 adds w0_i w0_j + w1_i w1_j to the Gram (the products of
+    // BF16 values are exact in FP32); the right-hand side stays in FP32 FMAs.
+    auto fma_pair_bf16 = [&](const uint32_t (&w0)[NW], const uint32_t (&w1)[NW], Tacc r0, Tacc r1) {
+        typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+        uint32_t pk[2 * NW];
+#pragma unroll
+        for (int m = 0; m < NW; ++m) {
+            pk[2 * m] = __builtin_amdgcn_perm(w1[m], w0[m], 0x05040100u);
+            pk[2 * m + 1] = __builtin_amdgcn_perm(w1[m], w0[m], 0x07060302u);
+        }
+#pragma unroll
+        for (int i = 0; i < KC; ++i) {
+            hs[i] += r0 * raw_elem<Tacc, Tw, NW>(w0, i);
+            hs[i] += r1 * raw_elem<Tacc, Tw, NW>(w1, i);
+            const bf16x2_t pi = __builtin_bit_cast(bf16x2_t, pk[i]);
+#pragma unroll
+            for (int j = 0; j <= i; ++j)
+                g[tri(i, j)] = __builtin_amdgcn_fdot2_f32_bf16(pi, __builtin_bit_cast(bf16x2_t, pk[j]),
+                                                               g[tri(i, j)], false);
+        }
+    };
     const int64_t step = 2 * (int64_t)G;
     int64_t e = p0 + gl;
     if constexpr (sizeof(Tw) < 8) {
@@ -394,8 +416,12 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
                 dn0 = a.idx[en + step]; dn1 = a.idx[en + step + G];
                 rn0 = (Tacc)val[en + step]; rn1 = (Tacc)val[en + step + G];
             }
-            fma_entry(wa0, ra0);
-            fma_entry(wa1, ra1);
+            if constexpr (sizeof(Tw) == 2) {
+                fma_pair_bf16(wa0, wa1, ra0, ra1);
+            } else {
+                fma_entry(wa0, ra0);
+                fma_entry(wa1, ra1);
+            }
 #pragma unroll
             for (int u = 0; u < NW; ++u) { wa0[u] = wb0[u]; wa1[u] = wb1[u]; }
             ra0 = rb0; ra1 = rb1;
@@ -515,14 +541,34 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
         for (int p = 0; p < i; ++p) s -= g[tri(i, p)] * y[p];
         y[i] = s * inv[i];
     }
+    // noise: block q of four normals has counter word 3 = q.  A group with at
+    // least as many lanes as blocks (inside one wavefront) draws each block once
+    // and shares it; otherwise every lane draws every block.
+    const int NQ = (K + 3) / 4;
+    if (G >= NQ && G <= 64) {
+        Tacc zq[4];
+        normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)(gl < NQ ? gl : 0), a.k0, a.k1, zq);
+        const int base = (threadIdx.x & 63) & ~(G - 1);
 #pragma unroll
-    for (int q = 0; q < (KC + 3) / 4; ++q) {
-        if (4 * q < K) {
-            Tacc z[4];
-            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)q, a.k0, a.k1, z);
+        for (int q = 0; q < (KC + 3) / 4; ++q) {
+            if (q < NQ) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (4 * q + c < KC && 4 * q + c < K) y[4 * q + c < KC ? 4 * q + c : 0] += z[c];
+                for (int c = 0; c < 4; ++c) {
+                    const Tacc zc = __shfl(zq[c], base + q);
+                    if (4 * q + c < KC && 4 * q + c < K) y[4 * q + c < KC ? 4 * q + c : 0] += zc;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < (KC + 3) / 4; ++q) {
+            if (4 * q < K) {
+                Tacc z[4];
+                normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)q, a.k0, a.k1, z);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (4 * q + c < KC && 4 * q + c < K) y[4 * q + c < KC ? 4 * q + c : 0] += z[c];
+            }
         }
     }
     Tacc x[KC];
@@ -1166,99 +1212,10 @@ __global__ __launch_bounds__(256) void k_sse(const SseArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// k_stats: FP64 partial sums sum x and sum x x^T of one side (for the
-// Normal-Wishart draw).  A job covers a contiguous range of entities, staged
-// through LDS in sub-chunks; thread (pair p, slice s) sums its pair over its
-// slice of rows and slices are combined in order.  k_reduce then sums the
-// jobs of a side in job order.  Fixed order throughout: deterministic.
+// Normal-Wishart sufficient statistics: k_stats_mfma (below, with the
+// reductions) writes one partial per job; k_reduce sums the jobs of a side in
+// job order.  Fixed order throughout: deterministic.
 // --------------------------------------------------------------------------
-template <typename Ts>
-__global__ __launch_bounds__(256) void k_stats(const StatsArgs a) {
-    constexpr int kLds = 4096;                 // doubles of staged factors
-    constexpr int kMaxPairsPerThread = 9;      // ceil((64 + 64*65/2) / 256)
-    __shared__ double xs[kLds];
-    __shared__ double red[256 * 2];
-    __shared__ short pr_a[2144], pr_b[2144];
-    const StatsJob jb = a.jobs[blockIdx.x];
-    const SideDesc &sd = a.sides[jb.side];
-    const Ts *X = reinterpret_cast<const Ts *>(jb.side < a.nrow_sides ? a.X : a.W) + sd.self_off * a.ks;
-    const int K = a.K;
-    const int npair = K + K * (K + 1) / 2;
-    const int t = threadIdx.x;
-    for (int p = t; p < npair; p += 256) {
-        int ra, cb;
-        if (p < K) { ra = p; cb = -1; } else unrank_tri(p - K, ra, cb);
-        pr_a[p] = (short)ra;
-        pr_b[p] = (short)cb;
-    }
-    // thread layout: S slices of npair threads when npair <= 256
-    const int S = npair <= 256 ? 256 / npair : 1;
-    const int slice = npair <= 256 ? t / npair : 0;
-    const int p0 = npair <= 256 ? t % npair : t;
-    const bool active = slice < S;
-    double acc[kMaxPairsPerThread];
-#pragma unroll
-    for (int q = 0; q < kMaxPairsPerThread; ++q) acc[q] = 0.0;
-    const int sc = kLds / K;                   // rows per sub-chunk
-    for (int r0 = 0; r0 < jb.count; r0 += sc) {
-        const int nr = min(sc, jb.count - r0);
-        __syncthreads();
-        {
-            // all of this thread's loads in flight before the first store
-            constexpr int kPer = kLds / 256;
-            Ts v[kPer];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int q = t + 256 * u;
-                const int r = q / K, k = q - r * K;
-                v[u] = q < nr * K ? X[(int64_t)(jb.first + r0 + r) * a.ks + k] : Ts(0);
-            }
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int q = t + 256 * u;
-                if (q < nr * K) xs[q] = elem_to_d(v[u]);
-            }
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-            for (int q = 0; q < kMaxPairsPerThread; ++q) {
-                const int p = p0 + 256 * q;
-                if (p < npair && (npair <= 256 ? q == 0 : true)) {
-                    const int ra = pr_a[p], cb = pr_b[p];
-                    double s0 = 0.0, s1 = 0.0;
-                    int r = slice;
-                    for (; r + S < nr; r += 2 * S) {
-                        const double x0 = xs[r * K + ra], x1 = xs[(r + S) * K + ra];
-                        s0 += cb < 0 ? x0 : x0 * xs[r * K + cb];
-                        s1 += cb < 0 ? x1 : x1 * xs[(r + S) * K + cb];
-                    }
-                    if (r < nr) {
-                        const double x0 = xs[r * K + ra];
-                        s0 += cb < 0 ? x0 : x0 * xs[r * K + cb];
-                    }
-                    acc[q] += s0 + s1;
-                }
-            }
-        }
-    }
-    // combine slices in order, write the job partial
-    double *part = a.part + (int64_t)jb.part * npair;
-    if (npair <= 256) {
-        __syncthreads();
-        if (active) red[t] = acc[0];
-        __syncthreads();
-        if (t < npair) {
-            double s = 0.0;
-            for (int q = 0; q < S; ++q) s += red[q * npair + t];
-            part[t] = s;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < kMaxPairsPerThread; ++q)
-            if (p0 + 256 * q < npair) part[p0 + 256 * q] = acc[q];
-    }
-}
 
 // --------------------------------------------------------------------------
 // k_reduce: dst[p] = sum_{q < count} src[q * width + p], one workgroup per job.
@@ -1270,6 +1227,89 @@ __global__ __launch_bounds__(256) void k_stats(const StatsArgs a) {
 // src[q * width + p].  Q threads per output (Q a power of two) each sum the
 // rows q = s, s + Q, ... with 8 loads in flight; the Q partials are combined
 // by a pairwise tree in LDS.
+// Normal-Wishart sufficient statistics (sum x, sum x x^T) of one job's rows
+// on FP64 MFMA.  The block's WB wavefronts split the rows; a wavefront takes
+// them four at a time, lane l supplying component 16 b + l % 16 of row l / 16
+// as both operands of v_mfma_f64_16x16x4_f64, so that tile (I, J) accumulates
+// sum x_[16 I + i] x_[16 J + j] (lane l, register v: i = 4 v + l / 16,
+// j = l % 16); sum x accumulates beside it on the VALU.  The wavefronts' sums
+// are added in wavefront order through LDS: one partial per job.  Every
+// product and sum is exact FP64 arithmetic in a fixed order.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+template <typename Ts, int KB, int WB>
+__global__ __launch_bounds__(64 * WB) void k_stats_mfma(const StatsArgs a) {
+    constexpr int NT = KB * (KB + 1) / 2;
+    extern __shared__ double wsum[];                 // WB x npair
+    const StatsJob jb = a.jobs[blockIdx.x];
+    const SideDesc &sd = a.sides[jb.side];
+    const Ts *X = reinterpret_cast<const Ts *>(jb.side < a.nrow_sides ? a.X : a.W) + sd.self_off * a.ks;
+    const int K = a.K;
+    const int npair = K + K * (K + 1) / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int comp = lane & 15, rsub = lane >> 4;
+    f64x4_t acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    double sx[KB];
+#pragma unroll
+    for (int b = 0; b < KB; ++b) sx[b] = 0.0;
+    // this wavefront's rows: a contiguous range, a multiple of 4 long
+    const int per = ((jb.count + 4 * WB - 1) / (4 * WB)) * 4;
+    const int lo = wave * per, hi = min(jb.count, lo + per);
+    for (int r0 = lo; r0 < hi; r0 += 16) {
+        double v[4][KB];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + 4 * u + rsub;
+#pragma unroll
+            for (int b = 0; b < KB; ++b) {
+                const int k = 16 * b + comp;
+                v[u][b] = (r < hi && k < K) ? elem_to_d(X[(int64_t)(jb.first + r) * a.ks + k]) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            int t = 0;
+#pragma unroll
+            for (int I = 0; I < KB; ++I) {
+                sx[I] += v[u][I];
+#pragma unroll
+                for (int J = 0; J <= I; ++J, ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[u][I], v[u][J], acc[t], 0, 0, 0);
+            }
+        }
+    }
+    // sum x over the four row groups of the wavefront
+#pragma unroll
+    for (int b = 0; b < KB; ++b) sx[b] = bfly_step<32>(bfly_step<16>(sx[b]));
+    double *ws = wsum + wave * npair;
+    if (rsub == 0) {
+#pragma unroll
+        for (int b = 0; b < KB; ++b)
+            if (16 * b + comp < K) ws[16 * b + comp] = sx[b];
+    }
+    {
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < KB; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J, ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 4 * v + rsub, j = comp;
+                    const int ra = 16 * I + i, cb = 16 * J + j;
+                    if (ra < K && cb < K && (I > J || i >= j)) ws[K + ra * (ra + 1) / 2 + cb] = acc[t][v];
+                }
+    }
+    __syncthreads();
+    double *part = a.part + (int64_t)jb.part * npair;
+    for (int p = threadIdx.x; p < npair; p += 64 * WB) {
+        double s = 0.0;
+        for (int w = 0; w < WB; ++w) s += wsum[w * npair + p];
+        part[p] = s;
+    }
+}
+
 constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs) {
     __shared__ double red[kReduceThreads];
@@ -1910,15 +1950,25 @@ hipError_t launch_gram_part(int32_t kp, const GramPartArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename Ts, int KB, int WB>
+static void stats_mfma(const StatsArgs &a, int32_t njobs, hipStream_t s) {
+    const size_t lds = sizeof(double) * WB * (a.K + a.K * (a.K + 1) / 2);
+    hipLaunchKernelGGL((k_stats_mfma<Ts, KB, WB>), dim3(njobs), dim3(64 * WB), lds, s, a);
+}
+template <typename Ts>
+static hipError_t stats_ts(const StatsArgs &a, int32_t njobs, hipStream_t s) {
+    // wavefronts per block: the LDS holding their sums stays within 64 KB
+    if (a.K <= 16) stats_mfma<Ts, 1, 16>(a, njobs, s);
+    else if (a.K <= 32) stats_mfma<Ts, 2, 8>(a, njobs, s);
+    else if (a.K <= 64) stats_mfma<Ts, 4, 2>(a, njobs, s);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    if (prec == kP64)
-        hipLaunchKernelGGL(k_stats<double>, dim3(njobs), dim3(256), 0, s, a);
-    else if (prec == kPBF)
-        hipLaunchKernelGGL(k_stats<uint16_t>, dim3(njobs), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_stats<float>, dim3(njobs), dim3(256), 0, s, a);
-    return hipGetLastError();
+    if (prec == kP64) return stats_ts<double>(a, njobs, s);
+    if (prec == kPBF) return stats_ts<uint16_t>(a, njobs, s);
+    return stats_ts<float>(a, njobs, s);
 }
 
 hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s) {

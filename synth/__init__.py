@@ -62,7 +62,11 @@ def _dedupe(keys):
     return np.unique(keys)
 
 
-def ratings_cells(N, D, nnz, s, dmin, rng):
+def _quiet(msg):
+    pass
+
+
+def ratings_cells(N, D, nnz, s, dmin, rng, progress=_quiet):
     """Configuration-model cells with Zipf row/column degree targets."""
     nnz = min(int(nnz), N * D)
     dr = zipf_targets(N, nnz, s, dmin, D, rng)
@@ -72,6 +76,7 @@ def ratings_cells(N, D, nnz, s, dmin, rng):
     cs = np.repeat(np.arange(D, dtype=np.int64), dc)
     cs = cs[rng.permutation(cs.size)[:m]]
     keys = _dedupe(rs * D + cs)
+    progress("cells: configuration model paired, %d distinct" % keys.size)
     pr = dr / dr.sum()
     pc = dc / dc.sum()
     for _ in range(50):
@@ -81,6 +86,7 @@ def ratings_cells(N, D, nnz, s, dmin, rng):
         r = rng.choice(N, size=extra, p=pr)
         c = rng.choice(D, size=extra, p=pc)
         keys = _dedupe(np.concatenate([keys, r * D + c]))
+        progress("cells: topped up to %d distinct" % keys.size)
     if keys.size > nnz:
         keys = np.sort(keys[rng.permutation(keys.size)[:nnz]])
     # raise every row and column to dmin entries
@@ -101,6 +107,7 @@ def ratings_cells(N, D, nnz, s, dmin, rng):
             cc = np.repeat(need_c, dmin)
             add.append(rng.choice(N, size=cc.size, p=pr) * D + cc)
         keys = _dedupe(np.concatenate([keys] + add))
+        progress("cells: minimum degree pass, %d distinct" % keys.size)
     return keys // D, keys % D
 
 
@@ -117,8 +124,9 @@ def _dot_rows(X, W, row, col, chunk=1 << 22):
     return out
 
 
-def make(kind, N, D, K, nnz, noise, seed, zipf_s=1.2, dmin=5, train_frac=0.9, **_):
-    """Draw one workload.  Returns a dict with the COO train and test sets."""
+def make(kind, N, D, K, nnz, noise, seed, zipf_s=1.2, dmin=5, train_frac=0.9, progress=_quiet, **_):
+    """Draw one workload.  Returns a dict with the COO train and test sets.
+    `progress(msg)` is called after each phase of a large draw."""
     rng = _rng(seed)
     if kind == "uniform":
         row, col = uniform_cells(N, D, nnz, rng)
@@ -126,19 +134,20 @@ def make(kind, N, D, K, nnz, noise, seed, zipf_s=1.2, dmin=5, train_frac=0.9, **
         W = rng.standard_normal((D, K))
         y = _dot_rows(X, W, row, col) + noise * rng.standard_normal(row.size)
     elif kind == "ratings":
-        row, col = ratings_cells(N, D, nnz, zipf_s, dmin, rng)
+        row, col = ratings_cells(N, D, nnz, zipf_s, dmin, rng, progress)
         sd = K ** -0.25
         X = sd * rng.standard_normal((N, K))
         W = sd * rng.standard_normal((D, K))
         y = _dot_rows(X, W, row, col) + noise * rng.standard_normal(row.size) + 3.0
         y = np.rint(np.clip(y, 1.0, 5.0))
     elif kind == "gaussian":
-        row, col = ratings_cells(N, D, nnz, zipf_s, dmin, rng)
+        row, col = ratings_cells(N, D, nnz, zipf_s, dmin, rng, progress)
         X = rng.standard_normal((N, K))
         W = rng.standard_normal((D, K))
         y = K ** -0.5 * _dot_rows(X, W, row, col) + noise * rng.standard_normal(row.size)
     else:
         raise ValueError(kind)
+    progress("values drawn for %d cells" % row.size)
     perm = rng.permutation(row.size)
     ntr = int(round(train_frac * row.size))
     tr, te = np.sort(perm[:ntr]), np.sort(perm[ntr:])
@@ -149,7 +158,7 @@ def make(kind, N, D, K, nnz, noise, seed, zipf_s=1.2, dmin=5, train_frac=0.9, **
                 test_val=y[te].astype(np.float32))
 
 
-def config(cid, seed=1):
+def config(cid, seed=1, progress=_quiet):
     """Workload of one of the five benchmark configurations."""
     c = CONFIGS[cid]
-    return make(c["kind"], c["N"], c["D"], c["K"], c["nnz"], c["noise"], seed)
+    return make(c["kind"], c["N"], c["D"], c["K"], c["nnz"], c["noise"], seed, progress=progress)
