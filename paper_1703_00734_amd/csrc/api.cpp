@@ -30,7 +30,8 @@ constexpr int32_t kFallbackGrid = 128;      // workgroups of the FP64 redo pass
 constexpr int64_t kSegNnz = 2048;           // MFMA path: entities with more entries are split
 constexpr int32_t kWaveGridCap = 1 << 20;
 
-enum Counter { kFbRow = 0, kFbCol = 1, kFbTotal = 2, kNonPD = 3, kRidged = 4, kCorr = 5, kNumCounters = 16 };
+enum Counter { kFbRow = 0, kFbCol = 1, kFbTotal = 2, kNonPD = 3, kRidged = 4, kCorr = 5, kHyperDone = 6,
+               kNumCounters = 16 };
 
 // Kernel classes for the optional per-launch timing.
 enum KClass { kKRows = 0, kKCols, kKGram, kKFallback, kKSse, kKStats, kKReduce, kKHyper, kKInit, kKMM, kKAgg, kKPredict, kKFill, kNumK };
@@ -767,7 +768,7 @@ static bmf_status run_sse(bmf_ctx *c, int32_t k) {
     return reduce_sse(c, k);
 }
 
-static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi) {
+static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi, bool reduce = true) {
     const Layout &L = c->L;
     StageLists &S = c->S;
     const int32_t nbs = (int32_t)S.blocks.size();
@@ -786,11 +787,12 @@ static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi) {
         const int32_t n = (int32_t)(hi - lo);
         if ((st = timed(c, kKStats, [&] { return launch_stats(c->prec(), a, n, c->ls); }))) return st;
     }
+    if (!reduce) return BMF_OK;
     const ReduceJob *rj = c->dev<ReduceJob>(L.m_reduce) + nbs + side_lo;
     return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->ls); });
 }
 
-static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool use_ss) {
+static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool use_ss, bool advance = false) {
     if (j1 <= j0) return BMF_OK;
     const Layout &L = c->L;
     HyperArgs a{};
@@ -809,6 +811,11 @@ static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool
     a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
     a.k1 = (uint32_t)(c->cfg.seed >> 32);
     a.nonpd = c->dev<int32_t>(L.counters) + kNonPD;
+    if (advance) {
+        a.advance = c->dev<SweepState>(L.sweep);
+        a.fb_counts = c->dev<int32_t>(L.counters) + kFbRow;
+        a.done = c->dev<int32_t>(L.counters) + kHyperDone;
+    }
     return timed(c, kKHyper, [&] { return launch_hyper(a, j1 - j0, c->ls); });
 }
 
@@ -818,21 +825,27 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
     StageLists &S = c->S;
     bmf_status st;
     const int32_t nbs = (int32_t)S.blocks.size();
-    const int32_t nblk = c->cfg.batched ? 1 : nbs;
-    for (int32_t q = 0; q < nblk; ++q) {
-        const int32_t k = c->cfg.batched ? -1 : q;
-        if ((st = run_pass(c, true, 0, nullptr, k, true))) return st;
-        if ((st = run_pass(c, false, 0, nullptr, k, true, c->cfg.sample_tau != 0))) return st;
-        if (c->cfg.sample_tau && (st = reduce_sse(c, k))) return st;
-        if (k < 0) {
-            if ((st = run_stats(c, 0, 2 * nbs))) return st;
-        } else {
+    const bool tau = c->cfg.sample_tau != 0;
+    if (c->cfg.batched) {
+        // one launch per step; the SSE and statistics reductions share a launch
+        // (their jobs are contiguous), and the hyperparameter launch advances
+        // the sweep state in its last block
+        if ((st = run_pass(c, true, 0, nullptr, -1, true))) return st;
+        if ((st = run_pass(c, false, 0, nullptr, -1, true, tau))) return st;
+        if ((st = run_stats(c, 0, 2 * nbs, false))) return st;
+        const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce) + (tau ? 0 : nbs);
+        const int32_t nr = (tau ? nbs : 0) + 2 * nbs;
+        if ((st = timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->ls); }))) return st;
+        if (S.hyper_begin[nbs] > 0) return run_hyper(c, 0, S.hyper_begin[nbs], 0, true, true);
+    } else {
+        for (int32_t k = 0; k < nbs; ++k) {
+            if ((st = run_pass(c, true, 0, nullptr, k, true))) return st;
+            if ((st = run_pass(c, false, 0, nullptr, k, true, tau))) return st;
+            if (tau && (st = reduce_sse(c, k))) return st;
             if ((st = run_stats(c, k, k + 1))) return st;
             if ((st = run_stats(c, nbs + k, nbs + k + 1))) return st;
+            if ((st = run_hyper(c, S.hyper_begin[k], S.hyper_begin[k + 1], 0, true))) return st;
         }
-        const int32_t j0 = k < 0 ? 0 : S.hyper_begin[k];
-        const int32_t j1 = k < 0 ? S.hyper_begin[nbs] : S.hyper_begin[k + 1];
-        if ((st = run_hyper(c, j0, j1, 0, true))) return st;
     }
     SweepState *ss = c->dev<SweepState>(c->L.sweep);
     int32_t *fbc = c->dev<int32_t>(c->L.counters) + kFbRow;

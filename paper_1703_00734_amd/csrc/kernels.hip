@@ -93,6 +93,19 @@ __device__ double gamma_draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1,
     return d * boost;
 }
 
+// End of a sweep: the fallback queues of the row and column passes start
+// empty, the sweep index moves on, and the next sweep's sample slot (or none).
+__device__ __forceinline__ void sweep_advance(SweepState *ss, int32_t *fb_counts) {
+    fb_counts[0] = 0;
+    fb_counts[1] = 0;
+    SweepState s = *ss;
+    if (s.slot >= 0) s.kept += 1;
+    s.t += 1;
+    const bool keep = (int64_t)s.t >= s.burnin && ((int64_t)s.t - s.burnin) % s.thin == 0 && s.kept < s.max_kept;
+    s.slot = keep ? s.kept : -1;
+    *ss = s;
+}
+
 // --------------------------------------------------------------------------
 // butterfly sums inside a wavefront without the LDS crossbar
 // --------------------------------------------------------------------------
@@ -390,41 +403,57 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     const int64_t step = 2 * (int64_t)G;
     int64_t e = p0 + gl;
     if constexpr (sizeof(Tw) < 8) {
-        uint32_t wa0[NW], wa1[NW];           // rows of the current pair
-        Tacc ra0 = 0, ra1 = 0;
-        int dn0 = 0, dn1 = 0;                // indices / values of the next pair
-        Tacc rn0 = 0, rn1 = 0;
-        if (e + G < p1) {
-            const int d0 = a.idx[e], d1 = a.idx[e + G];
-            ra0 = (Tacc)val[e]; ra1 = (Tacc)val[e + G];
-            load_raw<NW>(other + (int64_t)d0 * KSW, wa0);
-            load_raw<NW>(other + (int64_t)d1 * KSW, wa1);
-        }
-        if (e + step + G < p1) {
-            dn0 = a.idx[e + step]; dn1 = a.idx[e + step + G];
-            rn0 = (Tacc)val[e + step]; rn1 = (Tacc)val[e + step + G];
-        }
-        for (; e + G < p1; e += step) {
-            const int64_t en = e + step;
-            uint32_t wb0[NW], wb1[NW];
-            if (en + G < p1) {
-                load_raw<NW>(other + (int64_t)dn0 * KSW, wb0);
-                load_raw<NW>(other + (int64_t)dn1 * KSW, wb1);
-            }
-            const Tacc rb0 = rn0, rb1 = rn1;
-            if (en + step + G < p1) {
-                dn0 = a.idx[en + step]; dn1 = a.idx[en + step + G];
-                rn0 = (Tacc)val[en + step]; rn1 = (Tacc)val[en + step + G];
-            }
-            if constexpr (sizeof(Tw) == 2) {
-                fma_pair_bf16(wa0, wa1, ra0, ra1);
-            } else {
-                fma_entry(wa0, ra0);
-                fma_entry(wa1, ra1);
-            }
+        // Four entries per lane per iteration (e, e + G, e + 2G, e + 3G).  Every
+        // load is unconditional (addresses clamped to the entity's last entry;
+        // entries past the end are masked where the rows are consumed), and
+        // the next batch's indices and values are loaded into the registers
+        // this batch has finished with: no loaded register is copied or
+        // selected before use, so the loads stay in flight across iterations
+        // instead of forcing a wait on each one.
+        constexpr int B = 4;
+        const int64_t last = p1 - 1;
+        int dq[B];
+        Tacc rq[B];
 #pragma unroll
-            for (int u = 0; u < NW; ++u) { wa0[u] = wb0[u]; wa1[u] = wb1[u]; }
-            ra0 = rb0; ra1 = rb1;
+        for (int u = 0; u < B; ++u) {
+            const int64_t eu = min(e + u * (int64_t)G, last);
+            dq[u] = p1 > p0 ? a.idx[eu] : 0;
+            rq[u] = p1 > p0 ? (Tacc)val[eu] : (Tacc)0;
+        }
+        for (; e < p1; e += B * (int64_t)G) {
+            Tacc rc[B];
+            bool ok[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                ok[u] = e + u * (int64_t)G < p1;
+                rc[u] = ok[u] ? rq[u] : (Tacc)0;
+            }
+            // issue order: this batch's rows, then the next batch's indices and
+            // values; one wait (for the rows only) before the arithmetic
+            uint32_t w[B][NW];
+#pragma unroll
+            for (int u = 0; u < B; ++u) load_raw<NW>(other + (int64_t)dq[u] * KSW, w[u]);
+            const int64_t en = e + B * (int64_t)G;
+#pragma unroll
+            for (int u = 0; u < B; ++u) dq[u] = a.idx[min(en + u * (int64_t)G, last)];
+#pragma unroll
+            for (int u = 0; u < B; ++u) rq[u] = (Tacc)val[min(en + u * (int64_t)G, last)];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+#pragma unroll
+                for (int v = 0; v < NW; ++v) asm volatile("" : "+v"(w[u][v]));
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+#pragma unroll
+                for (int v = 0; v < NW; ++v) w[u][v] = ok[u] ? w[u][v] : 0u;
+            if constexpr (sizeof(Tw) == 2) {
+                fma_pair_bf16(w[0], w[1], rc[0], rc[1]);
+                fma_pair_bf16(w[2], w[3], rc[2], rc[3]);
+            } else {
+#pragma unroll
+                for (int u = 0; u < B; ++u) fma_entry(w[u], rc[u]);
+            }
         }
     } else {
         // FP64 rows: one pair in flight (the pipeline would cost occupancy)
@@ -1356,26 +1385,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs
 //   A_kl ~ N(0,1)), Lambda = (T A)(T A)^T; mu = mu* + beta*^-1/2 C^-T z with
 //   C C^T = Lambda.  tau ~ Gamma(a0 + M/2, rate b0 + SSE/2).
 // --------------------------------------------------------------------------
+// Normal-Wishart draw of one side of one block (one wavefront).
 template <int KP>
-__global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
+__device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, uint32_t t_sw, int lane) {
     constexpr int LD = KP + 2;                     // doubles; 16-byte rows, few bank conflicts
     __shared__ __align__(16) double S0[KP * LD];   // W*^-1, then Lambda
     __shared__ __align__(16) double S1[KP * LD];   // R, then C (rows of the factors)
     __shared__ __align__(16) double S2[KP * LD];   // Bartlett A, then B = R^-T A
     __shared__ double sx[KP], mus[KP], dg[KP], sinv[KP], zz[KP];
-    const HyperJob jb = a.jobs[blockIdx.x];
-    int lane = threadIdx.x;
     const int K = a.K;
-    const uint32_t t_sw = a.ss ? a.ss->t : a.t;
-    if (jb.kind == 2) {
-        if (lane == 0) {
-            const double s = a.sse_part[jb.part_begin];
-            const double shape = a.a0 + 0.5 * (double)jb.n;
-            const double rate = a.b0 + 0.5 * s;
-            *jb.out = gamma_draw(a.k0, a.k1, 0u, t_sw, counter_word(jb.block, kTau), shape) / rate;
-        }
-        return;
-    }
     asm volatile("" : "+v"(lane));
     int z0 = 0;
     asm volatile("" : "+v"(z0));
@@ -1540,6 +1558,36 @@ __global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
         packed[q] = S0[r * LD + c];
     }
     if (!ok && lane == 0) atomicAdd(a.nonpd, 1);
+}
+
+template <int KP>
+__global__ __launch_bounds__(64) void k_hyper(const HyperArgs a) {
+    const HyperJob jb = a.jobs[blockIdx.x];
+    const int lane = threadIdx.x;
+    const uint32_t t_sw = a.ss ? a.ss->t : a.t;
+    if (jb.kind == 2) {
+        if (lane == 0) {
+            const double s = a.sse_part[jb.part_begin];
+            const double shape = a.a0 + 0.5 * (double)jb.n;
+            const double rate = a.b0 + 0.5 * s;
+            *jb.out = gamma_draw(a.k0, a.k1, 0u, t_sw, counter_word(jb.block, kTau), shape) / rate;
+        }
+    } else {
+        nw_draw<KP>(a, jb, t_sw, lane);
+    }
+    if (a.advance) {
+        // the last block to finish (every block has read the sweep index)
+        // advances the sweep state and clears the counter for the next launch
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            if (atomicAdd(a.done, 1) == (int)gridDim.x - 1) {
+                __threadfence();
+                sweep_advance(a.advance, a.fb_counts);
+                *a.done = 0;
+            }
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1818,14 +1866,7 @@ __global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
 // t >= burnin, (t - burnin) % thin == 0 and the store is not full).
 __global__ void k_advance(SweepState *ss, int32_t *fb_counts) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    fb_counts[0] = 0;   // fallback queues of the row and column passes
-    fb_counts[1] = 0;
-    SweepState s = *ss;
-    if (s.slot >= 0) s.kept += 1;
-    s.t += 1;
-    const bool keep = (int64_t)s.t >= s.burnin && ((int64_t)s.t - s.burnin) % s.thin == 0 && s.kept < s.max_kept;
-    s.slot = keep ? s.kept : -1;
-    *ss = s;
+    sweep_advance(ss, fb_counts);
 }
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {

@@ -115,6 +115,10 @@ struct HyperArgs {
     uint32_t t, k0, k1;
     const SweepState *ss;     // when set, t comes from here
     int32_t *nonpd;
+    // when set, the last block to finish advances the sweep state (as k_advance)
+    SweepState *advance;
+    int32_t *fb_counts;       // the fallback queue counters it resets
+    int32_t *done;            // completion counter of the launch (zero between launches)
 };
 
 struct InitArgs {

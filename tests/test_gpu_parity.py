@@ -314,3 +314,28 @@ def test_chain_rmse_matches_oracle(precision, K):
         g.close()
     print("rmse gpu", rg, "oracle", ro)
     assert abs(np.mean(rg) - np.mean(ro)) <= 0.005 * np.mean(ro)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_pp_chain_rmse_matches_oracle(precision):
+    """Posterior propagation on a 2 x 2 partition (stages 1-3 under propagated
+    priors, moment matching, Algorithm 2 aggregation, prediction): test RMSE
+    within 0.5 % of the oracle's PP chains (mean of 3 seeds)."""
+    import synth
+    K = 10
+    d = synth.make("ratings", 3000, 1500, K, 300000, 0.8, 6)
+    rg, ro = [], []
+    for seed in (201, 202, 203):
+        g, o = pair(d, K, precision, I=2, J=2, order="random", seed=seed, burnin=15, max_kept=25)
+        for s in (1, 2, 3):
+            g.pp_stage(s, 40)
+            o.run_stage(s, 40)
+        pg = g.predict(d["test_row"], d["test_col"])
+        o.aggregate()
+        po = o.predict(d["test_row"], d["test_col"])
+        rg.append(np.sqrt(np.mean((pg - d["test_val"]) ** 2)))
+        ro.append(np.sqrt(np.mean((po - d["test_val"]) ** 2)))
+        assert g.stats()["nonpd_rows"] == 0
+        g.close()
+    print("pp rmse gpu", rg, "oracle", ro)
+    assert abs(np.mean(rg) - np.mean(ro)) <= 0.005 * np.mean(ro)
