@@ -113,9 +113,14 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
                    precision=precision, batched=batched)
 
     stream = torch.cuda.current_stream()
-    g = ctx(0, warmup + 2 * steps)
+    # moment matching needs more kept samples than the rank: stages that feed a
+    # next stage top up their samples with untimed sweeps
+    need = 2 * d["K"] + 2
+    extra = max(0, need - (warmup + 2 * steps))
+    g = ctx(0, warmup + 2 * steps + extra)
     per_stage = {}
-    for s in stages_of(cfg):
+    stages = stages_of(cfg)
+    for s in stages:
         g.pp_stage(s, 0)
         g.gibbs_sweep(warmup)
         torch.cuda.synchronize()
@@ -135,6 +140,9 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
         g.enable_timing(False)
         row_updates, ratings = g.stage_work()
         print("bench: stage %d timed, %.4f ms per sweep" % (s, ms), file=sys.stderr, flush=True)
+        if s != stages[-1] and extra:
+            g.gibbs_sweep(extra)
+            torch.cuda.synchronize()
         per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
                             ktimes=g.kernel_times(), row_updates=row_updates, ratings=ratings,
                             schedule=g.schedule())

@@ -146,7 +146,10 @@ bmf_status bmf_gibbs_sweep(bmf_ctx *c, int32_t nsweeps);
  * block (i, 0)), the W side iff i > 0 (from block (0, j)); a propagated side
  * takes no Normal-Wishart draw.  Stages must be begun in order (else
  * BMF_ESTATE); a stage with no blocks (stage 3 when I = 1 or J = 1) returns
- * BMF_OK and does nothing. */
+ * BMF_OK and does nothing.  Moment matching needs at least 2 kept samples and,
+ * for a well-conditioned prior, more than K of them: with S <= K the sample
+ * covariance is singular, every row is ridged (counted in bmf_get_stats) and
+ * the propagated prior is nearly degenerate in the missing directions. */
 bmf_status bmf_pp_stage(bmf_ctx *c, int32_t stage, int32_t nsweeps);
 
 /* Predict n entries (row[q], col[q]) (host, original ids) into out (host):

@@ -854,61 +854,81 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 
+// LDS staging of mfma_gram: the rows of one chunk of 32 entries (16-byte
+// aligned rows of KP + 8 elements) and the chunk's 32 values.
+template <int KP> __host__ __device__ constexpr int gram_stage_bytes() { return 2 * 32 * (KP + 8) + 4 * 32; }
+
 // MFMA Gram and right-hand side of the observed entries [b0, b1) of one
 // entity (BF16 factors of stride ks): on return, accumulator v of lane l holds
 // G[8 (v / 4) + 4 (l / 32) + v % 4][l % 32] of the blocks G00 (c00), G10
 // (c10) and G11 (c11) (KP = 64), and hlo / hhi the lane's partial h[l % 32] /
 // h[32 + l % 32] (add lanes l and l ^ 32).
+// Chunks of 32 entries go through LDS: the rows are loaded in 16-byte pieces
+// (KP / 8 lanes per row, so a few wide loads per lane instead of one 2-byte
+// load per element), entries past the end are staged as zero rows, and each
+// lane then reads its MFMA operand (component l % 32 of 8 entries) from LDS.
+// The next chunk's indices are loaded before this chunk's arithmetic; loads
+// are unconditional (addresses clamped to the last entry).
 template <int KP>
 __device__ __forceinline__ void mfma_gram(const uint16_t *other, int ks, const int32_t *idx,
                                           const float *val, int64_t b0, int64_t b1, int lane,
-                                          f32x16_t &c00, f32x16_t &c10, f32x16_t &c11, float &hlo,
-                                          float &hhi) {
+                                          uint16_t *stage, f32x16_t &c00, f32x16_t &c10,
+                                          f32x16_t &c11, float &hlo, float &hhi) {
+    constexpr int LDR = KP + 8;             // staged row stride (elements)
+    constexpr int LPR = KP / 8;             // lanes per row, one 16-byte piece each
+    constexpr int RPI = 64 / LPR;           // rows per load instruction
+    constexpr int NLD = 32 / RPI;           // load instructions per chunk
+    float *sval = reinterpret_cast<float *>(stage + 32 * LDR);
     const int col = lane & 31;
     const int kg = (lane >> 5) * 8;
-    // two chunks of 16 entries per iteration: all index loads, then all factor
-    // loads, then the MFMAs, so both chunks' gathers are in flight together
+    const int rsub = lane / LPR, piece = lane - rsub * LPR;
+    const int64_t last = b1 > b0 ? b1 - 1 : b0;
+    int dq[NLD];
+#pragma unroll
+    for (int t = 0; t < NLD; ++t) dq[t] = b1 > b0 ? idx[min(b0 + rsub + RPI * t, last)] : 0;
     for (int64_t c0 = b0; c0 < b1; c0 += 32) {
-        int32_t d[2][8];
-        float rr[2][8];
+        uint4 rw[NLD];
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int t = 0; t < NLD; ++t)
+            rw[t] = *reinterpret_cast<const uint4 *>(other + (int64_t)dq[t] * ks + 8 * piece);
+        const float vv = val[min(c0 + col, last)];
+        const int64_t cn = c0 + 32;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t e = c0 + 16 * u + kg + j;
-                const bool ok = e < b1;
-                d[u][j] = ok ? idx[e] : -1;
-                rr[u][j] = ok ? val[e] : 0.0f;
-            }
-        u16x8_t lo[2], hi[2];
+        for (int t = 0; t < NLD; ++t) dq[t] = idx[min(cn + rsub + RPI * t, last)];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                unsigned short vlo = 0, vhi = 0;
-                if (d[u][j] >= 0) {
-                    const uint16_t *row = other + (int64_t)d[u][j] * ks;
-                    vlo = row[col];
-                    if constexpr (KP == 64) vhi = row[32 + col];
-                }
-                lo[u][j] = vlo;
-                hi[u][j] = vhi;
-            }
+        for (int t = 0; t < NLD; ++t) {
+            const int r = rsub + RPI * t;
+            const uint4 v = c0 + r < b1 ? rw[t] : make_uint4(0u, 0u, 0u, 0u);
+            *reinterpret_cast<uint4 *>(stage + r * LDR + 8 * piece) = v;
+        }
+        if (lane < 32) sval[lane] = c0 + lane < b1 ? vv : 0.0f;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
+            u16x8_t lo, hi;
+            float rr[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                hlo += rr[u][j] * bf16_to_f32(lo[u][j]);
-                if constexpr (KP == 64) hhi += rr[u][j] * bf16_to_f32(hi[u][j]);
+                const int r = 16 * u + kg + j;
+                lo[j] = stage[r * LDR + col];
+                if constexpr (KP == 64) hi[j] = stage[r * LDR + 32 + col];
+                rr[j] = sval[r];
             }
-            const bf16x8_t blo = __builtin_bit_cast(bf16x8_t, lo[u]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                hlo += rr[j] * bf16_to_f32(lo[j]);
+                if constexpr (KP == 64) hhi += rr[j] * bf16_to_f32(hi[j]);
+            }
+            const bf16x8_t blo = __builtin_bit_cast(bf16x8_t, lo);
             c00 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(blo, blo, c00, 0, 0, 0);
             if constexpr (KP == 64) {
-                const bf16x8_t bhi = __builtin_bit_cast(bf16x8_t, hi[u]);
+                const bf16x8_t bhi = __builtin_bit_cast(bf16x8_t, hi);
                 c10 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, blo, c10, 0, 0, 0);
                 c11 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bhi, bhi, c11, 0, 0, 0);
             }
         }
+        __builtin_amdgcn_wave_barrier();
     }
     hlo = bfly_step<32>(hlo);
     hhi = bfly_step<32>(hhi);
@@ -942,10 +962,11 @@ __global__ __launch_bounds__(64) void k_gram_part(const GramPartArgs a) {
     const SegItem sg = a.segs[blockIdx.x];
     const SideDesc &sd = a.sides[sg.side];
     const uint16_t *other = reinterpret_cast<const uint16_t *>(a.other) + sd.other_off * a.ks_other;
+    __shared__ __align__(16) uint16_t stage[gram_stage_bytes<KP>() / 2];
     f32x16_t c00 = {}, c10 = {}, c11 = {};
     float hlo = 0.0f, hhi = 0.0f;
     mfma_gram<KP>(other, a.ks_other, a.idx, reinterpret_cast<const float *>(a.val), sg.begin, sg.end,
-                  threadIdx.x, c00, c10, c11, hlo, hhi);
+                  threadIdx.x, stage, c00, c10, c11, hlo, hhi);
     float *dst = a.gpart + (int64_t)sg.slot * (KP * KP + KP);
     store_gram<KP, float>(dst, KP, dst + KP * KP, threadIdx.x, c00, c10, c11, hlo, hhi);
 }
@@ -1018,8 +1039,12 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             } else {
                 f32x16_t c00 = {}, c10 = {}, c11 = {};
                 float hlo = 0.0f, hhi = 0.0f;
+                // the Gram's LDS is free until store_gram: it stages the chunks
+                static_assert(gram_stage_bytes<KP>() <= (int)sizeof(Tacc) * KP * LDL, "stage fits sA");
                 mfma_gram<KP>(reinterpret_cast<const uint16_t *>(other), a.ks_other, a.idx,
-                              reinterpret_cast<const float *>(val), p0, p1, lane, c00, c10, c11, hlo, hhi);
+                              reinterpret_cast<const float *>(val), p0, p1, lane,
+                              reinterpret_cast<uint16_t *>(sA), c00, c10, c11, hlo, hhi);
+                __builtin_amdgcn_wave_barrier();
                 store_gram<KP, Tacc>(sA, LD, sh, lane, c00, c10, c11, hlo, hhi);
             }
             __syncthreads();
