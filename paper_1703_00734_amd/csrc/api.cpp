@@ -742,7 +742,7 @@ static bmf_status reduce_sse(bmf_ctx *c, int32_t k) {
     const int32_t nbs = (int32_t)c->S.blocks.size();
     const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce) + (k < 0 ? 0 : k);
     const int32_t nr = k < 0 ? nbs : 1;
-    return timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->ls); });
+    return timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->L.npair, c->ls); });
 }
 
 // Residual SSE of stage block k's columns on their own (a tau step).
@@ -789,7 +789,7 @@ static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi, bool r
     }
     if (!reduce) return BMF_OK;
     const ReduceJob *rj = c->dev<ReduceJob>(L.m_reduce) + nbs + side_lo;
-    return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->ls); });
+    return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->L.npair, c->ls); });
 }
 
 static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool use_ss, bool advance = false) {
@@ -835,7 +835,7 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
         if ((st = run_stats(c, 0, 2 * nbs, false))) return st;
         const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce) + (tau ? 0 : nbs);
         const int32_t nr = (tau ? nbs : 0) + 2 * nbs;
-        if ((st = timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->ls); }))) return st;
+        if ((st = timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->L.npair, c->ls); }))) return st;
         if (S.hyper_begin[nbs] > 0) return run_hyper(c, 0, S.hyper_begin[nbs], 0, true, true);
     } else {
         for (int32_t k = 0; k < nbs; ++k) {

@@ -1365,20 +1365,24 @@ __global__ __launch_bounds__(64 * WB) void k_stats_mfma(const StatsArgs a) {
 }
 
 constexpr int kReduceThreads = 1024;
+constexpr int kReduceSlice = 256;           // outputs per block at most (blockIdx.y: slice)
 __global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs) {
     __shared__ double red[kReduceThreads];
     const ReduceJob jb = jobs[blockIdx.x];
     const int t = threadIdx.x;
-    const int E = jb.width < kReduceThreads ? jb.width : kReduceThreads;
+    const int lo = blockIdx.y * kReduceSlice;
+    if (lo >= jb.width) return;             // uniform per block
+    const int hi = min(jb.width, lo + kReduceSlice);
+    const int E = hi - lo;
     int Q = 1;
     while (2 * Q * E <= kReduceThreads) Q *= 2;
     const int s = t / E, pe = t - s * E;
-    for (int base = 0; base < jb.width; base += E) {
+    for (int base = lo; base < hi; base += E) {
         const int p = base + pe;
         double acc[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-        if (s < Q && p < jb.width) {
+        if (s < Q && p < hi) {
             int q = s;
             for (; q + 7 * Q < jb.count; q += 8 * Q) {
                 double v[8];
@@ -1396,7 +1400,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs
             if (s < h) red[s * E + pe] += red[(s + h) * E + pe];
         }
         __syncthreads();
-        if (s == 0 && p < jb.width) jb.dst[p] = red[pe];
+        if (s == 0 && p < hi) jb.dst[p] = red[pe];
     }
 }
 
@@ -1746,58 +1750,138 @@ __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// k_agg: Algorithm 2 for one row of a row (or column) block (FP64).
+// k_agg: Algorithm 2 for one row of a row (or column) block (FP64), one
+// wavefront per row.
 // --------------------------------------------------------------------------
-// Smallest eigenvalue of the symmetric K x K matrix in A (destroyed), cyclic
-// Jacobi rotations (Golub & Van Loan, Sec. 8.5), single lane.
-__device__ double jacobi_min_eig(double *A, int K, int ld) {
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int p = 0; p < K; ++p)
-            for (int q = 0; q < K; ++q) {
-                const double v = A[p * ld + q] * A[p * ld + q];
-                tot += v;
-                if (p != q) off += v;
-            }
-        if (off <= 1e-30 * tot) break;
-        for (int p = 0; p < K - 1; ++p) {
-            for (int q = p + 1; q < K; ++q) {
-                const double apq = A[p * ld + q];
-                if (apq == 0.0) continue;
-                const double th = (A[q * ld + q] - A[p * ld + p]) / (2.0 * apq);
-                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-                const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-                for (int k = 0; k < K; ++k) {
-                    const double akp = A[k * ld + p], akq = A[k * ld + q];
-                    A[k * ld + p] = c * akp - s * akq;
-                    A[k * ld + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < K; ++k) {
-                    const double apk = A[p * ld + k], aqk = A[q * ld + k];
-                    A[p * ld + k] = c * apk - s * aqk;
-                    A[q * ld + k] = s * apk + c * aqk;
-                }
-            }
+// Smallest eigenvalue of the symmetric K x K matrix in S (full, row stride ld,
+// destroyed) by cyclic Jacobi rotations (Golub & Van Loan, Sec. 8.5) in the
+// parallel ordering of Brent & Luk: a sweep is n - 1 rounds of n/2 rotations
+// on disjoint index pairs (n = K rounded up to even; an odd K gets one dummy
+// index with zero coupling, which no rotation touches).  Rotations on disjoint
+// pairs commute and do not change each other's 2 x 2 blocks, so a round equals
+// applying its rotations one after another.  All 64 lanes call it; S needs
+// n rows and columns; sc holds n/2 (c, s) pairs, sp n/2 index pairs.
+template <int KP>
+__device__ double wave_min_eig(double *S, int K, int ld, int lane, double *sc, int *sp) {
+    const int n = K + (K & 1);
+    if (K & 1) {
+        for (int q = lane; q < n; q += 64) {
+            S[K * ld + q] = 0.0;
+            S[q * ld + K] = 0.0;
         }
     }
-    double m = A[0];
-    for (int k = 1; k < K; ++k) m = fmin(m, A[k * ld + k]);
+    __syncthreads();
+    const int half = n / 2;
+    // lane's first (pair, index) item of the half * n updates of a phase, and
+    // the step to its next one (64 items on)
+    const int m0 = lane / n, k0 = lane - m0 * n, dm = 64 / n, dk = 64 - dm * n;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int q = lane; q < K * K; q += 64) {
+            const int r = q / K, c = q - r * K;
+            const double v = S[r * ld + c] * S[r * ld + c];
+            tot += v;
+            if (r != c) off += v;
+        }
+        off = group_sum1(off, 64);
+        tot = group_sum1(tot, 64);
+        if (off <= 1e-30 * tot) break;
+        for (int rd = 0; rd < n - 1; ++rd) {
+            if (lane < half) {
+                int p, q;
+                if (lane == 0) {
+                    p = rd;
+                    q = n - 1;
+                } else {
+                    p = (rd + lane) % (n - 1);
+                    q = (rd - lane + n - 1) % (n - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                const double apq = S[p * ld + q];
+                double c = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    const double th = (S[q * ld + q] - S[p * ld + p]) / (2.0 * apq);
+                    const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sn = t * c;
+                }
+                sc[2 * lane] = c;
+                sc[2 * lane + 1] = sn;
+                sp[2 * lane] = p;
+                sp[2 * lane + 1] = q;
+            }
+            __syncthreads();
+            // columns p, q of every row
+            for (int m = m0, k = k0; m < half;) {
+                const int p = sp[2 * m], q = sp[2 * m + 1];
+                const double c = sc[2 * m], sn = sc[2 * m + 1];
+                const double akp = S[k * ld + p], akq = S[k * ld + q];
+                S[k * ld + p] = c * akp - sn * akq;
+                S[k * ld + q] = sn * akp + c * akq;
+                m += dm;
+                k += dk;
+                if (k >= n) {
+                    k -= n;
+                    ++m;
+                }
+            }
+            __syncthreads();
+            // rows p, q of every column
+            for (int m = m0, k = k0; m < half;) {
+                const int p = sp[2 * m], q = sp[2 * m + 1];
+                const double c = sc[2 * m], sn = sc[2 * m + 1];
+                const double apk = S[p * ld + k], aqk = S[q * ld + k];
+                S[p * ld + k] = c * apk - sn * aqk;
+                S[q * ld + k] = sn * apk + c * aqk;
+                m += dm;
+                k += dk;
+                if (k >= n) {
+                    k -= n;
+                    ++m;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    double m = S[0];
+    for (int k = 1; k < K; ++k) m = fmin(m, S[k * ld + k]);
+    __syncthreads();
     return m;
 }
 
+// Entry (r, c) of a packed lower-triangular row-major symmetric matrix.
+__device__ __forceinline__ double packed_sym(const double *P, int r, int c) {
+    return r >= c ? P[tri(r, c)] : P[tri(c, r)];
+}
+
+// Algorithm 2 for one row: Lambda* = (2 - J) Lambda_b + sum_j Lambda~_j and
+// Lambda* mu* = (2 - J) Lambda_b mu_b + sum_j Lambda~_j mu_j, where
+// Lambda~_j = Lambda_j when Lambda_j - Lambda_b is positive definite and
+// (Lambda_j - Lambda_b) + (|lambda_min| + eps) I + Lambda_b otherwise,
+// eps = 1e-6 tr(Lambda_b) / K.  The rows (packed [Lambda, Lambda mu, mu]) are
+// read from global memory; the positive-definiteness test is a register
+// Cholesky with a zero pivot threshold.
+template <int KP>
 __global__ __launch_bounds__(64) void k_agg(const AggArgs a) {
-    constexpr int LD = 64;
-    __shared__ double Lb[64 * LD];
-    __shared__ double Ls[64 * LD];
-    __shared__ double Dm[64 * LD];
-    __shared__ double Wm[64 * LD];
-    __shared__ double mub[64], rhs[64];
-    __shared__ double lmin;
-    __shared__ int flag;
-    const int lane = threadIdx.x;
+    constexpr int LD = KP + 2;                     // doubles; 16-byte rows
+    __shared__ __align__(16) double sLb[KP * LD];  // Lambda_b (full)
+    __shared__ __align__(16) double sA[KP * LD];   // D_j, its factor, Jacobi scratch
+    __shared__ __align__(16) double sS[KP * LD];   // Lambda* (lower, identity padding)
+    __shared__ double mub[KP], rhs[KP], dg[KP], sinv[KP], zero[KP], sc[KP];
+    __shared__ int sp[KP];
+    int lane = threadIdx.x;
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
+    const bool own = lane < KP;
     for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        asm volatile("" : "+v"(lane));
+        int z0 = 0;
+        asm volatile("" : "+v"(z0));
+        z0 &= ~15;
         const int2 item = a.items[it];
         const AggJob &jb = a.jobs[item.x];
         const int n = item.y;
@@ -1807,67 +1891,75 @@ __global__ __launch_bounds__(64) void k_agg(const AggArgs a) {
             if (lane < K) out[lane] = brow[kk2 + K + lane];
             continue;
         }
-        for (int q = lane; q < kk2; q += 64) {
-            int r, c;
-            unrank_tri(q, r, c);
-            Lb[r * LD + c] = brow[q];
-            Lb[c * LD + r] = brow[q];
+        for (int q = lane; q < KP * KP; q += 64) {
+            const int r = q / KP, c = q - r * KP;
+            sLb[r * LD + c] = (r < K && c < K) ? packed_sym(brow, r, c) : 0.0;
         }
-        if (lane < K) mub[lane] = brow[kk2 + K + lane];
+        if (own) {
+            mub[lane] = lane < K ? brow[kk2 + K + lane] : 0.0;
+            zero[lane] = 0.0;
+        }
         __syncthreads();
-        const double cb = 2.0 - (double)(jb.nsib + 1);
-        for (int q = lane; q < K * K; q += 64) Ls[q / K * LD + q % K] = cb * Lb[q / K * LD + q % K];
-        if (lane < K) {
-            double s = 0.0;
-            for (int c = 0; c < K; ++c) s += Lb[lane * LD + c] * mub[c];
-            rhs[lane] = cb * s;
-        }
         double tr = 0.0;
-        for (int k = 0; k < K; ++k) tr += Lb[k * LD + k];
+        for (int k = 0; k < K; ++k) tr += sLb[k * LD + k];
         const double eps = 1e-6 * tr / (double)K;
+        const double cb = 2.0 - (double)(jb.nsib + 1);
+        for (int q = lane; q < KP * KP; q += 64) {
+            const int r = q / KP, c = q - r * KP;
+            sS[r * LD + c] = (r < K && c < K) ? cb * sLb[r * LD + c] : (double)(r == c);
+        }
+        if (own) {
+            double s2 = 0.0;
+            for (int c = 0; c < K; ++c) s2 += sLb[lane * LD + c] * mub[c];
+            rhs[lane] = lane < K ? cb * s2 : 0.0;
+        }
         __syncthreads();
         for (int s = 0; s < jb.nsib; ++s) {
             const double *srow = jb.sib[s] + (int64_t)n * a.prow;
-            for (int q = lane; q < kk2; q += 64) {
-                int r, c;
-                unrank_tri(q, r, c);
-                const double v = srow[q];
-                Wm[r * LD + c] = v;
-                Wm[c * LD + r] = v;
-                Dm[r * LD + c] = v - Lb[r * LD + c];
-                Dm[c * LD + r] = v - Lb[c * LD + r];
+            // D_j = Lambda_j - Lambda_b (lower, identity padding)
+            for (int q = lane; q < KP * KP; q += 64) {
+                const int r = q / KP, c = q - r * KP;
+                sA[r * LD + c] = (r < K && c < K) ? packed_sym(srow, r, c) - sLb[r * LD + c] : (double)(r == c);
             }
             __syncthreads();
-            const bool pd = chol_lds<double>(Dm, K, LD, 0.0, nullptr, lane, &flag);
+            if (own) dg[lane] = sA[lane * LD + lane];
+            __syncthreads();
+            double rr[KP];
+            const bool pd = chol_rows<KP, double>(sA, LD, sA, LD, dg, sinv, 0.0, lane, z0, rr);
+            __syncthreads();
+            double shift = 0.0;
             if (!pd) {
-                for (int q = lane; q < K * K; q += 64) {
-                    const int r = q / K, c = q - r * K;
-                    Dm[r * LD + c] = Wm[r * LD + c] - Lb[r * LD + c];
+                for (int q = lane; q < KP * KP; q += 64) {
+                    const int r = q / KP, c = q - r * KP;
+                    sA[r * LD + c] = (r < K && c < K) ? packed_sym(srow, r, c) - sLb[r * LD + c] : 0.0;
                 }
                 __syncthreads();
-                if (lane == 0) {
-                    lmin = jacobi_min_eig(Dm, K, LD);
-                    atomicAdd(a.corrections, 1);
-                }
-                __syncthreads();
-                const double shift = fabs(lmin) + eps;
-                for (int q = lane; q < K * K; q += 64) {
-                    const int r = q / K, c = q - r * K;
-                    Wm[r * LD + c] = (Wm[r * LD + c] - Lb[r * LD + c]) + (r == c ? shift : 0.0) + Lb[r * LD + c];
-                }
-                __syncthreads();
+                const double lmin = wave_min_eig<KP>(sA, K, LD, lane, sc, sp);
+                shift = fabs(lmin) + eps;
+                if (lane == 0) atomicAdd(a.corrections, 1);
             }
-            for (int q = lane; q < K * K; q += 64) Ls[q / K * LD + q % K] += Wm[q / K * LD + q % K];
+            // Lambda~_j into Lambda*, Lambda~_j mu_j into the right-hand side
+            for (int q = lane; q < K * K; q += 64) {
+                const int r = q / K, c = q - r * K;
+                double v = packed_sym(srow, r, c);
+                if (!pd) v = ((v - sLb[r * LD + c]) + (r == c ? shift : 0.0)) + sLb[r * LD + c];
+                sS[r * LD + c] += v;
+            }
             if (lane < K) {
                 double s2 = 0.0;
-                for (int c = 0; c < K; ++c) s2 += Wm[lane * LD + c] * srow[kk2 + K + c];
+                for (int c = 0; c < K; ++c) {
+                    double v = packed_sym(srow, lane, c);
+                    if (!pd) v = ((v - sLb[lane * LD + c]) + (lane == c ? shift : 0.0)) + sLb[lane * LD + c];
+                    s2 += v * srow[kk2 + K + c];
+                }
                 rhs[lane] += s2;
             }
             __syncthreads();
         }
-        chol_lds<double>(Ls, K, LD, 0.0, nullptr, lane, &flag);
-        fwd_lds<double>(Ls, K, LD, rhs, lane);
-        bwd_lds<double>(Ls, K, LD, rhs, lane);
+        // mu* = Lambda*^-1 (Lambda* mu*)
+        if (own) dg[lane] = sS[lane * LD + lane];
+        __syncthreads();
+        factor_solve_regs<KP, double>(sS, LD, sS, LD, rhs, zero, dg, sinv, 0.0, K, lane);
         if (lane < K) out[lane] = rhs[lane];
         __syncthreads();
     }
@@ -2037,9 +2129,10 @@ hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStre
     return stats_ts<float>(a, njobs, s);
 }
 
-hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s) {
+hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce, dim3(njobs), dim3(kReduceThreads), 0, s, jobs);
+    const int slices = (max_width + kReduceSlice - 1) / kReduceSlice;
+    hipLaunchKernelGGL(k_reduce, dim3(njobs, slices < 1 ? 1 : slices), dim3(kReduceThreads), 0, s, jobs);
     return hipGetLastError();
 }
 
@@ -2080,7 +2173,10 @@ hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s) {
 
 hipError_t launch_agg(const AggArgs &a, hipStream_t s) {
     if (a.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_agg, dim3(grid_for(a.nitems, 1, 65536)), dim3(64), 0, s, a);
+    const dim3 grid(grid_for(a.nitems, 1, 65536));
+    if (a.K <= 16) hipLaunchKernelGGL(k_agg<16>, grid, dim3(64), 0, s, a);
+    else if (a.K <= 32) hipLaunchKernelGGL(k_agg<32>, grid, dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_agg<64>, grid, dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -171,7 +171,9 @@ hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_
 hipError_t launch_sse(int32_t kc, int32_t prec, const SseArgs &a, int32_t ntiles, hipStream_t s);
 hipError_t launch_gram_part(int32_t kp, const GramPartArgs &a, hipStream_t s);
 hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s);
-hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, hipStream_t s);
+// max_width: the largest width among the jobs (blocks cover at most 256
+// outputs of a job each).
+hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width, hipStream_t s);
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
 hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s);
 hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);

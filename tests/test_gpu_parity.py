@@ -268,12 +268,13 @@ def test_fp64_chain_tracks_oracle_1x1():
     np.testing.assert_allclose(pg, po, rtol=1e-5, atol=1e-5)
 
 
-@pytest.mark.parametrize("IJ,order", [((2, 2), "random"), ((3, 2), "decreasing"), ((2, 1), "given")])
-def test_fp64_pp_stages_track_oracle(IJ, order):
+@pytest.mark.parametrize("IJ,order,K", [((2, 2), "random", 6), ((3, 2), "decreasing", 6), ((2, 1), "given", 6),
+                                        ((2, 3), "random", 5)])
+def test_fp64_pp_stages_track_oracle(IJ, order, K):
     """PP stages 1-3 with propagated per-row priors, moment matching, Algorithm 2
-    aggregation and prediction, FP64, identical noise."""
-    d = small_data(6, seed=7, N=300, D=200, nnz=12000, empty_rows=0)
-    K = 6
+    aggregation (with its eigenvalue corrections) and prediction, FP64,
+    identical noise."""
+    d = small_data(K, seed=7, N=300, D=200, nnz=12000, empty_rows=0)
     I, J = IJ
     g, o = pair(d, K, "fp64", I=I, J=J, order=order, burnin=2, thin=1, max_kept=8)
     for s in (1, 2, 3):
@@ -288,6 +289,8 @@ def test_fp64_pp_stages_track_oracle(IJ, order):
     pg = g.predict(d["test_row"], d["test_col"])
     o.aggregate()
     po = o.predict(d["test_row"], d["test_col"])
+    print("aggregation corrections: gpu", g.stats()["agg_corrections"], "oracle", o.corrections)
+    assert g.stats()["agg_corrections"] == o.corrections
     np.testing.assert_allclose(pg, po, rtol=1e-5, atol=1e-5)
     mx = g.get_aggregate(0)
     for r in range(0, d["N"], 7):
