@@ -51,7 +51,7 @@ struct Layout {
     // byte offsets
     int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, ord, X, W, hyper, tau, mu0,
         W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
-        counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits,
+        counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
         m_items, m_items2, m_stats, m_hyper, m_mmout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
         p_out, total;
     int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
@@ -129,6 +129,7 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.sse_col = take(8 * 4 * L.E_c);
     L.colsq = take(8 * L.E_c);
     L.sse_final = take(8 * L.nb);
+    L.nw_noise = take(8 * 3 * L.nb * (c.K * (c.K + 3) / 2));
     L.stats_part = take(8 * L.n_stats_cap * L.npair);
     L.stats_final = take(8 * 2 * L.nb * L.npair);
     L.counters = take(4 * kNumCounters);
@@ -792,7 +793,8 @@ static bmf_status run_stats(bmf_ctx *c, int32_t side_lo, int32_t side_hi, bool r
     return timed(c, kKReduce, [&] { return launch_reduce(rj, side_hi - side_lo, c->L.npair, c->ls); });
 }
 
-static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool use_ss, bool advance = false) {
+static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool use_ss, bool advance = false,
+                            bool noise_ready = false) {
     if (j1 <= j0) return BMF_OK;
     const Layout &L = c->L;
     HyperArgs a{};
@@ -816,6 +818,8 @@ static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool
         a.fb_counts = c->dev<int32_t>(L.counters) + kFbRow;
         a.done = c->dev<int32_t>(L.counters) + kHyperDone;
     }
+    a.noise = c->dev<double>(L.nw_noise) + (int64_t)j0 * (c->cfg.K * (c->cfg.K + 3) / 2);
+    a.noise_ready = noise_ready ? 1 : 0;
     return timed(c, kKHyper, [&] { return launch_hyper(a, j1 - j0, c->ls); });
 }
 
@@ -835,8 +839,19 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
         if ((st = run_stats(c, 0, 2 * nbs, false))) return st;
         const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce) + (tau ? 0 : nbs);
         const int32_t nr = (tau ? nbs : 0) + 2 * nbs;
-        if ((st = timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->L.npair, c->ls); }))) return st;
-        if (S.hyper_begin[nbs] > 0) return run_hyper(c, 0, S.hyper_begin[nbs], 0, true, true);
+        // the reduction launch also draws the Normal-Wishart noise of every
+        // hyper job (extra blocks), off the hyperparameter launch's path
+        NoiseArgs na{};
+        na.jobs = c->dev<HyperJob>(c->L.m_hyper);
+        na.njobs = S.hyper_begin[nbs];
+        na.K = c->cfg.K;
+        na.nu0 = c->cfg.nu0;
+        na.ss = c->dev<SweepState>(c->L.sweep);
+        na.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
+        na.k1 = (uint32_t)(c->cfg.seed >> 32);
+        na.noise = c->dev<double>(c->L.nw_noise);
+        if ((st = timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->L.npair, c->ls, &na); }))) return st;
+        if (S.hyper_begin[nbs] > 0) return run_hyper(c, 0, S.hyper_begin[nbs], 0, true, true, true);
     } else {
         for (int32_t k = 0; k < nbs; ++k) {
             if ((st = run_pass(c, true, 0, nullptr, k, true))) return st;

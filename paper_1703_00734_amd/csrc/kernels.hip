@@ -345,12 +345,16 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     const int G = tl.G;                    // lanes per entity: 1..64, or 128/256 (several waves)
     const int grp = threadIdx.x / G;
     const bool wide = G > 64;              // uniform per tile
-    if (!wide && grp >= tl.count) return;  // whole groups only: shuffles stay inside a group
+    // groups of at least four lanes hand their sums to one lane each for the
+    // factorization (through LDS, after a barrier): empty groups stay until then
+    constexpr bool kPackable = sizeof(Tacc) == 4;
+    const bool pack = kPackable && G >= 4;
+    if (!wide && !pack && grp >= tl.count) return;  // whole groups only: shuffles stay inside a group
     const bool active = grp < tl.count;
-    const int gl = threadIdx.x & (G - 1);
+    int gl = threadIdx.x & (G - 1);
     const SideDesc &sd = a.sides[tl.side];
     const int K = a.K;
-    const int n = active ? a.ord[tl.start + grp] : 0;
+    int n = active ? a.ord[tl.start + grp] : 0;
     const int64_t p0 = active ? a.ptr[sd.ptr_off + n] : 0;
     const int64_t p1 = active ? a.ptr[sd.ptr_off + n + 1] : 0;
     const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * KSW;
@@ -501,8 +505,31 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
             for (int u = 1; u < nw; ++u) v += wsum[w0 + u][NT + i];
             hs[i] = v;
         }
-        if (!active) return;
+        if (!active && !pack) return;
     }
+    if (pack) {
+        // one lane per entity from here on: lane t of the block factors the
+        // t-th entity of the tile, so that a tile of wide groups runs the
+        // factorization on one wavefront instead of on every lane of every group
+        constexpr int NS = NT + KC;
+        __shared__ Tacc psum[kPackable ? 64 * NS : 1];
+        if (active && gl == 0) {
+#pragma unroll
+            for (int q = 0; q < NT; ++q) psum[grp * NS + q] = g[q];
+#pragma unroll
+            for (int i = 0; i < KC; ++i) psum[grp * NS + NT + i] = hs[i];
+        }
+        __syncthreads();
+        const int t = threadIdx.x;
+        if (t >= tl.count) return;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) g[q] = psum[t * NS + q];
+#pragma unroll
+        for (int i = 0; i < KC; ++i) hs[i] = psum[t * NS + NT + i];
+        n = a.ord[tl.start + t];
+        gl = 0;
+    }
+    const int Ge = pack ? 1 : G;            // lanes per entity in the factorization
 
     // A = P + tau G, h = P m + tau hs (identity padding beyond K); the prior is
     // a packed row [P lower (row-major), P m, m]: the side's own row when
@@ -574,10 +601,10 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     // least as many lanes as blocks (inside one wavefront) draws each block once
     // and shares it; otherwise every lane draws every block.
     const int NQ = (K + 3) / 4;
-    if (G >= NQ && G <= 64) {
+    if (Ge >= NQ && Ge <= 64) {
         Tacc zq[4];
         normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)(gl < NQ ? gl : 0), a.k0, a.k1, zq);
-        const int base = (threadIdx.x & 63) & ~(G - 1);
+        const int base = (threadIdx.x & 63) & ~(Ge - 1);
 #pragma unroll
         for (int q = 0; q < (KC + 3) / 4; ++q) {
             if (q < NQ) {
@@ -1364,10 +1391,47 @@ __global__ __launch_bounds__(64 * WB) void k_stats_mfma(const StatsArgs a) {
     }
 }
 
+// Noise of one Normal-Wishart draw, written to dst: [Bartlett diagonal
+// sqrt(chi2(nu* - i)), i < K | K(K-1)/2 standard normals below the diagonal,
+// row-major | K standard normals for the mean].  The diagonal is drawn by
+// threads [0, K), the normals in blocks of four by threads from `first` on,
+// `stride` apart (first = 0 and stride = 64 in a single wavefront).
+__device__ void nw_noise(const HyperJob &jb, int K, double nu0, uint32_t t_sw, uint32_t k0, uint32_t k1,
+                         double *dst, int tid, int first, int stride) {
+    const uint32_t c2 = counter_word(jb.block, jb.kind == 0 ? kHyperX : kHyperW);
+    const double nu_s = nu0 + (double)jb.n;
+    if (tid < K) dst[tid] = sqrt(2.0 * gamma_draw(k0, k1, (uint32_t)(tid + 1), t_sw, c2, 0.5 * (nu_s - tid)));
+    const int noff = K * (K - 1) / 2;
+    const int go = (noff + 3) / 4, gm = (K + 3) / 4;
+    for (int u = tid - first; u >= 0 && u < go + gm; u += stride) {
+        double z[4];
+        const bool off = u < go;
+        const int g = off ? u : u - go;
+        normals4(off ? 0u : (uint32_t)(K + 1), t_sw, c2, (uint32_t)g, k0, k1, z);
+        const int lim = off ? noff : K;
+        double *d = dst + K + (off ? 0 : noff);
+        for (int c = 0; c < 4; ++c)
+            if (4 * g + c < lim) d[4 * g + c] = z[c];
+    }
+}
+
 constexpr int kReduceThreads = 1024;
 constexpr int kReduceSlice = 256;           // outputs per block at most (blockIdx.y: slice)
-__global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs) {
+__global__ __launch_bounds__(kReduceThreads) void k_reduce(const ReduceJob *jobs, const int32_t njobs,
+                                                           const NoiseArgs na) {
     __shared__ double red[kReduceThreads];
+    if ((int)blockIdx.x >= njobs) {
+        // the Normal-Wishart noise of hyper job blockIdx.x - njobs (first slice
+        // only): the diagonal in the first wavefront, the normals from the second
+        const int j = blockIdx.x - njobs;
+        if (blockIdx.y != 0) return;
+        const HyperJob hj = na.jobs[j];
+        if (hj.kind > 1) return;
+        const uint32_t t_sw = na.ss ? na.ss->t : na.t;
+        nw_noise(hj, na.K, na.nu0, t_sw, na.k0, na.k1, na.noise + (int64_t)j * (na.K * (na.K + 3) / 2),
+                 threadIdx.x, 64, kReduceThreads - 64);
+        return;
+    }
     const ReduceJob jb = jobs[blockIdx.x];
     const int t = threadIdx.x;
     const int lo = blockIdx.y * kReduceSlice;
@@ -1429,8 +1493,13 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
     z0 &= ~15;
     const bool own = lane < KP;
     const int row = own ? lane : KP - 1;
-    const uint32_t c2 = counter_word(jb.block, jb.kind == 0 ? kHyperX : kHyperW);
     const int npair = K + K * (K + 1) / 2;
+    // the draw's noise: made by the reduction launch before this one, or here
+    const double *nz = a.noise + (int64_t)blockIdx.x * (K * (K + 3) / 2);
+    if (!a.noise_ready) {
+        nw_noise(jb, K, a.nu0, t_sw, a.k0, a.k1, const_cast<double *>(nz), lane, 0, 64);
+        __syncthreads();
+    }
     // 1. the side's sums (reduced in fixed order by the statistics kernel) and
     //    identity padding beyond K
     for (int q = lane; q < KP * KP; q += 64) {
@@ -1451,7 +1520,7 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
     }
     __syncthreads();
     const double N = (double)jb.n;
-    const double beta_s = a.beta0 + N, nu_s = a.nu0 + N;
+    const double beta_s = a.beta0 + N;
     if (lane < K) mus[lane] = (a.beta0 * a.mu0[lane] + sx[lane]) / beta_s;
     // 2. W*^-1 = W0^-1 + (sum x x^T - N xbar xbar^T) + beta0 N / beta* (mu0 - xbar)(mu0 - xbar)^T
     const double coef = a.beta0 * N / beta_s;
@@ -1474,21 +1543,12 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
         S2[r * LD + c] = (r == c && r >= K) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (lane < K)
-        S2[lane * LD + lane] =
-            sqrt(2.0 * gamma_draw(a.k0, a.k1, (uint32_t)(lane + 1), t_sw, c2, 0.5 * (nu_s - lane)));
+    if (lane < K) S2[lane * LD + lane] = nz[lane];
     const int noff = K * (K - 1) / 2;
-    for (int g = lane; 4 * g < noff; g += 64) {
-        double z[4];
-        normals4(0u, t_sw, c2, (uint32_t)g, a.k0, a.k1, z);
-        for (int c = 0; c < 4; ++c) {
-            const int q = 4 * g + c;
-            if (q < noff) {
-                int r, cc;
-                unrank_tri(q, r, cc);          // strict lower, row-major: row r+1, column cc
-                S2[(r + 1) * LD + cc] = z[c];
-            }
-        }
+    for (int q = lane; q < noff; q += 64) {
+        int r, cc;
+        unrank_tri(q, r, cc);                  // strict lower, row-major: row r+1, column cc
+        S2[(r + 1) * LD + cc] = nz[K + q];
     }
     __syncthreads();
     asm volatile("" : "+v"(lane));
@@ -1541,13 +1601,7 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
     __syncthreads();
     // 7. C C^T = Lambda (rows of C in S1); 8. mu = mu* + C^-T z / sqrt(beta*)
     ok = chol_rows<KP, double>(S0, LD, S1, LD, dg, sinv, 0.0, lane, z0, rr) && ok;
-    if (lane * 4 < K) {
-        double z[4];
-        normals4((uint32_t)(K + 1), t_sw, c2, (uint32_t)lane, a.k0, a.k1, z);
-        for (int c = 0; c < 4; ++c)
-            if (4 * lane + c < K) zz[4 * lane + c] = z[c];
-    }
-    if (lane >= K && own) zz[lane] = 0.0;
+    if (own) zz[lane] = lane < K ? nz[K + noff + lane] : 0.0;
     __syncthreads();
     asm volatile("" : "+v"(lane));
     {
@@ -2129,16 +2183,25 @@ hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStre
     return stats_ts<float>(a, njobs, s);
 }
 
-hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width, hipStream_t s) {
-    if (njobs <= 0) return hipSuccess;
+hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width, hipStream_t s,
+                         const NoiseArgs *noise) {
+    const int nn = noise ? noise->njobs : 0;
+    if (njobs + nn <= 0) return hipSuccess;
     const int slices = (max_width + kReduceSlice - 1) / kReduceSlice;
-    hipLaunchKernelGGL(k_reduce, dim3(njobs, slices < 1 ? 1 : slices), dim3(kReduceThreads), 0, s, jobs);
+    NoiseArgs na{};
+    if (noise) na = *noise;
+    hipLaunchKernelGGL(k_reduce, dim3(njobs + nn, slices < 1 ? 1 : slices), dim3(kReduceThreads), 0, s, jobs,
+                       njobs, na);
     return hipGetLastError();
 }
 
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    if (a.K <= 16)
+    if (a.K <= 8)
+        hipLaunchKernelGGL(k_hyper<8>, dim3(njobs), dim3(64), 0, s, a);
+    else if (a.K <= 12)
+        hipLaunchKernelGGL(k_hyper<12>, dim3(njobs), dim3(64), 0, s, a);
+    else if (a.K <= 16)
         hipLaunchKernelGGL(k_hyper<16>, dim3(njobs), dim3(64), 0, s, a);
     else if (a.K <= 32)
         hipLaunchKernelGGL(k_hyper<32>, dim3(njobs), dim3(64), 0, s, a);

@@ -119,6 +119,22 @@ struct HyperArgs {
     SweepState *advance;
     int32_t *fb_counts;       // the fallback queue counters it resets
     int32_t *done;            // completion counter of the launch (zero between launches)
+    // Normal-Wishart noise of job j at noise + j * K(K+3)/2: drawn by the
+    // preceding reduction launch when noise_ready, else by this launch
+    double *noise;
+    int32_t noise_ready;
+};
+
+// Noise draws of the Normal-Wishart jobs that a reduction launch makes in
+// extra blocks (one per job), for the hyperparameter launch after it.
+struct NoiseArgs {
+    const HyperJob *jobs;
+    int32_t njobs;            // hyper jobs; kinds 0 and 1 get noise
+    int32_t K;
+    double nu0;
+    uint32_t t, k0, k1;
+    const SweepState *ss;     // when set, t comes from here
+    double *noise;
 };
 
 struct InitArgs {
@@ -173,7 +189,8 @@ hipError_t launch_gram_part(int32_t kp, const GramPartArgs &a, hipStream_t s);
 hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s);
 // max_width: the largest width among the jobs (blocks cover at most 256
 // outputs of a job each).
-hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width, hipStream_t s);
+hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width, hipStream_t s,
+                         const NoiseArgs *noise = nullptr);
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
 hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s);
 hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
