@@ -415,33 +415,42 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
         // selected before use, so the loads stay in flight across iterations
         // instead of forcing a wait on each one.
         constexpr int B = 4;
-        const int64_t last = p1 - 1;
+        // 32-bit entry offsets from the entity's first entry, and 32-bit byte
+        // offsets of the gathered rows from the side's (uniform) base, so the
+        // loads take the scalar-base plus vector-offset form
+        const int32_t deg = (int32_t)(p1 - p0);
+        const int32_t lastk = deg - 1;
+        const int32_t *idxb = a.idx + p0;
+        const Tv *valb = val + p0;
+        const char *ob = reinterpret_cast<const char *>(other);
+        constexpr uint32_t RB = KSW * sizeof(Tw);
+        int32_t k = gl;
         int dq[B];
         Tacc rq[B];
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            const int64_t eu = min(e + u * (int64_t)G, last);
-            dq[u] = p1 > p0 ? a.idx[eu] : 0;
-            rq[u] = p1 > p0 ? (Tacc)val[eu] : (Tacc)0;
+            const int32_t ku = min(k + u * G, lastk);
+            dq[u] = deg > 0 ? idxb[ku] : 0;
+            rq[u] = deg > 0 ? (Tacc)valb[ku] : (Tacc)0;
         }
-        for (; e < p1; e += B * (int64_t)G) {
+        for (; k < deg; k += B * G) {
             Tacc rc[B];
             bool ok[B];
 #pragma unroll
             for (int u = 0; u < B; ++u) {
-                ok[u] = e + u * (int64_t)G < p1;
+                ok[u] = k + u * G < deg;
                 rc[u] = ok[u] ? rq[u] : (Tacc)0;
             }
             // issue order: this batch's rows, then the next batch's indices and
             // values; one wait (for the rows only) before the arithmetic
             uint32_t w[B][NW];
 #pragma unroll
-            for (int u = 0; u < B; ++u) load_raw<NW>(other + (int64_t)dq[u] * KSW, w[u]);
-            const int64_t en = e + B * (int64_t)G;
+            for (int u = 0; u < B; ++u) load_raw<NW>(ob + (uint32_t)dq[u] * RB, w[u]);
+            const int32_t kn = k + B * G;
 #pragma unroll
-            for (int u = 0; u < B; ++u) dq[u] = a.idx[min(en + u * (int64_t)G, last)];
+            for (int u = 0; u < B; ++u) dq[u] = idxb[min(kn + u * G, lastk)];
 #pragma unroll
-            for (int u = 0; u < B; ++u) rq[u] = (Tacc)val[min(en + u * (int64_t)G, last)];
+            for (int u = 0; u < B; ++u) rq[u] = (Tacc)valb[min(kn + u * G, lastk)];
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < B; ++u)
@@ -459,6 +468,7 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
                 for (int u = 0; u < B; ++u) fma_entry(w[u], rc[u]);
             }
         }
+        e = p0 + k;
     } else {
         // FP64 rows: one pair in flight (the pipeline would cost occupancy)
         for (; e + G < p1; e += step) {
