@@ -26,7 +26,7 @@ namespace {
 constexpr int32_t kStatsRowsPerJob = 512;   // entities per NW statistics job (about)
 constexpr int32_t kStatsJobsMax = 256;      // jobs per side at most
 constexpr int64_t kPredictChunk = 1 << 20;  // prediction pairs per launch
-constexpr int32_t kFallbackGrid = 512;      // workgroups of the FP64 redo pass
+constexpr int32_t kFallbackGrid = 128;      // workgroups of the FP64 redo pass
 constexpr int64_t kSegNnz = 2048;           // MFMA path: entities with more entries are split
 constexpr int32_t kWaveGridCap = 1 << 20;
 
