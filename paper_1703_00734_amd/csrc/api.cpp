@@ -27,6 +27,7 @@ constexpr int32_t kStatsRowsPerJob = 512;   // entities per NW statistics job (a
 constexpr int32_t kStatsJobsMax = 256;      // jobs per side at most
 constexpr int64_t kPredictChunk = 1 << 20;  // prediction pairs per launch
 constexpr int32_t kFallbackGrid = 128;      // workgroups of the FP64 redo pass
+constexpr int64_t kLightNnz = 16;           // entities the batched MFMA path gives to the VALU-Gram kernel
 constexpr int64_t kSegNnz = 2048;           // MFMA path: entities with more entries are split
 constexpr int32_t kWaveGridCap = 1 << 20;
 
@@ -169,6 +170,10 @@ struct StageLists {
     // wave kernel items, same four lists
     std::vector<int2> items;
     int64_t i_row_blk = 0, i_row_heavy = 0, i_col_blk = 0, i_col_heavy = 0, i_end = 0;
+    // first item of the heavy-first order with at most kLightNnz entries, and
+    // the same per block (block item lists are in decreasing degree order)
+    int64_t i_row_light = 0, i_col_light = 0;
+    std::vector<int64_t> row_item_light, col_item_light;
     std::vector<int64_t> row_item_begin, col_item_begin;
     std::vector<int2> ents;                         // every (side, entity) of the stage
     // MFMA path: segments of heavy entities ([rows grouped | cols grouped]) and,
@@ -429,8 +434,11 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
             const int32_t side = rows ? k : nbs + k;
             ibeg.push_back((int64_t)igrp.size());
             sbeg.push_back((int64_t)slot);
+            std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
+            blight.push_back(-1);
             for (int32_t e : (rows ? S.ord_row[k] : S.ord_col[k])) {
                 const int64_t deg = ptr[e + 1] - ptr[e];
+                if (blight.back() < 0 && deg <= kLightNnz) blight.back() = (int64_t)igrp.size();
                 igrp.push_back(make_int2(side, e));
                 ideg.push_back(deg);
                 if (mf && deg > kSegNnz) {
@@ -455,6 +463,11 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         }
         ibeg.push_back((int64_t)igrp.size());
         sbeg.push_back((int64_t)slot);
+        {
+            std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
+            for (int32_t k = 0; k < nbs; ++k)
+                if (blight[k] < 0) blight[k] = ibeg[k + 1];
+        }
         std::vector<int64_t> iperm(igrp.size());
         for (size_t q = 0; q < iperm.size(); ++q) iperm[q] = (int64_t)q;
         std::stable_sort(iperm.begin(), iperm.end(), [&](int64_t a2, int64_t b2) { return ideg[a2] > ideg[b2]; });
@@ -462,10 +475,14 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         S.items.insert(S.items.end(), igrp.begin(), igrp.end());
         S.splits.insert(S.splits.end(), sgrp.begin(), sgrp.end());
         (rows ? S.i_row_heavy : S.i_col_heavy) = (int64_t)S.items.size();
+        int64_t &light = rows ? S.i_row_light : S.i_col_light;
+        light = -1;
         for (int64_t q : iperm) {
+            if (light < 0 && ideg[q] <= kLightNnz) light = (int64_t)S.items.size();
             S.items.push_back(igrp[q]);
             S.splits.push_back(sgrp[q]);
         }
+        if (light < 0) light = (int64_t)S.items.size();
     }
     S.s_end = (int64_t)S.segs.size();
     S.i_end = (int64_t)S.items.size();
@@ -707,7 +724,34 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
                 if ((st = timed(c, kKGram, [&] { return launch_gram_part(L.kc, ga, c->ls); }))) return st;
             }
         }
-        for (auto &r : ranges) {
+        // MFMA path: the light entities (at most kLightNnz entries, the tail of
+        // each decreasing-degree range) run on the VALU-Gram kernel, which needs
+        // fewer registers and so keeps more entities in flight
+        std::vector<bool> vg(ranges.size(), false);
+        if (L.mfma) {
+            std::vector<std::pair<int64_t, int64_t>> split;
+            std::vector<bool> svg;
+            for (size_t ri = 0; ri < ranges.size(); ++ri) {
+                int64_t light;
+                if (batched) {
+                    light = rows ? S.i_row_light : S.i_col_light;
+                } else {
+                    const int32_t q = k < 0 ? (int32_t)ri : k;
+                    light = (rows ? S.i_row_blk : S.i_col_blk) + (rows ? S.row_item_light : S.col_item_light)[q];
+                }
+                light = std::min(std::max(light, ranges[ri].first), ranges[ri].second);
+                split.push_back({ranges[ri].first, light});
+                svg.push_back(false);
+                split.push_back({light, ranges[ri].second});
+                svg.push_back(true);
+            }
+            ranges.swap(split);
+            vg.swap(svg);
+        }
+        for (size_t ri = 0; ri < ranges.size(); ++ri) {
+            const auto &r = ranges[ri];
+            if (r.second <= r.first) continue;
+            const bool vgram = vg[ri];
             UpdArgs b = a;
             b.items = c->dev<int2>(L.m_items) + r.first;
             b.nitems = (int32_t)(r.second - r.first);
@@ -716,7 +760,8 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
                 b.gpart = c->dev<float>(L.gpart);
             }
             const int32_t g = (int32_t)std::min<int64_t>(b.nitems, kWaveGridCap);
-            if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->ls); }))) return st;
+            if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->ls, vgram); })))
+                return st;
         }
     }
     if (!c->fp64()) {

@@ -1025,7 +1025,11 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
     constexpr int LD = KP + 1;                       // A: odd stride, conflict-free rows
     constexpr int LDL = KP + 16 / (int)sizeof(Tacc); // L: 16-byte rows for broadcast loads
     __shared__ __align__(16) Tacc sA[KP * LDL];
-    __shared__ Tacc sw[MF ? 1 : CH * KP];
+    // the VALU Gram stages its chunks in sA when they fit (the Gram is held in
+    // registers until the chunks are done): less LDS, more waves per CU
+    constexpr bool kSwInA = CH * KP <= KP * LDL;
+    __shared__ Tacc swbuf[MF || kSwInA ? 1 : CH * KP];
+    Tacc *const sw = kSwInA ? sA : swbuf;
     __shared__ Tacc sr[MF ? 1 : CH];
     __shared__ Tacc sh[KP];
     __shared__ Tacc sz[KP];
@@ -1084,47 +1088,6 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
                 __builtin_amdgcn_wave_barrier();
                 store_gram<KP, Tacc>(sA, LD, sh, lane, c00, c10, c11, hlo, hhi);
             }
-            __syncthreads();
-            const Tacc tau = (Tacc)(*sd.tau);
-            const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
-            const double *pv = pr + K * (K + 1) / 2;
-            // packed lower prior, lanes over consecutive entries (coalesced), all
-            // loads issued before the first use.  Row of entry q: the floor of
-            // (sqrt(8q + 1) - 1) / 2, which is an integer at the start of a row
-            // and at least 2 / (2 row + 3) > 0.015 below the next integer
-            // elsewhere (row < 64), so an approximate square root plus 1e-3
-            // floors to the right row
-            const int npk = K * (K + 1) / 2;
-            constexpr int NQ = (KP * (KP + 1) / 2 + 63) / 64;
-            constexpr int CQ = 8;                            // loads in flight per chunk
-#pragma unroll
-            for (int u0 = 0; u0 < NQ; u0 += CQ) {
-                double pq[CQ];
-#pragma unroll
-                for (int u = 0; u < CQ; ++u) {
-                    const int q = lane + 64 * (u0 + u);
-                    pq[u] = (u0 + u < NQ && q < npk) ? pr[q] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < CQ; ++u) {
-                    const int q = lane + 64 * (u0 + u);
-                    if (u0 + u < NQ && q < npk) {
-                        const int ra = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f + 1e-3f);
-                        const int cb = q - ra * (ra + 1) / 2;
-                        sA[ra * LD + cb] = (Tacc)pq[u] + tau * sA[ra * LD + cb];
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            // identity padding rows K..KP-1
-            for (int q = lane; q < (KP - K) * KP; q += 64) {
-                const int ra = K + q / KP, cb = q % KP;
-                if (cb <= ra) sA[ra * LD + cb] = (Tacc)(ra == cb);
-            }
-            for (int q = lane; q < KP; q += 64) {
-                shraw[q] = sh[q];
-                sh[q] = q < K ? (Tacc)pv[q] + tau * sh[q] : (Tacc)0;
-            }
         } else {
             Tacc acc[TL][TL];
             Tacc hacc[TL];
@@ -1164,33 +1127,56 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
                 }
             }
             __syncthreads();
-
-            const Tacc tau = (Tacc)(*sd.tau);
-            const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
-            const double *pv = pr + K * (K + 1) / 2;
+            // the raw Gram and right-hand side, for the prior pass below
     #pragma unroll
-            for (int i = 0; i < TL; ++i) {
+            for (int i = 0; i < TL; ++i)
     #pragma unroll
-                for (int j = 0; j < TL; ++j) {
-                    const int ra = ti * TL + i, cb = tj * TL + j;
-                    Tacc v;
-                    if (ra < K && cb < K) {
-                        const double p = pr[ra >= cb ? tri(ra, cb) : tri(cb, ra)];
-                        v = (Tacc)p + tau * acc[i][j];
-                    } else {
-                        v = (Tacc)(ra == cb);
-                    }
-                    sA[ra * LD + cb] = v;
-                }
-            }
+                for (int j = 0; j < TL; ++j) sA[(ti * TL + i) * LD + tj * TL + j] = acc[i][j];
             if (tj == 0) {
     #pragma unroll
-                for (int i = 0; i < TL; ++i) {
-                    const int ra = ti * TL + i;
-                    shraw[ra] = hacc[i];
-                    sh[ra] = ra < K ? (Tacc)pv[ra] + tau * hacc[i] : (Tacc)0;
+                for (int i = 0; i < TL; ++i) sh[ti * TL + i] = hacc[i];
+            }
+        }
+        __syncthreads();
+        const Tacc tau = (Tacc)(*sd.tau);
+        const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
+        const double *pv = pr + K * (K + 1) / 2;
+        // packed lower prior, lanes over consecutive entries (coalesced), all
+        // loads issued before the first use.  Row of entry q: the floor of
+        // (sqrt(8q + 1) - 1) / 2, which is an integer at the start of a row
+        // and at least 2 / (2 row + 3) > 0.015 below the next integer
+        // elsewhere (row < 64), so an approximate square root plus 1e-3
+        // floors to the right row
+        const int npk = K * (K + 1) / 2;
+        constexpr int NQ = (KP * (KP + 1) / 2 + 63) / 64;
+        constexpr int CQ = 8;                            // loads in flight per chunk
+#pragma unroll
+        for (int u0 = 0; u0 < NQ; u0 += CQ) {
+            double pq[CQ];
+#pragma unroll
+            for (int u = 0; u < CQ; ++u) {
+                const int q = lane + 64 * (u0 + u);
+                pq[u] = (u0 + u < NQ && q < npk) ? pr[q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CQ; ++u) {
+                const int q = lane + 64 * (u0 + u);
+                if (u0 + u < NQ && q < npk) {
+                    const int ra = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f + 1e-3f);
+                    const int cb = q - ra * (ra + 1) / 2;
+                    sA[ra * LD + cb] = (Tacc)pq[u] + tau * sA[ra * LD + cb];
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // identity padding rows K..KP-1
+        for (int q = lane; q < (KP - K) * KP; q += 64) {
+            const int ra = K + q / KP, cb = q % KP;
+            if (cb <= ra) sA[ra * LD + cb] = (Tacc)(ra == cb);
+        }
+        for (int q = lane; q < KP; q += 64) {
+            shraw[q] = sh[q];
+            sh[q] = q < K ? (Tacc)pv[q] + tau * sh[q] : (Tacc)0;
         }
         if (lane * 4 < K) {
             Tacc z[4];
@@ -2113,12 +2099,17 @@ hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t
 }
 
 template <int KP>
-static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s, bool vgram) {
     constexpr bool kMF = KP >= 32;   // BF16 state: Gram on MFMA
     switch (prec) {
     case kP64: hipLaunchKernelGGL((k_update_wave<KP, kP64, false>), dim3(grid), dim3(64), 0, s, a); break;
     case kP32: hipLaunchKernelGGL((k_update_wave<KP, kP32, false>), dim3(grid), dim3(64), 0, s, a); break;
-    case kPBF: hipLaunchKernelGGL((k_update_wave<KP, kPBF, kMF>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPBF:
+        if (kMF && !vgram)
+            hipLaunchKernelGGL((k_update_wave<KP, kPBF, kMF>), dim3(grid), dim3(64), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_update_wave<KP, kPBF, false>), dim3(grid), dim3(64), 0, s, a);
+        break;
     case kPFB32: hipLaunchKernelGGL((k_update_wave<KP, kPFB32, false>), dim3(grid), dim3(64), 0, s, a); break;
     case kPFB16: hipLaunchKernelGGL((k_update_wave<KP, kPFB16, false>), dim3(grid), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
@@ -2126,11 +2117,11 @@ static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s, bool vgram) {
     if (grid <= 0) return hipSuccess;
-    if (kp <= 16) return upd_wave_kp<16>(prec, a, grid, s);
-    if (kp <= 32) return upd_wave_kp<32>(prec, a, grid, s);
-    if (kp <= 64) return upd_wave_kp<64>(prec, a, grid, s);
+    if (kp <= 16) return upd_wave_kp<16>(prec, a, grid, s, vgram);
+    if (kp <= 32) return upd_wave_kp<32>(prec, a, grid, s, vgram);
+    if (kp <= 64) return upd_wave_kp<64>(prec, a, grid, s, vgram);
     return hipErrorInvalidValue;
 }
 

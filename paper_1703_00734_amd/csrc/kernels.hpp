@@ -182,8 +182,9 @@ struct PredictArgs {
 
 hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t ntiles,
                              hipStream_t s);
-hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid,
-                              hipStream_t s);
+// vgram: BF16 state with K > 16 takes the VALU-Gram kernel instead of the MFMA one
+hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
+                              bool vgram = false);
 hipError_t launch_sse(int32_t kc, int32_t prec, const SseArgs &a, int32_t ntiles, hipStream_t s);
 hipError_t launch_gram_part(int32_t kp, const GramPartArgs &a, hipStream_t s);
 hipError_t launch_stats(int32_t prec, const StatsArgs &a, int32_t njobs, hipStream_t s);
