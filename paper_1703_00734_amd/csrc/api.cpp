@@ -27,7 +27,7 @@ constexpr int32_t kStatsRowsPerJob = 512;   // entities per NW statistics job (a
 constexpr int32_t kStatsJobsMax = 256;      // jobs per side at most
 constexpr int64_t kPredictChunk = 1 << 20;  // prediction pairs per launch
 constexpr int32_t kFallbackGrid = 128;      // workgroups of the FP64 redo pass
-constexpr int64_t kLightNnz = 16;           // entities the batched MFMA path gives to the VALU-Gram kernel
+constexpr int64_t kLightNnz = 16;           // light entities: VALU-Gram or two-per-wavefront kernels
 constexpr int64_t kSegNnz = 2048;           // MFMA path: entities with more entries are split
 constexpr int32_t kWaveGridCap = 1 << 20;
 
@@ -728,7 +728,9 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         // each decreasing-degree range) run on the VALU-Gram kernel, which needs
         // fewer registers and so keeps more entities in flight
         std::vector<bool> vg(ranges.size(), false);
-        if (L.mfma) {
+        // 16 < K <= 32 in FP32 arithmetic: light entities two per wavefront
+        const bool duo = L.kc == 32 && (c->prec() == kP32 || c->prec() == kPBF);
+        if (L.mfma || duo) {
             std::vector<std::pair<int64_t, int64_t>> split;
             std::vector<bool> svg;
             for (size_t ri = 0; ri < ranges.size(); ++ri) {
@@ -758,6 +760,11 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
             if (L.mfma) {
                 b.splits = c->dev<int2>(L.m_splits) + r.first;
                 b.gpart = c->dev<float>(L.gpart);
+            }
+            if (vgram && duo) {
+                const int32_t g = (int32_t)std::min<int64_t>((b.nitems + 1) / 2, kWaveGridCap);
+                if ((st = timed(c, kcls, [&] { return launch_update_duo(c->prec(), b, g, c->ls); }))) return st;
+                continue;
             }
             const int32_t g = (int32_t)std::min<int64_t>(b.nitems, kWaveGridCap);
             if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->ls, vgram); })))

@@ -1238,6 +1238,243 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// k_update_duo: two light entities per wavefront (16 < K <= 32, FP32
+// arithmetic).  Lanes 32h .. 32h + 31 hold entity h: lane r owns row r of its
+// Gram, of its factor and of its solves, so the factorisation steps, which
+// leave half of a wavefront idle at one entity per wavefront, serve two.  For
+// entities with at most kDuoNnz entries (their rows are staged in LDS at once).
+// --------------------------------------------------------------------------
+constexpr int kDuoNnz = 16;
+
+// Value of lane 32h + q for the lanes of half h (q uniform).
+__device__ __forceinline__ float half_bcast(float v, int q, int h) {
+    const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+    const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + q));
+    return h ? hi : lo;
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
+    using Tacc = typename PrecT<P>::acc;
+    using Tw = typename PrecT<P>::w;
+    using Tv = typename PrecT<P>::v;
+    using Ts = typename PrecT<P>::s;
+    using Tp = typename PrecT<P>::p;
+    static_assert(sizeof(Tacc) == 4, "FP32 arithmetic");
+    constexpr int KP = 32;
+    constexpr int LDL = KP + 4;                      // 16-byte rows for broadcast loads
+    constexpr int CH = kDuoNnz;
+    static_assert(CH * KP <= KP * LDL, "staged rows fit the Gram's LDS");
+    __shared__ __align__(16) Tacc sA[2 * KP * LDL];  // per entity: staged rows, then A, then L
+    __shared__ Tacc sr[2 * CH];
+    __shared__ Tacc sh[2 * KP];
+    __shared__ Tacc shraw[2 * KP];
+    __shared__ Tacc sz[2 * KP];
+    __shared__ Tacc sinv[2 * KP];
+
+    const int K = a.K;
+    const int nitems = a.nitems_dev ? *a.nitems_dev : a.nitems;
+    uint32_t t_sw = a.t;
+    void *sample = a.sample;
+    if (a.ss) {
+        t_sw = a.ss->t;
+        sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
+    }
+    const Tw *otherb = reinterpret_cast<const Tw *>(a.other);
+    const Tv *val = reinterpret_cast<const Tv *>(a.val);
+
+    for (int pit = blockIdx.x; 2 * pit < nitems; pit += gridDim.x) {
+        int lane = threadIdx.x;
+        asm volatile("" : "+v"(lane));
+        const int h = lane >> 5, r = lane & 31;
+        const int it = 2 * pit + h;
+        const bool valid = it < nitems;             // uniform per half
+        const int2 item = a.items[valid ? it : 2 * pit];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        const int64_t p0 = a.ptr[sd.ptr_off + n];
+        const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
+        const bool fits = deg <= CH;                 // else: the FP64 redo takes it
+        const int nc = fits ? deg : 0;
+        const Tw *other = otherb + sd.other_off * a.ks_other;
+        Tacc *A = sA + h * (KP * LDL);
+        Tacc *rv = sr + h * CH;
+        Tacc *hh = sh + h * KP, *hr = shraw + h * KP, *zz = sz + h * KP, *iv = sinv + h * KP;
+
+        __syncthreads();                             // the previous pair is done with the LDS
+        // the entity's rows (zero beyond K) and values, staged in its A
+        for (int q = r; q < nc * KP; q += 32) {
+            const int e = q / KP, k = q - e * KP;
+            A[q] = k < K ? to_acc<Tacc>(other[(int64_t)a.idx[p0 + e] * a.ks_other + k]) : (Tacc)0;
+        }
+        if (r < CH) rv[r] = r < nc ? (Tacc)val[p0 + r] : (Tacc)0;
+        __syncthreads();
+        // row r of the Gram and entry r of the right-hand side
+        Tacc g[KP];
+#pragma unroll
+        for (int c = 0; c < KP; ++c) g[c] = (Tacc)0;
+        Tacc hs = (Tacc)0;
+        for (int e = 0; e < nc; ++e) {
+            const Tacc *we = A + e * KP;
+            const Tacc wr = we[r];
+#pragma unroll
+            for (int c = 0; c < KP; ++c) g[c] += wr * we[c];
+            hs += rv[e] * wr;
+        }
+        __syncthreads();                             // staged rows read
+#pragma unroll
+        for (int c = 0; c < KP; ++c) A[r * LDL + c] = g[c];
+        hh[r] = hs;
+        __syncthreads();
+        // A = P + tau G, h = P m + tau hs: the packed prior, coalesced over the
+        // half's lanes (row of entry q as in the wave kernel)
+        const Tacc tau = (Tacc)(*sd.tau);
+        const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
+        const int npk = K * (K + 1) / 2;
+        constexpr int NQ = (KP * (KP + 1) / 2 + 31) / 32;
+        constexpr int CQ = 9;
+#pragma unroll
+        for (int u0 = 0; u0 < NQ; u0 += CQ) {
+            double pq[CQ];
+#pragma unroll
+            for (int u = 0; u < CQ; ++u) {
+                const int q = r + 32 * (u0 + u);
+                pq[u] = (u0 + u < NQ && q < npk) ? pr[q] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < CQ; ++u) {
+                const int q = r + 32 * (u0 + u);
+                if (u0 + u < NQ && q < npk) {
+                    const int ra = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f + 1e-3f);
+                    const int cb = q - ra * (ra + 1) / 2;
+                    A[ra * LDL + cb] = (Tacc)pq[u] + tau * A[ra * LDL + cb];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (r >= K) {
+            // identity padding row
+#pragma unroll
+            for (int c = 0; c < KP; ++c)
+                if (c <= r) A[r * LDL + c] = (Tacc)(c == r);
+        }
+        hr[r] = hs;
+        hh[r] = r < K ? (Tacc)pr[npk + r] + tau * hs : (Tacc)0;
+        if (r * 4 < K) {
+            Tacc z[4];
+            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (4 * r + c < K) zz[4 * r + c] = z[c];
+        }
+        if (r >= K) zz[r] = (Tacc)0;
+        __syncthreads();
+
+        // left-looking Cholesky, row r in registers, rows of L broadcast from LDS
+        // (L overlays A: every row is read before the first write)
+        asm volatile("" : "+v"(lane));
+        Tacc rr[KP];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) {
+            const Tacc v = A[r * LDL + j];
+            rr[j] = j <= r ? v : (Tacc)0;
+            asm volatile("" : "+v"(rr[j]));
+        }
+        const Tacc d0 = A[r * LDL + r];
+        __syncthreads();
+        int mybad = 0;
+        Tacc myinv = (Tacc)1;
+        const Tacc theta = (Tacc)a.theta;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            Tacc s0 = rr[k], s1 = (Tacc)0;
+            const Tacc *lk = A + k * LDL;
+#pragma unroll
+            for (int p = 0; p < k; ++p) {
+                if (p & 1) s1 -= rr[p] * lk[p];
+                else s0 -= rr[p] * lk[p];
+                if ((p & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+            }
+            const Tacc sk = s0 + s1;
+            const Tacc dk = half_bcast(sk, k, h);
+            mybad = r == k ? (int)!(sk > theta * d0) : mybad;
+            Tacc lkk, inv;
+            pivot_of(dk > (Tacc)0 ? dk : (Tacc)1, lkk, inv);
+            myinv = r == k ? inv : myinv;
+            rr[k] = r == k ? lkk : sk * inv;
+            A[r * LDL + k] = rr[k];
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" : "+v"(rr[k]), "+v"(myinv), "+v"(mybad));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        iv[r] = myinv;
+        const uint64_t bad = __ballot(mybad);
+        const bool ok = fits && ((bad >> (32 * h)) & 0xFFFFFFFFull) == 0;
+        __syncthreads();
+        asm volatile("" : "+v"(lane));
+        // y = L^-1 h; v = y + z; x = L^-T v (columns of L read from LDS)
+        Tacc acc = hh[r], y = (Tacc)0;
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const Tacc yq = half_bcast(acc, q, h) * iv[q];
+            y = r == q ? yq : y;
+            acc = r > q ? acc - rr[q] * yq : acc;
+        }
+        const Tacc v = r < K ? y + zz[r] : (Tacc)0;
+        Tacc cc[KP];
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            const Tacc v2 = A[q * LDL + r];
+            cc[q] = q >= r ? v2 : (Tacc)0;
+            asm volatile("" : "+v"(cc[q]));
+        }
+        acc = v;
+        Tacc x = (Tacc)0;
+#pragma unroll
+        for (int q = KP - 1; q >= 0; --q) {
+            const Tacc xq = half_bcast(acc, q, h) * iv[q];
+            x = r == q ? xq : x;
+            acc = r < q ? acc - cc[q] * xq : acc;
+        }
+        if (valid && !ok) {
+            if (r == 0) {
+                if (a.fb_list) {
+                    const int slot = atomicAdd(a.fb_count, 1);
+                    a.fb_list[slot] = make_int2(item.x, n);
+                    atomicAdd(a.fb_total, 1);
+                } else {
+                    atomicAdd(a.nonpd, 1);
+                }
+            }
+        }
+        const bool wr = valid && ok;
+        const Tacc xv = r < K ? x : (Tacc)0;
+        Ts *self = reinterpret_cast<Ts *>(a.self);
+        if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
+        if (wr && sample && r < a.ks_sample)
+            reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
+        if (a.sse_col) {
+            // the column's residual SSE in closed form (as in the wave kernel), FP64
+            __syncthreads();
+            zz[r] = r < K ? (Tacc)elem_to_d(elem_from<Ts>((double)xv)) : (Tacc)0;
+            __syncthreads();
+            const double tauv = (double)tau;
+            double u = 0.0;
+            for (int p = r; p < KP; ++p) u += (double)A[p * LDL + r] * (double)zz[p];
+            double sacc = u * u - 2.0 * tauv * (double)hr[r] * (double)zz[r];
+            for (int q = r; q < npk; q += 32) {
+                const int ra = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f + 1e-3f);
+                const int cb = q - ra * (ra + 1) / 2;
+                sacc -= (ra == cb ? 1.0 : 2.0) * pr[q] * (double)zz[ra] * (double)zz[cb];
+            }
+            sacc = group_sum1(sacc, 32);
+            if (wr && r < 4)
+                a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? a.colsq[sd.self_off + n] + sacc / tauv : 0.0;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // k_sse: residual SSE of every column of a column tile (the same per-column
 // slots the fused column pass writes), for a tau step on its own.
 // --------------------------------------------------------------------------
@@ -2112,6 +2349,16 @@ static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipS
         break;
     case kPFB32: hipLaunchKernelGGL((k_update_wave<KP, kPFB32, false>), dim3(grid), dim3(64), 0, s, a); break;
     case kPFB16: hipLaunchKernelGGL((k_update_wave<KP, kPFB16, false>), dim3(grid), dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    switch (prec) {
+    case kP32: hipLaunchKernelGGL((k_update_duo<kP32>), dim3(grid), dim3(64), 0, s, a); break;
+    case kPBF: hipLaunchKernelGGL((k_update_duo<kPBF>), dim3(grid), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

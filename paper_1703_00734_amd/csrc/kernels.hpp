@@ -182,6 +182,9 @@ struct PredictArgs {
 
 hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t ntiles,
                              hipStream_t s);
+// Two entities with at most 16 entries per wavefront, 16 < K <= 32, FP32 or
+// BF16 state (items in pairs: grid counts pairs).
+hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
 // vgram: BF16 state with K > 16 takes the VALU-Gram kernel instead of the MFMA one
 hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
                               bool vgram = false);

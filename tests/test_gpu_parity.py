@@ -177,10 +177,12 @@ def test_tau_draw(precision):
     assert tg == pytest.approx(blk["tau"], rel=1e-12 if precision == "fp64" else 1e-6)
 
 
-def test_fp32_fallback_path_redoes_rows_in_fp64():
+@pytest.mark.parametrize("K", [10, 32])
+def test_fp32_fallback_path_redoes_rows_in_fp64(K):
     """pivot_theta close to 1 fails every FP32 pivot test: every row is redone by
-    the FP64 pass, which then matches the oracle to FP32 input rounding."""
-    K = 10
+    the FP64 pass, which then matches the oracle to FP32 input rounding (K = 32:
+    light rows fail in the two-per-wavefront kernel, the others in the
+    wavefront kernel)."""
     d = small_data(K, seed=5)
     g, o = pair(d, K, "fp32", pivot_theta=0.9999)
     g.pp_stage(1, 0)
