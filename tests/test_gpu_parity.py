@@ -270,19 +270,21 @@ def test_fp64_chain_tracks_oracle_1x1():
     np.testing.assert_allclose(pg, po, rtol=1e-5, atol=1e-5)
 
 
-@pytest.mark.parametrize("IJ,order,K", [((2, 2), "random", 6), ((3, 2), "decreasing", 6), ((2, 1), "given", 6),
-                                        ((2, 3), "random", 5)])
-def test_fp64_pp_stages_track_oracle(IJ, order, K):
+@pytest.mark.parametrize("IJ,order,K,sweeps", [((2, 2), "random", 6, 8), ((3, 2), "decreasing", 6, 8),
+                                               ((2, 1), "given", 6, 8), ((2, 3), "random", 5, 8),
+                                               ((2, 2), "random", 17, 40)])
+def test_fp64_pp_stages_track_oracle(IJ, order, K, sweeps):
     """PP stages 1-3 with propagated per-row priors, moment matching, Algorithm 2
     aggregation (with its eigenvalue corrections) and prediction, FP64,
-    identical noise."""
+    identical noise.  K = 17 keeps more samples than 2K, so that moment matching
+    is not ridged and its precisions are well conditioned."""
     d = small_data(K, seed=7, N=300, D=200, nnz=12000, empty_rows=0)
     I, J = IJ
-    g, o = pair(d, K, "fp64", I=I, J=J, order=order, burnin=2, thin=1, max_kept=8)
+    g, o = pair(d, K, "fp64", I=I, J=J, order=order, burnin=2, thin=1, max_kept=sweeps)
     for s in (1, 2, 3):
-        g.pp_stage(s, 8)
+        g.pp_stage(s, sweeps)
         if o.stage_blocks(s):
-            o.run_stage(s, 8)
+            o.run_stage(s, sweeps)
     for b in range(I * J):
         for side, key in ((0, "x"), (1, "w")):
             mg, Lg = g.get_mm(b, side)
