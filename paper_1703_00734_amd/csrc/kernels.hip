@@ -1246,11 +1246,10 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
 // --------------------------------------------------------------------------
 constexpr int kDuoNnz = 16;
 
-// Value of lane 32h + q for the lanes of half h (q uniform).
-__device__ __forceinline__ float half_bcast(float v, int q, int h) {
-    const float lo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
-    const float hi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32 + q));
-    return h ? hi : lo;
+// Value of lane 32h + q for the lanes of half h (q uniform; hb = 128 h, the
+// byte address of the half's first lane): one cross-lane permute.
+__device__ __forceinline__ float half_bcast(float v, int q, int hb) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(hb + 4 * q, __float_as_int(v)));
 }
 
 template <int P>
@@ -1371,9 +1370,14 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         __syncthreads();
 
         // left-looking Cholesky, row r in registers, rows of L broadcast from LDS
-        // (L overlays A: every row is read before the first write)
+        // (L overlays A: every row is read before the first write).  Each phase
+        // derives its lane masks from a fresh opaque lane index, so that none is
+        // kept live (in scalar registers) across phases.
         asm volatile("" : "+v"(lane));
         Tacc rr[KP];
+        bool ok;
+        {
+        const int r = lane & 31, h = lane >> 5;
 #pragma unroll
         for (int j = 0; j < KP; ++j) {
             const Tacc v = A[r * LDL + j];
@@ -1396,7 +1400,7 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
                 if ((p & 15) == 15) __builtin_amdgcn_sched_barrier(0);
             }
             const Tacc sk = s0 + s1;
-            const Tacc dk = half_bcast(sk, k, h);
+            const Tacc dk = half_bcast(sk, k, 128 * h);
             mybad = r == k ? (int)!(sk > theta * d0) : mybad;
             Tacc lkk, inv;
             pivot_of(dk > (Tacc)0 ? dk : (Tacc)1, lkk, inv);
@@ -1409,32 +1413,36 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         }
         iv[r] = myinv;
         const uint64_t bad = __ballot(mybad);
-        const bool ok = fits && ((bad >> (32 * h)) & 0xFFFFFFFFull) == 0;
+        ok = fits && ((bad >> (32 * h)) & 0xFFFFFFFFull) == 0;
         __syncthreads();
         asm volatile("" : "+v"(lane));
+        }
+        const int r2 = lane & 31, h2 = lane >> 5;
         // y = L^-1 h; v = y + z; x = L^-T v (columns of L read from LDS)
-        Tacc acc = hh[r], y = (Tacc)0;
+        Tacc acc = hh[r2], y = (Tacc)0;
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-            const Tacc yq = half_bcast(acc, q, h) * iv[q];
-            y = r == q ? yq : y;
-            acc = r > q ? acc - rr[q] * yq : acc;
+            const Tacc yq = half_bcast(acc, q, 128 * h2) * iv[q];
+            y = r2 == q ? yq : y;
+            acc = r2 > q ? acc - rr[q] * yq : acc;
         }
-        const Tacc v = r < K ? y + zz[r] : (Tacc)0;
+        const Tacc v = r2 < K ? y + zz[r2] : (Tacc)0;
+        asm volatile("" : "+v"(lane));
+        const int r3 = lane & 31, h3 = lane >> 5;
         Tacc cc[KP];
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-            const Tacc v2 = A[q * LDL + r];
-            cc[q] = q >= r ? v2 : (Tacc)0;
+            const Tacc v2 = A[q * LDL + r3];
+            cc[q] = q >= r3 ? v2 : (Tacc)0;
             asm volatile("" : "+v"(cc[q]));
         }
         acc = v;
         Tacc x = (Tacc)0;
 #pragma unroll
         for (int q = KP - 1; q >= 0; --q) {
-            const Tacc xq = half_bcast(acc, q, h) * iv[q];
-            x = r == q ? xq : x;
-            acc = r < q ? acc - cc[q] * xq : acc;
+            const Tacc xq = half_bcast(acc, q, 128 * h3) * iv[q];
+            x = r3 == q ? xq : x;
+            acc = r3 < q ? acc - cc[q] * xq : acc;
         }
         if (valid && !ok) {
             if (r == 0) {
