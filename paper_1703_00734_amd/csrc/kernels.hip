@@ -812,6 +812,82 @@ __device__ __forceinline__ bool chol_rows(const T *sA, int ld, T *sL, int ldl, c
     return __ballot(mybad) == 0;
 }
 
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
+
+// chol_rows for KP = 64 in FP32 with the second panel's update on MFMA: steps
+// 0..31 as in chol_rows; then S = L21 L21^T (L21 = rows 32..63, columns 0..31
+// of L) by sixteen v_mfma_f32_32x32x2_f32, subtracted from the rows of lanes
+// 32..63; then steps 32..63 need only the columns 32..k-1 in their dot products.
+// The product's 32 x 32 result passes through the still unwritten block
+// (rows and columns 32..63) of sL.  Same contract as chol_rows.
+__device__ __forceinline__ bool chol_rows64_mfma(const float *sA, int ld, float *sL, int ldl, const float *diag0,
+                                                 float *sinv, float theta, int lane, int z0, float (&r)[64]) {
+    constexpr int KP = 64;
+    const int row = lane;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        const float v = sA[row * ld + j];
+        r[j] = j <= lane ? v : 0.0f;
+        asm volatile("" : "+v"(r[j]));
+    }
+    const float d0 = diag0[row];
+    __syncthreads();                        // all of A read before L overlays it
+    int mybad = 0;
+    float myinv = 1.0f;
+    auto step = [&](const int k, const int p0) __attribute__((always_inline)) {
+        float s0 = r[k], s1 = 0.0f;
+        const float *lk = sL + z0 + k * ldl;
+#pragma unroll
+        for (int p = p0; p < k; ++p) {
+            if (p & 1) s1 -= r[p] * lk[p];
+            else s0 -= r[p] * lk[p];
+            if ((p & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+        }
+        const float sk = s0 + s1;
+        const float dk = wave_bcast(sk, k);
+        mybad = lane == k ? (int)!(sk > theta * d0) : mybad;
+        float lkk, inv;
+        pivot_of(dk > 0.0f ? dk : 1.0f, lkk, inv);
+        myinv = lane == k ? inv : myinv;
+        r[k] = lane == k ? lkk : sk * inv;
+        sL[lane * ldl + k] = r[k];
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" : "+v"(r[k]), "+v"(myinv), "+v"(mybad));
+        __builtin_amdgcn_sched_barrier(0);
+    };
+#pragma unroll
+    for (int k = 0; k < 32; ++k) step(k, 0);
+    // S = L21 L21^T: operand of lane l at pair s is L[32 + l % 32][2s + l / 32]
+    // (the same register serves as A and as B)
+    f32x16_t acc = {};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const float up = __int_as_float(__builtin_amdgcn_ds_bpermute(4 * ((lane + 32) & 63), __float_as_int(r[2 * s])));
+        const float op = lane < 32 ? up : r[2 * s + 1];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(op, op, acc, 0, 0, 0);
+    }
+    {
+        const int col = lane & 31;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int rw = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+            sL[(32 + rw) * ldl + 32 + col] = acc[v];
+        }
+    }
+    __syncthreads();
+    if (lane >= 32) {
+#pragma unroll
+        for (int j = 32; j < KP; ++j) r[j] -= sL[lane * ldl + j];
+    }
+#pragma unroll
+    for (int j = 32; j < KP; ++j) asm volatile("" : "+v"(r[j]));
+    __syncthreads();                        // the product is read before steps 32.. overwrite it
+#pragma unroll
+    for (int k = 32; k < KP; ++k) step(k, 32);
+    sinv[lane] = myinv;
+    return __ballot(mybad) == 0;
+}
+
 // Factor A = L L^T and solve x = L^-T (L^-1 h + z) in registers (chol_rows,
 // then a forward solve with row ownership and a backward solve that reads
 // columns of L from LDS).  In: sA (lower, row stride ld, KP x KP with identity
@@ -834,7 +910,11 @@ __device__ __forceinline__ bool factor_solve_regs(const T *sA, int ld, T *sL, in
     const bool own = lane < KP;
     const int row = own ? lane : KP - 1;
     T r[KP];
-    const bool ok = chol_rows<KP, T>(sA, ld, sL, ldl, diag0, sinv, theta, lane, z0, r);
+    bool ok;
+    if constexpr (KP == 64 && sizeof(T) == 4)
+        ok = chol_rows64_mfma(sA, ld, sL, ldl, diag0, sinv, theta, lane, z0, r);
+    else
+        ok = chol_rows<KP, T>(sA, ld, sL, ldl, diag0, sinv, theta, lane, z0, r);
     __syncthreads();
     // each phase compares against a fresh opaque copy of the lane index, so
     // that no lane mask is shared (and kept live) across phases
@@ -888,7 +968,6 @@ template <typename T> __device__ __forceinline__ T to_acc(uint16_t v) { return (
 // k_update_wave: one wavefront per entity, any K <= KP.
 // --------------------------------------------------------------------------
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16_t;
 typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
 
 // LDS staging of mfma_gram: the rows of one chunk of 32 entries (16-byte
