@@ -954,11 +954,6 @@ __device__ __forceinline__ bool factor_solve_regs(const T *sA, int ld, T *sL, in
     return ok;
 }
 
-__device__ __forceinline__ void unrank_tri(int q, int &r, int &c) {
-    r = 0;
-    while ((r + 1) * (r + 2) / 2 <= q) ++r;
-    c = q - r * (r + 1) / 2;
-}
 
 template <typename T> __device__ __forceinline__ T to_acc(float v) { return (T)v; }
 template <typename T> __device__ __forceinline__ T to_acc(double v) { return (T)v; }
@@ -1820,35 +1815,27 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
         nw_noise(jb, K, a.nu0, t_sw, a.k0, a.k1, const_cast<double *>(nz), lane, 0, 64);
         __syncthreads();
     }
-    // 1. the side's sums (reduced in fixed order by the statistics kernel) and
-    //    identity padding beyond K
-    for (int q = lane; q < KP * KP; q += 64) {
-        const int r = q / KP, c = q - r * KP;
-        S0[r * LD + c] = (double)(r == c);
-    }
-    __syncthreads();
-    for (int p = lane; p < npair; p += 64) {
-        const double v = a.part[(int64_t)jb.part_begin * npair + p];
-        if (p < K) {
-            sx[p] = v;
-        } else {
-            int r, c;
-            unrank_tri(p - K, r, c);
-            S0[r * LD + c] = v;
-            S0[c * LD + r] = v;
-        }
-    }
+    // 1. the side's sums (reduced in fixed order by the statistics kernel):
+    //    sum x, then sum x x^T packed lower
+    const double *part = a.part + (int64_t)jb.part_begin * npair;
+    if (lane < K) sx[lane] = part[lane];
     __syncthreads();
     const double N = (double)jb.n;
     const double beta_s = a.beta0 + N;
     if (lane < K) mus[lane] = (a.beta0 * a.mu0[lane] + sx[lane]) / beta_s;
-    // 2. W*^-1 = W0^-1 + (sum x x^T - N xbar xbar^T) + beta0 N / beta* (mu0 - xbar)(mu0 - xbar)^T
+    // 2. W*^-1 = W0^-1 + (sum x x^T - N xbar xbar^T) + beta0 N / beta* (mu0 - xbar)(mu0 - xbar)^T,
+    //    identity padding beyond K (the KP x KP grid, no index unranking)
     const double coef = a.beta0 * N / beta_s;
-    for (int q = lane; q < K * K; q += 64) {
-        const int r = q / K, c = q - r * K;
-        const double xr = sx[r] / N, xc = sx[c] / N;
-        const double ns = S0[r * LD + c] - N * xr * xc;
-        S0[r * LD + c] = a.W0inv[r * K + c] + ns + coef * (a.mu0[r] - xr) * (a.mu0[c] - xc);
+    for (int q = lane; q < KP * KP; q += 64) {
+        const int r = q / KP, c = q - (q / KP) * KP;
+        double v = (double)(r == c);
+        if (r < K && c < K) {
+            const double sxx = part[K + (r >= c ? tri(r, c) : tri(c, r))];
+            const double xr = sx[r] / N, xc = sx[c] / N;
+            const double ns = sxx - N * xr * xc;
+            v = a.W0inv[r * K + c] + ns + coef * (a.mu0[r] - xr) * (a.mu0[c] - xc);
+        }
+        S0[r * LD + c] = v;
     }
     __syncthreads();
     if (own) dg[lane] = S0[lane * LD + lane];
@@ -1857,18 +1844,15 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
     double rr[KP];
     bool ok = chol_rows<KP, double>(S0, LD, S1, LD, dg, sinv, 0.0, lane, z0, rr);
     // 4. Bartlett factor A (lower) in S2: A_kk^2 ~ chi2(nu* - k) for k < K,
-    //    A_kl ~ N(0, 1) below the diagonal, identity padding
-    for (int q = lane; q < KP * KP; q += 64) {
-        const int r = q / KP, c = q - r * KP;
-        S2[r * LD + c] = (r == c && r >= K) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    if (lane < K) S2[lane * LD + lane] = nz[lane];
+    //    A_kl ~ N(0, 1) below the diagonal (row-major order of the strict lower
+    //    triangle: entry (r, c) is number tri(r - 1, c)), identity padding
     const int noff = K * (K - 1) / 2;
-    for (int q = lane; q < noff; q += 64) {
-        int r, cc;
-        unrank_tri(q, r, cc);                  // strict lower, row-major: row r+1, column cc
-        S2[(r + 1) * LD + cc] = nz[K + q];
+    for (int q = lane; q < KP * KP; q += 64) {
+        const int r = q / KP, c = q - (q / KP) * KP;
+        double v = 0.0;
+        if (r == c) v = r < K ? nz[r] : 1.0;
+        else if (c < r && r < K) v = nz[K + tri(r - 1, c)];
+        S2[r * LD + c] = v;
     }
     __syncthreads();
     asm volatile("" : "+v"(lane));
@@ -1905,13 +1889,15 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
         __syncthreads();
         for (int s = 0; s < KP; ++s) {
             const double *bs = S2 + z0 + s * LD;
-            double a0 = 0.0, a1 = 0.0;
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
-            for (int c = 0; c < KP; ++c) {
-                if (c & 1) a1 += br[c] * bs[c];
-                else a0 += br[c] * bs[c];
+            for (int c = 0; c < KP; c += 4) {
+                a0 += br[c] * bs[c];
+                if (c + 1 < KP) a1 += br[c + 1] * bs[c + 1];
+                if (c + 2 < KP) a2 += br[c + 2] * bs[c + 2];
+                if (c + 3 < KP) a3 += br[c + 3] * bs[c + 3];
             }
-            const double v = a0 + a1;
+            const double v = (a0 + a2) + (a1 + a3);
             if (own) S0[lane * LD + s] = v;
             if (lane < K && s < K) outL[lane * K + s] = v;
         }
@@ -1955,10 +1941,9 @@ __device__ __forceinline__ void nw_draw(const HyperArgs &a, const HyperJob &jb, 
         packed[K * (K + 1) / 2 + lane] = s;
         packed[K * (K + 1) / 2 + K + lane] = sx[lane];
     }
-    for (int q = lane; q < K * (K + 1) / 2; q += 64) {
-        int r, c;
-        unrank_tri(q, r, c);
-        packed[q] = S0[r * LD + c];
+    for (int q = lane; q < KP * KP; q += 64) {
+        const int r = q / KP, c = q - (q / KP) * KP;
+        if (c <= r && r < K) packed[tri(r, c)] = S0[r * LD + c];
     }
     if (!ok && lane == 0) atomicAdd(a.nonpd, 1);
 }
@@ -2026,12 +2011,12 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
 // Lambda_hat = L^-T L^-1, eta = Lambda_hat mu_hat.  Output row:
 // [Lambda_hat packed lower, eta, mu_hat].
 // --------------------------------------------------------------------------
-template <typename Ts>
+template <typename Ts, int KP>
 __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
-    constexpr int LD = 64;
-    __shared__ double sig[64 * LD];
-    __shared__ double lin[64 * LD];
-    __shared__ double mu[64];
+    constexpr int LD = KP + 1;                     // LDS sized to K: more entities per CU
+    __shared__ double sig[KP * LD];
+    __shared__ double lin[KP * LD];
+    __shared__ double mu[KP];
     __shared__ int flag;
     const int lane = threadIdx.x;
     const int K = a.K, S = a.S;
@@ -2108,10 +2093,9 @@ __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
             }
         }
         __syncthreads();
-        for (int q = lane; q < kk2; q += 64) {
-            int r, c;
-            unrank_tri(q, r, c);
-            out[q] = lin[r * LD + c];
+        for (int q = lane; q < K * K; q += 64) {
+            const int r = q / K, c = q - (q / K) * K;
+            if (c <= r) out[tri(r, c)] = lin[r * LD + c];
         }
         if (lane < K) {
             double s = 0.0;
@@ -2562,10 +2546,17 @@ hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s) {
 hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s) {
     if (a.nitems <= 0) return hipSuccess;
     const int g = grid_for(a.nitems, 1, 65536);
-    if (prec == kP64)
-        hipLaunchKernelGGL(k_mm<double>, dim3(g), dim3(64), 0, s, a);
-    else
-        hipLaunchKernelGGL(k_mm<float>, dim3(g), dim3(64), 0, s, a);
+    const bool d = prec == kP64;
+    if (a.K <= 16) {
+        if (d) hipLaunchKernelGGL((k_mm<double, 16>), dim3(g), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_mm<float, 16>), dim3(g), dim3(64), 0, s, a);
+    } else if (a.K <= 32) {
+        if (d) hipLaunchKernelGGL((k_mm<double, 32>), dim3(g), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_mm<float, 32>), dim3(g), dim3(64), 0, s, a);
+    } else {
+        if (d) hipLaunchKernelGGL((k_mm<double, 64>), dim3(g), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_mm<float, 64>), dim3(g), dim3(64), 0, s, a);
+    }
     return hipGetLastError();
 }
 
