@@ -136,18 +136,21 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1) / steps
-        g.kernel_times()                     # drop what earlier stages recorded
+        before = g.kernel_times()            # totals so far (earlier stages)
         g.enable_timing(True)
         g.gibbs_sweep(steps)
         torch.cuda.synchronize()
         g.enable_timing(False)
+        after = g.kernel_times()
+        ktimes = {k: (after[k][0] - before.get(k, (0, 0.0))[0], after[k][1] - before.get(k, (0, 0.0))[1])
+                  for k in after}
         row_updates, ratings = g.stage_work()
         print("bench: stage %d timed, %.4f ms per sweep" % (s, ms), file=sys.stderr, flush=True)
         if s != stages[-1] and extra:
             g.gibbs_sweep(extra)
             torch.cuda.synchronize()
         per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
-                            ktimes=g.kernel_times(), row_updates=row_updates, ratings=ratings,
+                            ktimes=ktimes, row_updates=row_updates, ratings=ratings,
                             schedule=g.schedule())
     out = dict(per_stage=per_stage, stats=g.stats())
     g.close()

@@ -225,9 +225,10 @@ bmf_status bmf_get_stats(bmf_ctx *c, int64_t *fallback_rows, int64_t *nonpd_rows
                          int64_t *mm_ridged, int64_t *agg_corrections);
 
 /* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
- * the context's stream (sweeps are then launched eagerly, not from the graph); bmf_kernel_times returns, for up to n kernel classes,
- * their names (static strings), launch counts and total milliseconds, and the
- * number of classes in *count. */
+ * the context's stream (sweeps are then launched eagerly, not from the graph).
+ * bmf_kernel_times returns, for up to n kernel classes, their names (static
+ * strings), the launch counts and total milliseconds accumulated since the
+ * context was created, and the number of classes in *count. */
 bmf_status bmf_enable_timing(bmf_ctx *c, int32_t on);
 bmf_status bmf_kernel_times(bmf_ctx *c, int32_t n, const char **names, int64_t *launches,
                             double *ms, int32_t *count);
