@@ -25,6 +25,9 @@ if ROOT not in sys.path:
 
 METRIC = "row-updates/s and ratings/s per Gibbs sweep, batched BF16 vs plain FP32, equal RMSE"
 HBM_PEAK_GBS = 8000.0
+# entities with at most this many entries under a propagated prior take the
+# low-rank kernel (the library's own threshold)
+LOWRANK_NNZ = 4
 
 
 def parse():
@@ -45,16 +48,23 @@ def parse():
     return p.parse_args()
 
 
-def algorithmic_bytes(kind, M, n, K, state_bytes, kept, n_prop=0):
+def algorithmic_bytes(kind, M, n, K, state_bytes, kept, n_prop=0, n_empty=0, n_lowrank=0):
     """Bytes one update pass must move: per entry a column index and a value
     (8 B) plus the K-element factor row it gathers; per entity its pointer
     pair and its written state row (and sample row when the sweep is kept);
-    per entity under a propagated prior (PP stages 2-3) its packed FP64 prior,
-    K(K+1)/2 precision entries and K of the precision-weighted mean."""
+    per entity under a propagated prior (PP stages 2-3) that is factored its
+    packed FP64 prior, K(K+1)/2 precision entries and K of the
+    precision-weighted mean; per entity with no entries under a propagated
+    prior whose factor was computed at stage begin (n_empty) the FP32 factor,
+    K(K+1)/2 entries, and the K FP64 entries of the mean; per entity with a
+    few entries under such a prior (n_lowrank) the factor, the mean and the
+    precision-weighted mean."""
     b = M * (8 + K * state_bytes) + n * (8 + K * state_bytes)
     if kept:
         b += n * K * 4
     b += n_prop * (K * (K + 1) // 2 + K) * 8
+    b += n_empty * (K * (K + 1) // 2 * 4 + K * 8)
+    b += n_lowrank * (K * (K + 1) // 2 * 4 + 2 * K * 8)
     return b
 
 
@@ -145,13 +155,27 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
         ktimes = {k: (after[k][0] - before.get(k, (0, 0.0))[0], after[k][1] - before.get(k, (0, 0.0))[1])
                   for k in after}
         row_updates, ratings = g.stage_work()
+        # entities with no entries (or at most LOWRANK_NNZ) under a propagated
+        # prior: the prior-factor paths take them in FP32/BF16 passes with K > 16
+        empty, lowrank = [0, 0], [0, 0]
+        if precision != "fp64" and d["K"] > 16 and cfg["I"] * cfg["J"] > 1:
+            for b in range(g.nblocks()):
+                info = g.block_info(b)
+                if info["stage"] != s:
+                    continue
+                bi, bj = divmod(b, cfg["J"])
+                for side, prop in ((0, bj > 0), (1, bi > 0)):
+                    if prop:
+                        deg = np.diff(g.block_csr(b, side)[0])
+                        empty[side] += int(np.count_nonzero(deg == 0))
+                        lowrank[side] += int(np.count_nonzero((deg >= 1) & (deg <= LOWRANK_NNZ)))
         print("bench: stage %d timed, %.4f ms per sweep" % (s, ms), file=sys.stderr, flush=True)
         if s != stages[-1] and extra:
             g.gibbs_sweep(extra)
             torch.cuda.synchronize()
         per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
                             ktimes=ktimes, row_updates=row_updates, ratings=ratings,
-                            schedule=g.schedule())
+                            schedule=g.schedule(), empty_prop=empty, lowrank_prop=lowrank)
     out = dict(per_stage=per_stage, stats=g.stats())
     g.close()
     if rmse:
@@ -265,11 +289,13 @@ def main():
         # entities of the pass: rows (or columns) of every block of the stage
         side = 0 if dom == "update_rows" else 1
         n = rows_cols_of_stage(d, cfg, head)[side]
-        n_prop = rows_cols_of_stage(d, cfg, head, propagated=True)[side]
+        n_empty = m["empty_prop"][side]
+        n_lowrank = m["lowrank_prop"][side]
+        n_prop = rows_cols_of_stage(d, cfg, head, propagated=True)[side] - n_empty - n_lowrank
         # a pass is one launch (K <= 16) or a few: heavy entities, light ones
         # (K > 16), segment Grams apart; the rate is the pass's bytes over the
         # pass's summed launch time
-        per_pass = algorithmic_bytes(dom, M, n, K, state_bytes, True, n_prop)
+        per_pass = algorithmic_bytes(dom, M, n, K, state_bytes, True, n_prop, n_empty, n_lowrank)
         passes = a.steps
         # the partial Grams of heavy entities (both passes) count against this pass
         seg_ms = kt.get("gram_segments", (0, 0.0))[1]

@@ -46,14 +46,14 @@ int64_t kHyPacked(const Layout &L);
 
 // Sizes of everything the device holds, computable from the configuration.
 struct Layout {
-    int32_t K = 0, kc = 0, prec = 0, ks_m = 0, ks_p = 0, prow = 0, hy = 0, npair = 0;
+    int32_t K = 0, kc = 0, prec = 0, ks_m = 0, ks_p = 0, prow = 0, hy = 0, npair = 0, pfrow = 0;
     int64_t nb = 0, E_r = 0, E_c = 0, Emax = 0, Pmax = 0;
     int64_t vs = 0, ss = 0, sp = 0;  // value / state / sample element bytes
     // byte offsets
     int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, ord, X, W, hyper, tau, mu0,
         W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
-        m_items, m_items2, m_stats, m_hyper, m_mmout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
+        m_items, m_items2, m_stats, m_hyper, m_mmout, pfac, m_pfout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
         p_out, total;
     int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
     bool mfma = false;
@@ -123,6 +123,11 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.mu0 = take(8 * c.K);
     L.W0inv = take(8 * c.K * c.K);
     L.mm = take(8 * (L.E_r + L.E_c) * L.prow);
+    // prior factors of the moment-matched rows that seed later stages (the rows
+    // of blocks (i, 0) and the columns of blocks (0, j): N + D rows), for the
+    // empty-entity path of FP32/BF16 passes on the wavefront kernels
+    if (!fp64 && L.kc >= 32 && L.nb > 1) L.pfrow = (int32_t)align_up(c.K * (c.K + 1) / 2 + 1, 4);
+    L.pfac = take(4 * ((int64_t)c.N + c.D) * L.pfrow);
     L.agg_x = take(8 * c.N * c.K);
     L.agg_w = take(8 * c.D * c.K);
     L.sample = take(L.sp * (int64_t)c.max_kept * L.Emax * L.ks_p);
@@ -150,6 +155,7 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.m_stats = take(sizeof(StatsJob) * L.n_stats_cap);
     L.m_hyper = take(sizeof(HyperJob) * 3 * L.nb);
     L.m_mmout = take(sizeof(double *) * 2 * L.nb);
+    L.m_pfout = take(sizeof(float *) * 2 * L.nb);
     L.m_agg_jobs = take(sizeof(AggJob) * (c.I + c.J));
     L.m_agg_items = take(sizeof(int2) * (c.N + c.D));
     L.p_xslot = take(8 * kPredictChunk);
@@ -174,6 +180,14 @@ struct StageLists {
     // the same per block (block item lists are in decreasing degree order)
     int64_t i_row_light = 0, i_col_light = 0;
     std::vector<int64_t> row_item_light, col_item_light;
+    // first item of the heavy-first order (and per block) that the low-rank
+    // kernel takes (at most lowrank_max_nnz() entries under a per-row prior with
+    // a factor; these sort after every other item, by decreasing degree), and
+    // the first of those that the empty-entity kernel takes (no entries)
+    int64_t i_row_lowrank = 0, i_col_lowrank = 0, i_row_empty = 0, i_col_empty = 0;
+    std::vector<int64_t> row_item_lowrank, col_item_lowrank, row_item_empty, col_item_empty;
+    // per side: prior-factor rows this stage's moment matching writes (or null)
+    std::vector<float *> pfout;
     std::vector<int64_t> row_item_begin, col_item_begin;
     std::vector<int2> ents;                         // every (side, entity) of the stage
     // MFMA path: segments of heavy entities ([rows grouped | cols grouped]) and,
@@ -373,6 +387,18 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
     double *mm = c->dev<double>(L.mm);
     double *tau = c->dev<double>(L.tau);
     S.sides.resize(2 * nbs);
+    S.pfout.assign(2 * nbs, nullptr);
+    // prior-factor row of the first row of row block i (columns: N + first
+    // column of column block j)
+    float *pf = L.pfrow ? c->dev<float>(L.pfac) : nullptr;
+    std::vector<int64_t> pfx(P.I + 1, 0), pfw(P.J + 1, 0);
+    for (const PlanBlock &B : P.blocks) {
+        if (B.j == 0) pfx[B.i + 1] = B.R;
+        if (B.i == 0) pfw[B.j + 1] = B.C;
+    }
+    for (int32_t i = 0; i < P.I; ++i) pfx[i + 1] += pfx[i];
+    pfw[0] = c->cfg.N;
+    for (int32_t j = 0; j < P.J; ++j) pfw[j + 1] += pfw[j];
     int64_t soff = 0;
     for (int32_t k = 0; k < nbs; ++k) {
         const int32_t b = S.blocks[k];
@@ -386,6 +412,7 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         soff += B.R;
         r.prior = xp ? mm + c->x_off[B.i * J + 0] * L.prow : hyper + ((int64_t)b * 2 + 0) * L.hy + kHyPacked(L);
         r.tau = tau + b;
+        r.pfac = xp && pf ? pf + pfx[B.i] * L.pfrow : nullptr;
         r.n = (int32_t)B.R;
         r.per_row = xp;
         r.c2 = counter_word(b, kRow);
@@ -398,6 +425,7 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         soff += B.C;
         q.prior = wp ? mm + (L.E_r + c->w_off[0 * J + B.j]) * L.prow : hyper + ((int64_t)b * 2 + 1) * L.hy + kHyPacked(L);
         q.tau = tau + b;
+        q.pfac = wp && pf ? pf + pfw[B.j] * L.pfrow : nullptr;
         q.n = (int32_t)B.C;
         q.per_row = wp;
         q.c2 = counter_word(b, kCol);
@@ -405,6 +433,8 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         q.block = b;
         S.sides[k] = r;
         S.sides[nbs + k] = q;
+        if (pf && s < 3 && B.j == 0) S.pfout[k] = pf + pfx[B.i] * L.pfrow;
+        if (pf && s < 3 && B.i == 0) S.pfout[nbs + k] = pf + pfw[B.j] * L.pfrow;
         S.row_updates += B.R + B.C;
         S.ratings += B.M;
         S.row_ents += B.R;
@@ -423,6 +453,8 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         const bool rows = pass == 0;
         std::vector<int2> igrp, sgrp;
         std::vector<int64_t> ideg;
+        std::vector<char> ifast;                    // few entries under a factored per-row prior
+        const int64_t nlr = lowrank_max_nnz();
         std::vector<int64_t> &ibeg = rows ? S.row_item_begin : S.col_item_begin;
         std::vector<int64_t> &sbeg = rows ? S.row_seg_begin : S.col_seg_begin;
         (rows ? S.s_row : S.s_col) = (int64_t)S.segs.size();
@@ -435,12 +467,20 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
             ibeg.push_back((int64_t)igrp.size());
             sbeg.push_back((int64_t)slot);
             std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
+            std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
+            std::vector<int64_t> &bempty = rows ? S.row_item_empty : S.col_item_empty;
             blight.push_back(-1);
+            blowr.push_back(-1);
+            bempty.push_back(-1);
+            const bool fast = S.sides[side].pfac != nullptr;
             for (int32_t e : (rows ? S.ord_row[k] : S.ord_col[k])) {
                 const int64_t deg = ptr[e + 1] - ptr[e];
                 if (blight.back() < 0 && deg <= kLightNnz) blight.back() = (int64_t)igrp.size();
+                if (fast && blowr.back() < 0 && deg <= nlr) blowr.back() = (int64_t)igrp.size();
+                if (fast && bempty.back() < 0 && deg == 0) bempty.back() = (int64_t)igrp.size();
                 igrp.push_back(make_int2(side, e));
                 ideg.push_back(deg);
+                ifast.push_back(fast && deg <= nlr);
                 if (mf && deg > kSegNnz) {
                     const int32_t nseg = (int32_t)((deg + kSegNnz - 1) / kSegNnz);
                     sgrp.push_back(make_int2(slot, nseg));
@@ -465,24 +505,42 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         sbeg.push_back((int64_t)slot);
         {
             std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
-            for (int32_t k = 0; k < nbs; ++k)
+            std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
+            std::vector<int64_t> &bempty = rows ? S.row_item_empty : S.col_item_empty;
+            for (int32_t k = 0; k < nbs; ++k) {
                 if (blight[k] < 0) blight[k] = ibeg[k + 1];
+                if (blowr[k] < 0) blowr[k] = ibeg[k + 1];
+                if (bempty[k] < 0) bempty[k] = ibeg[k + 1];
+            }
         }
+        // heavy-first: decreasing degree, the low-rank and empty-entity kernels'
+        // items after all others
         std::vector<int64_t> iperm(igrp.size());
         for (size_t q = 0; q < iperm.size(); ++q) iperm[q] = (int64_t)q;
-        std::stable_sort(iperm.begin(), iperm.end(), [&](int64_t a2, int64_t b2) { return ideg[a2] > ideg[b2]; });
+        std::stable_sort(iperm.begin(), iperm.end(), [&](int64_t a2, int64_t b2) {
+            if (ifast[a2] != ifast[b2]) return ifast[a2] < ifast[b2];
+            return ideg[a2] > ideg[b2];
+        });
         (rows ? S.i_row_blk : S.i_col_blk) = (int64_t)S.items.size();
         S.items.insert(S.items.end(), igrp.begin(), igrp.end());
         S.splits.insert(S.splits.end(), sgrp.begin(), sgrp.end());
         (rows ? S.i_row_heavy : S.i_col_heavy) = (int64_t)S.items.size();
         int64_t &light = rows ? S.i_row_light : S.i_col_light;
+        int64_t &lowr = rows ? S.i_row_lowrank : S.i_col_lowrank;
+        int64_t &empty = rows ? S.i_row_empty : S.i_col_empty;
         light = -1;
+        lowr = -1;
+        empty = -1;
         for (int64_t q : iperm) {
             if (light < 0 && ideg[q] <= kLightNnz) light = (int64_t)S.items.size();
+            if (lowr < 0 && ifast[q]) lowr = (int64_t)S.items.size();
+            if (empty < 0 && ifast[q] && ideg[q] == 0) empty = (int64_t)S.items.size();
             S.items.push_back(igrp[q]);
             S.splits.push_back(sgrp[q]);
         }
         if (light < 0) light = (int64_t)S.items.size();
+        if (lowr < 0) lowr = (int64_t)S.items.size();
+        if (empty < 0) empty = (int64_t)S.items.size();
     }
     S.s_end = (int64_t)S.segs.size();
     S.i_end = (int64_t)S.items.size();
@@ -617,6 +675,7 @@ static bmf_status upload_stage(bmf_ctx *c) {
         outs[nbs + k] = c->dev<double>(L.mm) + (L.E_r + c->w_off[b]) * L.prow;
     }
     if ((st = upload(c, L.m_mmout, outs.data(), outs.size() * sizeof(double *)))) return st;
+    if ((st = upload(c, L.m_pfout, S.pfout.data(), S.pfout.size() * sizeof(float *)))) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return BMF_OK;
 }
@@ -644,6 +703,7 @@ static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample, bool us
     a.ks_sample = L.ks_p;
     a.K = c->cfg.K;
     a.prow = L.prow;
+    a.pfrow = L.pfrow;
     a.t = t;
     a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
     a.k1 = (uint32_t)(c->cfg.seed >> 32);
@@ -726,46 +786,69 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         }
         // MFMA path: the light entities (at most kLightNnz entries, the tail of
         // each decreasing-degree range) run on the VALU-Gram kernel, which needs
-        // fewer registers and so keeps more entities in flight
-        std::vector<bool> vg(ranges.size(), false);
-        // 16 < K <= 32 in FP32 arithmetic: light entities two per wavefront
+        // fewer registers and so keeps more entities in flight; 16 < K <= 32 in
+        // FP32 arithmetic: light entities two per wavefront.  Entities with at
+        // most lowrank_max_nnz() entries under a factored per-row prior (the
+        // tail) take the low-rank kernel, those without entries (the very tail)
+        // the empty-entity kernel.
         const bool duo = L.kc == 32 && (c->prec() == kP32 || c->prec() == kPBF);
-        if (L.mfma || duo) {
-            std::vector<std::pair<int64_t, int64_t>> split;
-            std::vector<bool> svg;
-            for (size_t ri = 0; ri < ranges.size(); ++ri) {
-                int64_t light;
-                if (batched) {
-                    light = rows ? S.i_row_light : S.i_col_light;
-                } else {
-                    const int32_t q = k < 0 ? (int32_t)ri : k;
-                    light = (rows ? S.i_row_blk : S.i_col_blk) + (rows ? S.row_item_light : S.col_item_light)[q];
-                }
-                light = std::min(std::max(light, ranges[ri].first), ranges[ri].second);
-                split.push_back({ranges[ri].first, light});
-                svg.push_back(false);
-                split.push_back({light, ranges[ri].second});
-                svg.push_back(true);
-            }
-            ranges.swap(split);
-            vg.swap(svg);
-        }
+        const bool lsplit = L.mfma || duo;
+        enum { kWave = 0, kLight = 1, kLowRank = 2, kEmpty = 3 };
+        std::vector<std::pair<int64_t, int64_t>> split;
+        std::vector<int> kind;
         for (size_t ri = 0; ri < ranges.size(); ++ri) {
-            const auto &r = ranges[ri];
+            int64_t light, lowr, empty;
+            if (batched) {
+                light = rows ? S.i_row_light : S.i_col_light;
+                lowr = rows ? S.i_row_lowrank : S.i_col_lowrank;
+                empty = rows ? S.i_row_empty : S.i_col_empty;
+            } else {
+                const int32_t q = k < 0 ? (int32_t)ri : k;
+                const int64_t base = rows ? S.i_row_blk : S.i_col_blk;
+                light = base + (rows ? S.row_item_light : S.col_item_light)[q];
+                lowr = base + (rows ? S.row_item_lowrank : S.col_item_lowrank)[q];
+                empty = base + (rows ? S.row_item_empty : S.col_item_empty)[q];
+            }
+            const int64_t lo = ranges[ri].first, hi = ranges[ri].second;
+            lowr = std::min(std::max(lowr, lo), hi);
+            empty = std::min(std::max(empty, lowr), hi);
+            light = lsplit ? std::min(std::max(light, lo), lowr) : lowr;
+            split.push_back({lo, light});
+            kind.push_back(kWave);
+            split.push_back({light, lowr});
+            kind.push_back(kLight);
+            split.push_back({lowr, empty});
+            kind.push_back(kLowRank);
+            split.push_back({empty, hi});
+            kind.push_back(kEmpty);
+        }
+        for (size_t ri = 0; ri < split.size(); ++ri) {
+            const auto &r = split[ri];
             if (r.second <= r.first) continue;
-            const bool vgram = vg[ri];
             UpdArgs b = a;
             b.items = c->dev<int2>(L.m_items) + r.first;
             b.nitems = (int32_t)(r.second - r.first);
+            if (kind[ri] == kEmpty || kind[ri] == kLowRank) {
+                const int32_t per = 64 / L.kc;
+                const int32_t g = (int32_t)std::min<int64_t>((b.nitems + per - 1) / per, kWaveGridCap);
+                if (kind[ri] == kEmpty) {
+                    if ((st = timed(c, kcls, [&] { return launch_update_empty(L.kc, c->prec(), b, g, c->ls); })))
+                        return st;
+                } else if ((st = timed(c, kcls, [&] { return launch_update_lowrank(L.kc, c->prec(), b, g, c->ls); }))) {
+                    return st;
+                }
+                continue;
+            }
             if (L.mfma) {
                 b.splits = c->dev<int2>(L.m_splits) + r.first;
                 b.gpart = c->dev<float>(L.gpart);
             }
-            if (vgram && duo) {
+            if (kind[ri] == kLight && duo) {
                 const int32_t g = (int32_t)std::min<int64_t>((b.nitems + 1) / 2, kWaveGridCap);
                 if ((st = timed(c, kcls, [&] { return launch_update_duo(c->prec(), b, g, c->ls); }))) return st;
                 continue;
             }
+            const bool vgram = kind[ri] == kLight;
             const int32_t g = (int32_t)std::min<int64_t>(b.nitems, kWaveGridCap);
             if ((st = timed(c, kcls, [&] { return launch_update_wave(L.kc, c->prec(), b, g, c->ls, vgram); })))
                 return st;
@@ -1118,6 +1201,17 @@ static bmf_status finalize_stage(bmf_ctx *c) {
     a.ridged = c->dev<int32_t>(L.counters) + kRidged;
     bmf_status st = timed(c, kKMM, [&] { return launch_mm(c->fp64() ? kP64 : kP32, a, c->ls); });
     if (st) return st;
+    if (L.pfrow && c->stage < 3) {
+        PfacArgs f{};
+        f.items = a.items;
+        f.nitems = a.nitems;
+        f.out = a.out;
+        f.pfout = c->dev<float *>(L.m_pfout);
+        f.K = c->cfg.K;
+        f.prow = L.prow;
+        f.pfrow = L.pfrow;
+        if ((st = timed(c, kKMM, [&] { return launch_pfac(L.kc, f, c->ls); }))) return st;
+    }
     c->finalized = c->stage;
     c->done_stages[c->stage] = c->kept;
     return BMF_OK;

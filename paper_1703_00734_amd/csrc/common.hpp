@@ -47,6 +47,8 @@ struct SideDesc {
     const double *prior; // shared: [Lambda (K*K), mu (K), Lambda*mu (K)];
                          // per-row: moment-matched rows [Lambda packed, eta, mu]
     const double *tau;   // this block's noise precision
+    const float *pfac;   // per-row priors of FP32/BF16 passes: per entity the inverse
+                         // factor of its prior precision (rows of stride pfrow), else null
     int32_t n;           // number of entities
     int32_t per_row;     // 0 shared prior, 1 propagated per-row prior
     uint32_t c2;         // Philox counter word of the conditional draws

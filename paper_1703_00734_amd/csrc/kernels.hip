@@ -1557,6 +1557,292 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// k_update_empty: entities with no entries in their block under a propagated
+// per-row prior.  With no likelihood term the conditional precision is the
+// prior's own, A = Lambda, and A^-1 h = mu, so the conditional draw reduces to
+// x = mu + L^-T z with L the Cholesky factor of Lambda: the factor is the
+// prior's, computed once per stage (k_pfac), and U = L^-T is applied as a
+// triangular product.  sd.pfac row j (j = 0 .. K-1) holds U[r][r + j] for
+// r < K - j, so lane r of an entity reads one float per row, coalesced over
+// the entity's lanes.  64 / KP entities per wavefront.  An entity whose prior
+// precision was not positive definite (flag at K(K+1)/2 is 0) goes to the
+// FP64 redo queue, as a failed factorisation would.
+// --------------------------------------------------------------------------
+template <int P, int KP>
+__global__ __launch_bounds__(64) void k_update_empty(const UpdArgs a) {
+    using Ts = typename PrecT<P>::s;
+    using Tp = typename PrecT<P>::p;
+    constexpr int G = 64 / KP;
+    __shared__ float sz[64];
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    const int nitems = a.nitems;
+    uint32_t t_sw = a.t;
+    void *sample = a.sample;
+    if (a.ss) {
+        t_sw = a.ss->t;
+        sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
+    }
+    Ts *self = reinterpret_cast<Ts *>(a.self);
+    for (int pit = blockIdx.x; G * pit < nitems; pit += gridDim.x) {
+        const int lane = threadIdx.x;
+        const int h = lane / KP, r = lane % KP;
+        const int it = G * pit + h;
+        const bool valid = it < nitems;              // uniform per entity
+        const int2 item = a.items[valid ? it : G * pit];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        const float *pf = sd.pfac + (int64_t)n * a.pfrow;
+        const bool ok = pf[kk2] > 0.0f;
+        __syncthreads();                             // the previous entities' noise is read
+        if (4 * r < K) {
+            float z[4];
+            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (4 * r + c < K) sz[h * KP + 4 * r + c] = z[c];
+        }
+        __syncthreads();
+        float acc = 0.0f;
+        int off = 0;                                 // start of stored row j
+#pragma unroll 8
+        for (int j = 0; j < K; ++j) {
+            if (r + j < K) acc += pf[off + r] * sz[h * KP + r + j];
+            off += K - j;
+        }
+        const double *mu = sd.prior + (int64_t)n * a.prow + kk2 + K;
+        const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
+        const bool wr = valid && ok;
+        if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
+        if (wr && sample && r < a.ks_sample)
+            reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
+        // an empty column's residual SSE is its (zero) sum of squared values
+        if (wr && a.sse_col && r < 4)
+            a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? a.colsq[sd.self_off + n] : 0.0;
+        if (valid && !ok && r == 0) {
+            if (a.fb_list) {
+                const int slot = atomicAdd(a.fb_count, 1);
+                a.fb_list[slot] = make_int2(item.x, n);
+                atomicAdd(a.fb_total, 1);
+            } else {
+                atomicAdd(a.nonpd, 1);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_update_lowrank: entities with 1 .. kLowRankNnz entries under a propagated
+// per-row prior whose factor U = L_P^-T (Lambda = L_P L_P^T) was computed at
+// stage begin.  With v_e = L_P^-1 w_e,
+//     A = Lambda + tau sum_e w_e w_e^T = L_P (I + tau sum_e v_e v_e^T) L_P^T,
+// and the Cholesky factor of A is L_P M_1 ... M_nc with M_e the factor of the
+// rank-one modification I + tau u_e u_e^T, u_e = (M_1 ... M_(e-1))^-1 v_e (the
+// product form of Gill, Golub, Murray and Saunders, 1974).  With
+// t_j = 1 + tau sum_(i<=j) u_i^2 (t_-1 = 1), M has diagonal sqrt(t_j / t_(j-1))
+// and entries tau u_i u_j / sqrt(t_j t_(j-1)) below it, and its triangular
+// solves reduce to one prefix (M^-1) or suffix (M^-T) sum each:
+//     (M^-1 b)_j = (b_j - tau u_j P_j / t_(j-1)) / d_j,    P_j = sum_(i<j) u_i b_i,
+//     (M^-T b)_j = (b_j - tau beta_j t_j S_j) / d_j,        S_j = sum_(i>j) u_i b_i / (d_i t_(i-1)),
+// with beta_j = u_j / sqrt(t_j t_(j-1)).  The draw x = L^-T (L^-1 h + z) is then
+// U (M_1^-T ... M_nc^-T (M_nc^-1 ... M_1^-1 U^T h + z)): the same factor
+// and the same noise as the factorising kernels, at O(nc K) segment scans and
+// nc + 2 triangular products instead of a K^3 / 3 factorisation.  64 / KP
+// entities per wavefront; a half with fewer entries than the other applies
+// identity factors (u = 0), so that every lane runs the same scans.  The
+// column pass computes the residual SSE directly from the few entries.
+// --------------------------------------------------------------------------
+constexpr int kLowRankNnz = 4;
+
+template <int W>
+__device__ __forceinline__ float seg_prefix(float x, int r) {   // inclusive, within W-lane segments
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+        const float y = __shfl_up(x, o, W);
+        x = r >= o ? x + y : x;
+    }
+    return x;
+}
+template <int W>
+__device__ __forceinline__ float seg_suffix(float x, int r) {   // inclusive, within W-lane segments
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+        const float y = __shfl_down(x, o, W);
+        x = r + o < W ? x + y : x;
+    }
+    return x;
+}
+
+template <int P, int KP>
+__global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
+    using Tw = typename PrecT<P>::w;
+    using Tv = typename PrecT<P>::v;
+    using Ts = typename PrecT<P>::s;
+    using Tp = typename PrecT<P>::p;
+    constexpr int G = 64 / KP;
+    constexpr int NC = kLowRankNnz;
+    __shared__ float sw[G][NC][KP];                  // the entries' rows of the other side
+    __shared__ float sy[G][NC];                      // their values
+    __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
+    __shared__ float sz[G][KP];                      // noise
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    const int nitems = a.nitems;
+    uint32_t t_sw = a.t;
+    void *sample = a.sample;
+    if (a.ss) {
+        t_sw = a.ss->t;
+        sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
+    }
+    const Tw *otherb = reinterpret_cast<const Tw *>(a.other);
+    const Tv *val = reinterpret_cast<const Tv *>(a.val);
+    Ts *self = reinterpret_cast<Ts *>(a.self);
+    for (int pit = blockIdx.x; G * pit < nitems; pit += gridDim.x) {
+        const int lane = threadIdx.x;
+        const int h = lane / KP, r = lane % KP;
+        const int it = G * pit + h;
+        const bool valid = it < nitems;              // uniform per entity
+        const int2 item = a.items[valid ? it : G * pit];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        const int64_t p0 = a.ptr[sd.ptr_off + n];
+        const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
+        const int nc = deg <= NC ? deg : 0;          // more: the FP64 redo takes it
+        const float *pf = sd.pfac + (int64_t)n * a.pfrow;
+        const bool ok = deg <= NC && pf[kk2] > 0.0f;
+        const double *pr = sd.prior + (int64_t)n * a.prow;
+        const float tau = (float)(*sd.tau);
+        const Tw *other = otherb + sd.other_off * a.ks_other;
+        __syncthreads();                             // the previous entities' LDS is read
+#pragma unroll
+        for (int e = 0; e < NC; ++e)
+            sw[h][e][r] = (e < nc && r < K) ? to_acc<float>(other[(int64_t)a.idx[p0 + e] * a.ks_other + r]) : 0.0f;
+        if (r < NC) sy[h][r] = r < nc ? (float)val[p0 + r] : 0.0f;
+        if (4 * r < K) {
+            float z[4];
+            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (4 * r + c < K) sz[h][4 * r + c] = z[c];
+        }
+        __syncthreads();
+        // h = Lambda mu + tau sum_e y_e w_e
+        float hs = 0.0f;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) hs += sy[h][e] * sw[h][e][r];
+        sb[h][r] = r < K ? (float)pr[kk2 + r] + tau * hs : 0.0f;
+        __syncthreads();
+        // y = U^T h and v_e = U^T w_e: lane c sums U[c - j][c] b[c - j] over j <= c,
+        // U[c - j][c] being entry c - j of stored row j (coalesced over c)
+        float y = 0.0f, v[NC];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) v[e] = 0.0f;
+        {
+            int off = 0;                             // start of stored row j
+#pragma unroll 4
+            for (int j = 0; j < K; ++j) {
+                if (j <= r && r < K) {
+                    const int q = r - j;
+                    const float u = pf[off + q];
+                    y += u * sb[h][q];
+#pragma unroll
+                    for (int e = 0; e < NC; ++e) v[e] += u * sw[h][e][q];
+                }
+                off += K - j;
+            }
+        }
+        // the rank-one factors, each applied forward to y and to the later v;
+        // ncw (the most entries of the wavefront's entities) keeps the scans uniform
+        int ncw = nc;
+        if (G == 2) ncw = max(nc, __shfl_xor(nc, 32));
+        float fu[NC], ft[NC], ftm[NC], fd[NC];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) {
+            fu[e] = 0.0f;
+            ft[e] = ftm[e] = fd[e] = 1.0f;
+            if (e >= ncw) continue;
+            const float u = v[e];
+            const float t = 1.0f + tau * seg_prefix<KP>(u * u, r);
+            const float tp = __shfl_up(t, 1, KP);
+            const float tm = r == 0 ? 1.0f : tp;
+            const float d = __builtin_amdgcn_sqrtf(t / tm);
+            fu[e] = u;
+            ft[e] = t;
+            ftm[e] = tm;
+            fd[e] = d;
+            {
+                const float pi = seg_prefix<KP>(u * y, r);
+                const float pp = __shfl_up(pi, 1, KP);   // every lane takes part
+                const float pe = r == 0 ? 0.0f : pp;
+                y = (y - tau * u * pe / tm) / d;
+            }
+#pragma unroll
+            for (int f = e + 1; f < NC; ++f) {
+                if (f >= ncw) continue;
+                const float pi = seg_prefix<KP>(u * v[f], r);
+                const float pp = __shfl_up(pi, 1, KP);   // every lane takes part
+                const float pe = r == 0 ? 0.0f : pp;
+                v[f] = (v[f] - tau * u * pe / tm) / d;
+            }
+        }
+        y += r < K ? sz[h][r] : 0.0f;
+#pragma unroll
+        for (int e = NC - 1; e >= 0; --e) {
+            if (e >= ncw) continue;
+            const float u = fu[e], t = ft[e], tm = ftm[e], d = fd[e];
+            const float si = seg_suffix<KP>(u * y / (d * tm), r);
+            const float sn = __shfl_down(si, 1, KP);
+            const float se = r == KP - 1 ? 0.0f : sn;
+            const float beta = u * __builtin_amdgcn_rsqf(t * tm);
+            y = (y - tau * beta * t * se) / d;
+        }
+        __syncthreads();                             // h is read
+        sb[h][r] = r < K ? y : 0.0f;
+        __syncthreads();
+        // x = U y (h carried the prior mean): U[r][r + j] is entry r of stored row j
+        float acc = 0.0f;
+        {
+            int off = 0;
+#pragma unroll 8
+            for (int j = 0; j < K; ++j) {
+                if (r + j < K) acc += pf[off + r] * sb[h][r + j];
+                off += K - j;
+            }
+        }
+        const float xv = r < K ? acc : 0.0f;
+        const bool wr = valid && ok;
+        if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
+        if (wr && sample && r < a.ks_sample)
+            reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
+        if (a.sse_col) {
+            // residual SSE over the entries, FP64, from the state-rounded draw
+            __syncthreads();
+            sb[h][r] = r < K ? (float)elem_to_d(elem_from<Ts>((double)xv)) : 0.0f;
+            __syncthreads();
+            double res = 0.0;
+            if (r < nc) {
+                double dot = 0.0;
+                for (int k = 0; k < K; ++k) dot += (double)sb[h][k] * (double)sw[h][r][k];
+                res = (double)sy[h][r] - dot;
+                res *= res;
+            }
+#pragma unroll
+            for (int o = 1; o < NC; o <<= 1) res += __shfl_down(res, o, KP);
+            if (wr && r < 4) a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? res : 0.0;
+        }
+        if (valid && !ok && r == 0) {
+            if (a.fb_list) {
+                const int slot = atomicAdd(a.fb_count, 1);
+                a.fb_list[slot] = make_int2(item.x, n);
+                atomicAdd(a.fb_total, 1);
+            } else {
+                atomicAdd(a.nonpd, 1);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // k_sse: residual SSE of every column of a column tile (the same per-column
 // slots the fused column pass writes), for a tau step on its own.
 // --------------------------------------------------------------------------
@@ -2108,6 +2394,56 @@ __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
 }
 
 // --------------------------------------------------------------------------
+// k_pfac: the factor k_update_empty applies, from one moment-matched row
+// [Lambda packed, Lambda mu, mu] (FP64): L = chol(Lambda), U = L^-T, written
+// as FP32 rows j = 0 .. K-1 of U[r][r + j] (r < K - j, row j at offset
+// j K - j (j - 1) / 2), then a flag (1: Lambda positive definite).  Items are
+// (side, entity); sides whose rows seed no later stage have no output.
+// --------------------------------------------------------------------------
+template <int KP>
+__global__ __launch_bounds__(64) void k_pfac(const PfacArgs a) {
+    constexpr int LD = KP + 1;
+    __shared__ double lin[KP * LD];
+    __shared__ double inv[KP * LD];
+    __shared__ int flag;
+    const int lane = threadIdx.x;
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        const int2 item = a.items[it];
+        float *pfo = a.pfout[item.x];
+        if (pfo == nullptr) continue;                // uniform over the block
+        pfo += (int64_t)item.y * a.pfrow;
+        const double *row = a.out[item.x] + (int64_t)item.y * a.prow;
+        for (int q = lane; q < K * K; q += 64) {
+            const int r = q / K, c = q - r * K;
+            lin[r * LD + c] = c <= r ? row[tri(r, c)] : 0.0;
+        }
+        __syncthreads();
+        const bool ok = chol_lds<double>(lin, K, LD, 0.0, nullptr, lane, &flag);
+        // inv <- L^-1, column c by lane c
+        for (int c = lane; c < K; c += 64) {
+            for (int i = 0; i < K; ++i) {
+                if (i < c) {
+                    inv[i * LD + c] = 0.0;
+                } else {
+                    double s = (i == c) ? 1.0 : 0.0;
+                    for (int p = c; p < i; ++p) s -= lin[i * LD + p] * inv[p * LD + c];
+                    inv[i * LD + c] = s / lin[i * LD + i];
+                }
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < K; ++j) {
+            const int off = j * K - j * (j - 1) / 2;
+            for (int r = lane; r < K - j; r += 64) pfo[off + r] = (float)inv[(r + j) * LD + r];
+        }
+        if (lane == 0) pfo[kk2] = ok ? 1.0f : 0.0f;
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------------------------
 // k_agg: Algorithm 2 for one row of a row (or column) block (FP64), one
 // wavefront per row.
 // --------------------------------------------------------------------------
@@ -2435,6 +2771,42 @@ hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipSt
     return hipGetLastError();
 }
 
+hipError_t launch_update_empty(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
+    switch (prec) {
+    case kP32:
+        if (kp == 32) hipLaunchKernelGGL((k_update_empty<kP32, 32>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_empty<kP32, 64>), dim3(grid), dim3(64), 0, s, a);
+        break;
+    case kPBF:
+        if (kp == 32) hipLaunchKernelGGL((k_update_empty<kPBF, 32>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_empty<kPBF, 64>), dim3(grid), dim3(64), 0, s, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    if (grid <= 0) return hipSuccess;
+    if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
+    switch (prec) {
+    case kP32:
+        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kP32, 32>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_lowrank<kP32, 64>), dim3(grid), dim3(64), 0, s, a);
+        break;
+    case kPBF:
+        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kPBF, 32>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_lowrank<kPBF, 64>), dim3(grid), dim3(64), 0, s, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int32_t lowrank_max_nnz() { return kLowRankNnz; }
+
 hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s, bool vgram) {
     if (grid <= 0) return hipSuccess;
     if (kp <= 16) return upd_wave_kp<16>(prec, a, grid, s, vgram);
@@ -2540,6 +2912,16 @@ hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_init<uint16_t>, dim3(g), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(k_init<float>, dim3(g), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    const int g = grid_for(a.nitems, 1, 65536);
+    if (a.K > kp) return hipErrorInvalidValue;
+    if (kp <= 32) hipLaunchKernelGGL((k_pfac<32>), dim3(g), dim3(64), 0, s, a);
+    else if (kp <= 64) hipLaunchKernelGGL((k_pfac<64>), dim3(g), dim3(64), 0, s, a);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

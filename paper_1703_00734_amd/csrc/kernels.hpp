@@ -43,6 +43,7 @@ struct UpdArgs {
     const SweepState *ss;     // when set, t and the sample slot come from here
     int32_t K;
     int32_t prow;             // doubles per moment-matched row
+    int32_t pfrow;            // floats per prior-factor row (SideDesc::pfac)
     uint32_t t;               // sweep index (Philox c1)
     uint32_t k0, k1;          // Philox key
     float theta;              // FP32 pivot threshold (0 in FP64)
@@ -160,6 +161,16 @@ struct MmArgs {
     int32_t *ridged;
 };
 
+// Prior factors of moment-matched rows: for each (side, entity) item the row
+// out[side] + entity * prow is factored into pfout[side] + entity * pfrow.
+struct PfacArgs {
+    const int2 *items;
+    int32_t nitems;
+    double *const *out;       // per side: moment-matched rows (as MmArgs::out)
+    float *const *pfout;      // per side: prior-factor rows, null for none
+    int32_t K, prow, pfrow;
+};
+
 struct AggArgs {
     const AggJob *jobs;
     const int2 *items;        // (job, row)
@@ -185,6 +196,15 @@ hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t
 // Two entities with at most 16 entries per wavefront, 16 < K <= 32, FP32 or
 // BF16 state (items in pairs: grid counts pairs).
 hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
+// Entities with no entries under a per-row prior whose factor is in pfac
+// (FP32 or BF16 state, K <= kp): x = mu + L^-T z without a factorisation;
+// 64 / kp entities per wavefront (grid counts wavefronts).
+hipError_t launch_update_empty(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
+// Entities with 1 .. lowrank_max_nnz() entries under a per-row prior whose factor
+// is in pfac (FP32 or BF16 state, K <= kp): the factor of the prior updated by
+// product-form rank-one modifications; 64 / kp entities per wavefront.
+hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
+int32_t lowrank_max_nnz();
 // vgram: BF16 state with K > 16 takes the VALU-Gram kernel instead of the MFMA one
 hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
                               bool vgram = false);
@@ -198,6 +218,7 @@ hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
 hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s);
 hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
+hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s);
 hipError_t launch_agg(const AggArgs &a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

@@ -198,6 +198,67 @@ def test_fp32_fallback_path_redoes_rows_in_fp64(K):
     assert rel.max() < 2e-6
 
 
+@pytest.mark.parametrize("precision,K", [("fp32", 24), ("bf16", 32), ("bf16", 40), ("fp32", 64)])
+def test_few_entry_entities_under_propagated_priors(precision, K):
+    """Stage-3 single steps on a sparse 2 x 2 partition where a quarter of the
+    rows and some columns have no entries in their block and most others one to
+    four: the former take the prior-factor kernel (x = mu + L^-T z, L the
+    Cholesky factor of the moment-matched precision, factored once per stage),
+    the latter the low-rank kernel (that factor updated by product-form
+    rank-one modifications), the rest the factorising kernels; every draw
+    against the oracle's from the same moment-matched priors and noise, and the
+    column pass's residual SSE through the tau draw.  More kept samples than 2K
+    keep the moment-matched precisions well conditioned."""
+    print("case empty", precision, K, flush=True)
+    d = small_data(K, seed=21 + K, N=400, D=240, nnz=1200, empty_rows=5, kind="uniform")
+    S = 2 * K + 8
+    g, o = pair(d, K, precision, I=2, J=2, order="random", max_kept=S)
+    g.pp_stage(1, S)
+    g.pp_stage(2, S)
+    g.pp_stage(3, 0)                 # moment matching of stage 2 and the prior factors
+    for b in range(4):
+        if g.block_info(b)["stage"] < 3:
+            mx, Lx = g.get_mm(b, 0)
+            mw, Lw = g.get_mm(b, 1)
+            o.mm[b] = dict(x_mu=mx, x_Lam=Lx, w_mu=mw, w_Lam=Lw, ridged=0)
+    o.begin_stage(3)
+    b = 3
+    blk = o.blocks[b]
+    assert g.block_info(b)["stage"] == 3
+    st = random_state(np.random.default_rng(300 + K), blk["R"], blk["C"], K)
+    for which, side, key, ptr in (("rows", 0, "X", "csr_ptr"), ("cols", 1, "W", "csc_ptr")):
+        load_state(g, o, b, st)
+        g.step(b, which, 4)
+        if which == "rows":
+            o.update_rows(blk, 4)
+        else:
+            o.update_cols(blk, 4)
+        deg = np.diff(blk[ptr])
+        empty = deg == 0
+        few = (deg >= 1) & (deg <= 4)
+        draw = g.get_draw(b, side)
+        prior = blk["x_prior" if which == "rows" else "w_prior"][0]
+        tr = cond_precision_trace(blk, which, K, blk["tau"], prior)
+        rel = rel_err_rows(draw, blk[key], tr, K)
+        print(which, "empty", int(empty.sum()), "1-4 entries", int(few.sum()), "of", empty.size,
+              "max rel", rel.max(), "of the empty", rel[empty].max() if empty.any() else None,
+              "of the 1-4", rel[few].max() if few.any() else None, flush=True)
+        assert rel.max() <= TOL[precision]
+        assert few.sum() >= (50 if which == "rows" else 20)
+        assert np.array_equal(g.get_state(b)[key], round_state(draw, precision))
+        assert empty.sum() >= (20 if which == "rows" else 5)
+    # a whole sweep (its first, t = 0): the tau draw that closes it reads the
+    # residual SSE the column pass left, per column, from the library's state
+    load_state(g, o, b, st)
+    g.gibbs_sweep(1)
+    sg = g.get_state(b)
+    blk["X"], blk["W"] = sg["X"].copy(), sg["W"].copy()
+    o.tau_draw(blk, 0)
+    print("tau", sg["tau"], "oracle", blk["tau"], flush=True)
+    np.testing.assert_allclose(sg["tau"], blk["tau"], rtol=1e-4)
+    assert g.stats()["nonpd_rows"] == 0
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_batched_equals_per_block_and_is_deterministic(precision):
     K = 10
