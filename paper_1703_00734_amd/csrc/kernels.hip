@@ -1654,24 +1654,45 @@ __global__ __launch_bounds__(64) void k_update_empty(const UpdArgs a) {
 // --------------------------------------------------------------------------
 constexpr int kLowRankNnz = 4;
 
+// Cross-lane moves of the segment scans (GFX9 DPP; lanes without a source,
+// and rows left out by the row mask, read 0).
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ float dpp0(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xF, false));
+}
+__device__ __forceinline__ float lane_f(float x, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+// Inclusive prefix sums within W-lane segments (W = 32 or 64): four row_shr
+// steps inside each 16-lane row, then row_bcast:15 (rows 1, 3 take the last
+// lane of rows 0, 2) and, for W = 64, row_bcast:31 (rows 2, 3 take lane 31).
 template <int W>
-__device__ __forceinline__ float seg_prefix(float x, int r) {   // inclusive, within W-lane segments
-#pragma unroll
-    for (int o = 1; o < W; o <<= 1) {
-        const float y = __shfl_up(x, o, W);
-        x = r >= o ? x + y : x;
-    }
+__device__ __forceinline__ float seg_prefix(float x) {
+    x += dpp0<0x111>(x);
+    x += dpp0<0x112>(x);
+    x += dpp0<0x114>(x);
+    x += dpp0<0x118>(x);
+    x += dpp0<0x142, 0xA>(x);
+    if (W == 64) x += dpp0<0x143, 0xC>(x);
     return x;
 }
+// Inclusive suffix sums within W-lane segments: row_shl steps inside each row,
+// then each row adds the totals of the later rows of its segment (their first
+// lanes, read with v_readlane).
 template <int W>
-__device__ __forceinline__ float seg_suffix(float x, int r) {   // inclusive, within W-lane segments
-#pragma unroll
-    for (int o = 1; o < W; o <<= 1) {
-        const float y = __shfl_down(x, o, W);
-        x = r + o < W ? x + y : x;
-    }
-    return x;
+__device__ __forceinline__ float seg_suffix(float x, int lane) {
+    x += dpp0<0x101>(x);
+    x += dpp0<0x102>(x);
+    x += dpp0<0x104>(x);
+    x += dpp0<0x108>(x);
+    const float s1 = lane_f(x, 16), s2 = lane_f(x, 32), s3 = lane_f(x, 48);
+    const int row = lane >> 4;
+    if (W == 32) return x + (row == 0 ? s1 : (row == 2 ? s3 : 0.0f));
+    return x + (row == 0 ? s1 + s2 + s3 : (row == 1 ? s2 + s3 : (row == 2 ? s3 : 0.0f)));
 }
+// The value of lane - 1 (wave_shr:1) and of lane + 1 (wave_shl:1).
+__device__ __forceinline__ float from_prev(float x) { return dpp0<0x138>(x); }
+__device__ __forceinline__ float from_next(float x) { return dpp0<0x130>(x); }
 
 template <int P, int KP>
 __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
@@ -1685,6 +1706,7 @@ __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
     __shared__ float sy[G][NC];                      // their values
     __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
     __shared__ float sz[G][KP];                      // noise
+    __shared__ float su[G][KP * (KP + 1) / 2];       // the stored factor U
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
     const int nitems = a.nitems;
@@ -1718,6 +1740,8 @@ __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
         for (int e = 0; e < NC; ++e)
             sw[h][e][r] = (e < nc && r < K) ? to_acc<float>(other[(int64_t)a.idx[p0 + e] * a.ks_other + r]) : 0.0f;
         if (r < NC) sy[h][r] = r < nc ? (float)val[p0 + r] : 0.0f;
+#pragma unroll 6
+        for (int q = r; q < kk2; q += KP) su[h][q] = pf[q];
         if (4 * r < K) {
             float z[4];
             normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
@@ -1743,7 +1767,7 @@ __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
             for (int j = 0; j < K; ++j) {
                 if (j <= r && r < K) {
                     const int q = r - j;
-                    const float u = pf[off + q];
+                    const float u = su[h][off + q];
                     y += u * sb[h][q];
 #pragma unroll
                     for (int e = 0; e < NC; ++e) v[e] += u * sw[h][e][q];
@@ -1755,46 +1779,43 @@ __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
         // ncw (the most entries of the wavefront's entities) keeps the scans uniform
         int ncw = nc;
         if (G == 2) ncw = max(nc, __shfl_xor(nc, 32));
-        float fu[NC], ft[NC], ftm[NC], fd[NC];
+        float fu[NC], ft[NC], fitm[NC], fid[NC];
 #pragma unroll
         for (int e = 0; e < NC; ++e) {
             fu[e] = 0.0f;
-            ft[e] = ftm[e] = fd[e] = 1.0f;
+            ft[e] = fitm[e] = fid[e] = 1.0f;
             if (e >= ncw) continue;
             const float u = v[e];
-            const float t = 1.0f + tau * seg_prefix<KP>(u * u, r);
-            const float tp = __shfl_up(t, 1, KP);
-            const float tm = r == 0 ? 1.0f : tp;
-            const float d = __builtin_amdgcn_sqrtf(t / tm);
+            const float t = 1.0f + tau * seg_prefix<KP>(u * u);
+            const float tp = from_prev(t);
+            const float itm = r == 0 ? 1.0f : __builtin_amdgcn_rcpf(tp);      // 1 / t_(j-1)
+            const float id = __builtin_amdgcn_rsqf(t * itm);                   // 1 / d_j
             fu[e] = u;
             ft[e] = t;
-            ftm[e] = tm;
-            fd[e] = d;
+            fitm[e] = itm;
+            fid[e] = id;
             {
-                const float pi = seg_prefix<KP>(u * y, r);
-                const float pp = __shfl_up(pi, 1, KP);   // every lane takes part
+                const float pp = from_prev(seg_prefix<KP>(u * y));
                 const float pe = r == 0 ? 0.0f : pp;
-                y = (y - tau * u * pe / tm) / d;
+                y = (y - tau * u * pe * itm) * id;
             }
 #pragma unroll
             for (int f = e + 1; f < NC; ++f) {
                 if (f >= ncw) continue;
-                const float pi = seg_prefix<KP>(u * v[f], r);
-                const float pp = __shfl_up(pi, 1, KP);   // every lane takes part
+                const float pp = from_prev(seg_prefix<KP>(u * v[f]));
                 const float pe = r == 0 ? 0.0f : pp;
-                v[f] = (v[f] - tau * u * pe / tm) / d;
+                v[f] = (v[f] - tau * u * pe * itm) * id;
             }
         }
         y += r < K ? sz[h][r] : 0.0f;
 #pragma unroll
         for (int e = NC - 1; e >= 0; --e) {
             if (e >= ncw) continue;
-            const float u = fu[e], t = ft[e], tm = ftm[e], d = fd[e];
-            const float si = seg_suffix<KP>(u * y / (d * tm), r);
-            const float sn = __shfl_down(si, 1, KP);
+            const float u = fu[e], t = ft[e], itm = fitm[e], id = fid[e];
+            const float sn = from_next(seg_suffix<KP>(u * y * id * itm, lane));
             const float se = r == KP - 1 ? 0.0f : sn;
-            const float beta = u * __builtin_amdgcn_rsqf(t * tm);
-            y = (y - tau * beta * t * se) / d;
+            // tau beta_j t_j S_j with beta_j = u_j / sqrt(t_j t_(j-1)) = u_j id itm
+            y = (y - tau * u * id * itm * t * se) * id;
         }
         __syncthreads();                             // h is read
         sb[h][r] = r < K ? y : 0.0f;
@@ -1805,7 +1826,7 @@ __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
             int off = 0;
 #pragma unroll 8
             for (int j = 0; j < K; ++j) {
-                if (r + j < K) acc += pf[off + r] * sb[h][r + j];
+                if (r + j < K) acc += su[h][off + r] * sb[h][r + j];
                 off += K - j;
             }
         }
