@@ -27,7 +27,7 @@ METRIC = "row-updates/s and ratings/s per Gibbs sweep, batched BF16 vs plain FP3
 HBM_PEAK_GBS = 8000.0
 # entities with at most this many entries under a propagated prior take the
 # low-rank kernel (the library's own threshold)
-LOWRANK_NNZ = 4
+LOWRANK_NNZ = 8
 
 
 def parse():

@@ -1652,7 +1652,7 @@ __global__ __launch_bounds__(64) void k_update_empty(const UpdArgs a) {
 // identity factors (u = 0), so that every lane runs the same scans.  The
 // column pass computes the residual SSE directly from the few entries.
 // --------------------------------------------------------------------------
-constexpr int kLowRankNnz = 4;
+constexpr int kLowRankNnz = 8;
 
 // Cross-lane moves of the segment scans (GFX9 DPP; lanes without a source,
 // and rows left out by the row mask, read 0).
