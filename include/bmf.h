@@ -53,7 +53,12 @@ typedef enum {
 } bmf_status;
 
 /* Arithmetic of the row/column conditional updates.  Hyperparameter, tau,
- * moment-matching and aggregation arithmetic is FP64 in every mode. */
+ * moment-matching and aggregation arithmetic is FP64 in every mode.  In the
+ * FP32 and BF16 modes with K > 16, an entity with at most eight entries under a
+ * propagated (moment-matched) prior skips the Cholesky: its prior's factor,
+ * computed once per stage in FP64 and stored in FP32, is applied directly (no
+ * entries) or updated by rank-one modifications (one to eight), giving the
+ * same factor and draw up to rounding. */
 typedef enum {
     BMF_PREC_FP64 = 0,    /* FP64 gathers, Gram, Cholesky and solves */
     BMF_PREC_FP32 = 1,    /* FP32 gathers and Gram; FP32 Cholesky with FP64 fallback */

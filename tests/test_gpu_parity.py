@@ -259,6 +259,36 @@ def test_few_entry_entities_under_propagated_priors(precision, K):
     assert g.stats()["nonpd_rows"] == 0
 
 
+@pytest.mark.parametrize("precision,K", [("bf16", 32), ("fp32", 24), ("bf16", 48)])
+def test_prior_factor_paths_same_in_every_launch_form(precision, K):
+    """Stages 2 and 3 on a sparse 2 x 2 partition, where the prior-factor,
+    low-rank, light and heavy kernels all take part: graph-replayed batched
+    sweeps, eagerly launched batched sweeps and per-block launches (different
+    item orders, so different pairings of entities in a wavefront) give the
+    same states bit for bit."""
+    print("case launch forms", precision, K, flush=True)
+    d = small_data(K, seed=60 + K, N=500, D=260, nnz=3000, empty_rows=3)
+    S = 2 * K + 4
+    runs = []
+    for batched, eager in ((True, False), (True, True), (False, False)):
+        g, _ = pair(d, K, precision, I=2, J=2, order="random", batched=batched, max_kept=S)
+        if eager:
+            g.enable_timing(True)
+        out = []
+        for s, nsw in ((1, S), (2, S), (3, 4)):
+            g.pp_stage(s, nsw)
+            for b in range(4):
+                if g.block_info(b)["stage"] == s:
+                    st = g.get_state(b)
+                    out += [st["X"], st["W"], st["tau"]]
+        runs.append(out)
+        assert g.stats()["nonpd_rows"] == 0
+        g.close()
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
 def test_batched_equals_per_block_and_is_deterministic(precision):
     K = 10
