@@ -74,3 +74,57 @@ def test_full_size_sweep_matches_oracle(cid):
     stats = g.stats()
     assert stats["nonpd_rows"] == 0
     g.close()
+
+
+def test_full_size_stage3_sweep_matches_oracle():
+    """The 480k x 17.8k, K = 32 workload on its 8 x 8 partition: stages 1 and 2
+    run with 2K + 2 kept samples, then one batched, graph-replayed sweep of
+    stage 3, which takes every update kernel: the prior-factor path (rows
+    without entries), the low-rank path (one to eight entries), the
+    two-per-wavefront kernel and the MFMA wavefront kernel.  Block (7, 7), of
+    the sparsest rows and columns (decreasing order), is checked against the
+    oracle's conditional draws under the library's own moment-matched priors
+    (rows: block (7, 0)'s, columns: block (0, 7)'s), from a state loaded into
+    both, with the same noise."""
+    import synth
+    cfg = synth.CONFIGS[5]
+    print("case: full-size workload 5, stage 3", flush=True)
+    d = synth.config(5, seed=1, progress=lambda m: print("data:", m, flush=True))
+    K = d["K"]
+    S = 2 * K + 2
+    g, o = pair(d, K, "bf16", I=cfg["I"], J=cfg["J"], order=cfg["order"], seed=101, max_kept=S)
+    print("library and oracle built", flush=True)
+    g.pp_stage(1, S)
+    g.pp_stage(2, S)
+    g.pp_stage(3, 0)
+    print("stages 1 and 2 done", flush=True)
+    I, J = cfg["I"], cfg["J"]
+    b = (I - 1) * J + (J - 1)
+    assert g.block_info(b)["stage"] == 3
+    mx, Lx = g.get_mm((I - 1) * J + 0, 0)
+    mw, Lw = g.get_mm(0 * J + (J - 1), 1)
+    blk = o.blocks[b]
+    blk["x_prior"] = (Lx, mx)
+    blk["w_prior"] = (Lw, mw)
+    deg = np.diff(blk["csr_ptr"])
+    print("rows", blk["R"], "cols", blk["C"], "empty rows", int((deg == 0).sum()), "rows with 1-8 entries",
+          int(((deg >= 1) & (deg <= 8)).sum()), flush=True)
+    assert (deg == 0).sum() > 1000 and ((deg >= 1) & (deg <= 8)).sum() > 1000
+    st = random_state(np.random.default_rng(75), blk["R"], blk["C"], K)
+    load_state(g, o, b, st)
+    g.gibbs_sweep(1)                         # sweep 0 of stage 3, batched and graph-captured
+    s = g.get_state(b)
+    o.update_rows(blk, 0)
+    rel = _rel(s["X"], round_state(blk["X"], "bf16"))
+    print("rows: max rel", rel.max(), "p99.9", np.quantile(rel, 0.999), flush=True)
+    assert rel.max() <= TOL_STATE
+    blk["X"] = s["X"].copy()
+    o.update_cols(blk, 0)
+    rel = _rel(s["W"], round_state(blk["W"], "bf16"))
+    print("cols: max rel", rel.max(), "p99.9", np.quantile(rel, 0.999), flush=True)
+    assert rel.max() <= TOL_STATE
+    blk["W"] = s["W"].copy()
+    o.tau_draw(blk, 0)
+    np.testing.assert_allclose(s["tau"], blk["tau"], rtol=1e-4)
+    assert g.stats()["nonpd_rows"] == 0
+    g.close()
