@@ -2321,8 +2321,11 @@ __global__ __launch_bounds__(256) void k_init(const InitArgs a) {
 template <typename Ts, int KP>
 __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
     constexpr int LD = KP + 1;                     // LDS sized to K: more entities per CU
+    constexpr int MC = 16;                         // samples per LDS chunk
+    constexpr int NPL = (KP * (KP + 1) / 2 + 63) / 64;   // covariance pairs per lane
     __shared__ double sig[KP * LD];
     __shared__ double lin[KP * LD];
+    __shared__ double xs[MC * KP];
     __shared__ double mu[KP];
     __shared__ int flag;
     const int lane = threadIdx.x;
@@ -2346,16 +2349,40 @@ __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
             __syncthreads();
             continue;
         }
-        for (int q = lane; q < K * K; q += 64) {
-            const int r = q / K, c = q - r * K;
-            if (c <= r) {
-                double s = 0.0;
-                for (int t = 0; t < S; ++t)
-                    s += ((double)smp[(int64_t)t * a.slot_elems + r] - mu[r]) *
-                         ((double)smp[(int64_t)t * a.slot_elems + c] - mu[c]);
-                s /= (double)(S - 1);
-                sig[r * LD + c] = s;
-                sig[c * LD + r] = s;
+        // covariance: lane owns packed pairs lane, lane + 64, ...; the centred
+        // samples pass through LDS in chunks of MC, each sum still in sample order
+        double cacc[NPL];
+#pragma unroll
+        for (int u = 0; u < NPL; ++u) cacc[u] = 0.0;
+        for (int t0 = 0; t0 < S; t0 += MC) {
+            const int nt = min(MC, S - t0);
+            for (int q = lane; q < nt * K; q += 64) {
+                const int t = q / K, k = q - t * K;
+                xs[t * KP + k] = (double)smp[(int64_t)(t0 + t) * a.slot_elems + k] - mu[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < NPL; ++u) {
+                const int q = lane + 64 * u;
+                if (q < kk2) {
+                    const int r = (int)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5 + 1e-9);
+                    const int c = q - r * (r + 1) / 2;
+                    double sacc = cacc[u];
+                    for (int t = 0; t < nt; ++t) sacc += xs[t * KP + r] * xs[t * KP + c];
+                    cacc[u] = sacc;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int u = 0; u < NPL; ++u) {
+            const int q = lane + 64 * u;
+            if (q < kk2) {
+                const int r = (int)((__builtin_sqrt(8.0 * (double)q + 1.0) - 1.0) * 0.5 + 1e-9);
+                const int c = q - r * (r + 1) / 2;
+                const double v = cacc[u] / (double)(S - 1);
+                sig[r * LD + c] = v;
+                sig[c * LD + r] = v;
             }
         }
         __syncthreads();
