@@ -186,6 +186,9 @@ struct StageLists {
     // the first of those that the empty-entity kernel takes (no entries)
     int64_t i_row_lowrank = 0, i_col_lowrank = 0, i_row_empty = 0, i_col_empty = 0;
     std::vector<int64_t> row_item_lowrank, col_item_lowrank, row_item_empty, col_item_empty;
+    // first low-rank item with at most lowrank_small_nnz() entries (the small instance's)
+    int64_t i_row_lowsmall = 0, i_col_lowsmall = 0;
+    std::vector<int64_t> row_item_lowsmall, col_item_lowsmall;
     // per side: prior-factor rows this stage's moment matching writes (or null)
     std::vector<float *> pfout;
     std::vector<int64_t> row_item_begin, col_item_begin;
@@ -454,7 +457,7 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         std::vector<int2> igrp, sgrp;
         std::vector<int64_t> ideg;
         std::vector<char> ifast;                    // few entries under a factored per-row prior
-        const int64_t nlr = lowrank_max_nnz();
+        const int64_t nlr = lowrank_max_nnz(), nls = lowrank_small_nnz();
         std::vector<int64_t> &ibeg = rows ? S.row_item_begin : S.col_item_begin;
         std::vector<int64_t> &sbeg = rows ? S.row_seg_begin : S.col_seg_begin;
         (rows ? S.s_row : S.s_col) = (int64_t)S.segs.size();
@@ -468,15 +471,18 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
             sbeg.push_back((int64_t)slot);
             std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
             std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
+            std::vector<int64_t> &blows = rows ? S.row_item_lowsmall : S.col_item_lowsmall;
             std::vector<int64_t> &bempty = rows ? S.row_item_empty : S.col_item_empty;
             blight.push_back(-1);
             blowr.push_back(-1);
+            blows.push_back(-1);
             bempty.push_back(-1);
             const bool fast = S.sides[side].pfac != nullptr;
             for (int32_t e : (rows ? S.ord_row[k] : S.ord_col[k])) {
                 const int64_t deg = ptr[e + 1] - ptr[e];
                 if (blight.back() < 0 && deg <= kLightNnz) blight.back() = (int64_t)igrp.size();
                 if (fast && blowr.back() < 0 && deg <= nlr) blowr.back() = (int64_t)igrp.size();
+                if (fast && blows.back() < 0 && deg <= nls) blows.back() = (int64_t)igrp.size();
                 if (fast && bempty.back() < 0 && deg == 0) bempty.back() = (int64_t)igrp.size();
                 igrp.push_back(make_int2(side, e));
                 ideg.push_back(deg);
@@ -506,10 +512,12 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         {
             std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
             std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
+            std::vector<int64_t> &blows = rows ? S.row_item_lowsmall : S.col_item_lowsmall;
             std::vector<int64_t> &bempty = rows ? S.row_item_empty : S.col_item_empty;
             for (int32_t k = 0; k < nbs; ++k) {
                 if (blight[k] < 0) blight[k] = ibeg[k + 1];
                 if (blowr[k] < 0) blowr[k] = ibeg[k + 1];
+                if (blows[k] < 0) blows[k] = ibeg[k + 1];
                 if (bempty[k] < 0) bempty[k] = ibeg[k + 1];
             }
         }
@@ -527,19 +535,23 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         (rows ? S.i_row_heavy : S.i_col_heavy) = (int64_t)S.items.size();
         int64_t &light = rows ? S.i_row_light : S.i_col_light;
         int64_t &lowr = rows ? S.i_row_lowrank : S.i_col_lowrank;
+        int64_t &lows = rows ? S.i_row_lowsmall : S.i_col_lowsmall;
         int64_t &empty = rows ? S.i_row_empty : S.i_col_empty;
         light = -1;
         lowr = -1;
+        lows = -1;
         empty = -1;
         for (int64_t q : iperm) {
             if (light < 0 && ideg[q] <= kLightNnz) light = (int64_t)S.items.size();
             if (lowr < 0 && ifast[q]) lowr = (int64_t)S.items.size();
+            if (lows < 0 && ifast[q] && ideg[q] <= nls) lows = (int64_t)S.items.size();
             if (empty < 0 && ifast[q] && ideg[q] == 0) empty = (int64_t)S.items.size();
             S.items.push_back(igrp[q]);
             S.splits.push_back(sgrp[q]);
         }
         if (light < 0) light = (int64_t)S.items.size();
         if (lowr < 0) lowr = (int64_t)S.items.size();
+        if (lows < 0) lows = (int64_t)S.items.size();
         if (empty < 0) empty = (int64_t)S.items.size();
     }
     S.s_end = (int64_t)S.segs.size();
@@ -793,32 +805,37 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         // the empty-entity kernel.
         const bool duo = L.kc == 32 && (c->prec() == kP32 || c->prec() == kPBF);
         const bool lsplit = L.mfma || duo;
-        enum { kWave = 0, kLight = 1, kLowRank = 2, kEmpty = 3 };
+        enum { kWave = 0, kLight = 1, kLowRank = 2, kLowSmall = 3, kEmpty = 4 };
         std::vector<std::pair<int64_t, int64_t>> split;
         std::vector<int> kind;
         for (size_t ri = 0; ri < ranges.size(); ++ri) {
-            int64_t light, lowr, empty;
+            int64_t light, lowr, lows, empty;
             if (batched) {
                 light = rows ? S.i_row_light : S.i_col_light;
                 lowr = rows ? S.i_row_lowrank : S.i_col_lowrank;
+                lows = rows ? S.i_row_lowsmall : S.i_col_lowsmall;
                 empty = rows ? S.i_row_empty : S.i_col_empty;
             } else {
                 const int32_t q = k < 0 ? (int32_t)ri : k;
                 const int64_t base = rows ? S.i_row_blk : S.i_col_blk;
                 light = base + (rows ? S.row_item_light : S.col_item_light)[q];
                 lowr = base + (rows ? S.row_item_lowrank : S.col_item_lowrank)[q];
+                lows = base + (rows ? S.row_item_lowsmall : S.col_item_lowsmall)[q];
                 empty = base + (rows ? S.row_item_empty : S.col_item_empty)[q];
             }
             const int64_t lo = ranges[ri].first, hi = ranges[ri].second;
             lowr = std::min(std::max(lowr, lo), hi);
             empty = std::min(std::max(empty, lowr), hi);
+            lows = std::min(std::max(lows, lowr), empty);
             light = lsplit ? std::min(std::max(light, lo), lowr) : lowr;
             split.push_back({lo, light});
             kind.push_back(kWave);
             split.push_back({light, lowr});
             kind.push_back(kLight);
-            split.push_back({lowr, empty});
+            split.push_back({lowr, lows});
             kind.push_back(kLowRank);
+            split.push_back({lows, empty});
+            kind.push_back(kLowSmall);
             split.push_back({empty, hi});
             kind.push_back(kEmpty);
         }
@@ -828,14 +845,16 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
             UpdArgs b = a;
             b.items = c->dev<int2>(L.m_items) + r.first;
             b.nitems = (int32_t)(r.second - r.first);
-            if (kind[ri] == kEmpty || kind[ri] == kLowRank) {
+            if (kind[ri] == kEmpty || kind[ri] == kLowRank || kind[ri] == kLowSmall) {
                 const int32_t per = 64 / L.kc;
                 const int32_t g = (int32_t)std::min<int64_t>((b.nitems + per - 1) / per, kWaveGridCap);
                 if (kind[ri] == kEmpty) {
                     if ((st = timed(c, kcls, [&] { return launch_update_empty(L.kc, c->prec(), b, g, c->ls); })))
                         return st;
-                } else if ((st = timed(c, kcls, [&] { return launch_update_lowrank(L.kc, c->prec(), b, g, c->ls); }))) {
-                    return st;
+                } else {
+                    const bool small = kind[ri] == kLowSmall;
+                    if ((st = timed(c, kcls, [&] { return launch_update_lowrank(L.kc, c->prec(), b, g, c->ls, small); })))
+                        return st;
                 }
                 continue;
             }

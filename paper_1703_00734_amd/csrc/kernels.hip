@@ -1653,6 +1653,7 @@ __global__ __launch_bounds__(64) void k_update_empty(const UpdArgs a) {
 // column pass computes the residual SSE directly from the few entries.
 // --------------------------------------------------------------------------
 constexpr int kLowRankNnz = 8;
+constexpr int kLowRankSmall = 2;                 // a second instance for 1 .. 2 entries
 
 // Cross-lane moves of the segment scans (GFX9 DPP; lanes without a source,
 // and rows left out by the row mask, read 0).
@@ -1694,14 +1695,13 @@ __device__ __forceinline__ float seg_suffix(float x, int lane) {
 __device__ __forceinline__ float from_prev(float x) { return dpp0<0x138>(x); }
 __device__ __forceinline__ float from_next(float x) { return dpp0<0x130>(x); }
 
-template <int P, int KP>
+template <int P, int KP, int NC>
 __global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
     using Tw = typename PrecT<P>::w;
     using Tv = typename PrecT<P>::v;
     using Ts = typename PrecT<P>::s;
     using Tp = typename PrecT<P>::p;
     constexpr int G = 64 / KP;
-    constexpr int NC = kLowRankNnz;
     __shared__ float sw[G][NC][KP];                  // the entries' rows of the other side
     __shared__ float sy[G][NC];                      // their values
     __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
@@ -2840,24 +2840,31 @@ hipError_t launch_update_empty(int32_t kp, int32_t prec, const UpdArgs &a, int32
     return hipGetLastError();
 }
 
-hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
-    if (grid <= 0) return hipSuccess;
-    if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
+template <int NC>
+static hipError_t lowrank_nc(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
     switch (prec) {
     case kP32:
-        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kP32, 32>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_update_lowrank<kP32, 64>), dim3(grid), dim3(64), 0, s, a);
+        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kP32, 32, NC>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_lowrank<kP32, 64, NC>), dim3(grid), dim3(64), 0, s, a);
         break;
     case kPBF:
-        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kPBF, 32>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_update_lowrank<kPBF, 64>), dim3(grid), dim3(64), 0, s, a);
+        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kPBF, 32, NC>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_lowrank<kPBF, 64, NC>), dim3(grid), dim3(64), 0, s, a);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
+                                 bool small) {
+    if (grid <= 0) return hipSuccess;
+    if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
+    return small ? lowrank_nc<kLowRankSmall>(kp, prec, a, grid, s) : lowrank_nc<kLowRankNnz>(kp, prec, a, grid, s);
+}
+
 int32_t lowrank_max_nnz() { return kLowRankNnz; }
+int32_t lowrank_small_nnz() { return kLowRankSmall; }
 
 hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s, bool vgram) {
     if (grid <= 0) return hipSuccess;

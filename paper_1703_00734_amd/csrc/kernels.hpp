@@ -202,9 +202,13 @@ hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipSt
 hipError_t launch_update_empty(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
 // Entities with 1 .. lowrank_max_nnz() entries under a per-row prior whose factor
 // is in pfac (FP32 or BF16 state, K <= kp): the factor of the prior updated by
-// product-form rank-one modifications; 64 / kp entities per wavefront.
-hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
+// product-form rank-one modifications; 64 / kp entities per wavefront.  small:
+// every item has at most lowrank_small_nnz() entries (an instance that carries
+// that many entry vectors; the results are the same bit for bit).
+hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
+                                 bool small);
 int32_t lowrank_max_nnz();
+int32_t lowrank_small_nnz();
 // vgram: BF16 state with K > 16 takes the VALU-Gram kernel instead of the MFMA one
 hipError_t launch_update_wave(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
                               bool vgram = false);
