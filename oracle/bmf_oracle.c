@@ -255,6 +255,53 @@ void orc_init_side(int64_t R, int32_t K, uint64_t seed, uint32_t c2, double *out
  * R x K x K and m is R x K (propagated per-row priors, eq. stage2a-stage3).
  * Returns the number of entities whose A failed the Cholesky (then x_n is left
  * unchanged); 0 in every valid run. */
+/* The conditional system of one entity: with G = sum_{d in Omega_n} w_d w_d^T
+ * and s = sum_{d in Omega_n} r_nd w_d (entries ptr[n] .. ptr[n+1] of idx/val),
+ *     A = P_n + tau G,   h = P_n m_n + tau s.
+ * G and hs are scratch (K x K and K). */
+static void orc_cond_system(int32_t K, int64_t e0, int64_t e1, const int32_t *idx, const double *val,
+                            const double *other, const double *Pn, const double *mn, double tau,
+                            double *G, double *hs, double *A, double *h)
+{
+    memset(G, 0, sizeof(double) * (size_t)K * K);
+    memset(hs, 0, sizeof(double) * (size_t)K);
+    for (int64_t e = e0; e < e1; ++e) {
+        const double *w = other + (int64_t)idx[e] * K;
+        const double r = val[e];
+        for (int a = 0; a < K; ++a) {
+            for (int b = 0; b < K; ++b)
+                G[a * K + b] += w[a] * w[b];
+            hs[a] += r * w[a];
+        }
+    }
+    for (int a = 0; a < K; ++a) {
+        double pm = 0.0;
+        for (int b = 0; b < K; ++b) {
+            A[a * K + b] = Pn[a * K + b] + tau * G[a * K + b];
+            pm += Pn[a * K + b] * mn[b];
+        }
+        h[a] = pm + tau * hs[a];
+    }
+}
+
+/* The conditional precision A_n of every entity of one side (R x K x K), as
+ * the update below forms it (for the positive-definiteness pin). */
+void orc_cond_precision(int64_t R, int32_t K, const int64_t *ptr, const int32_t *idx,
+                        const double *val, const double *other, int32_t per_row,
+                        const double *P, const double *m, double tau, double *A)
+{
+    double *G = (double *)malloc(sizeof(double) * (size_t)K * K);
+    double *hs = (double *)malloc(sizeof(double) * (size_t)K);
+    double *h = (double *)malloc(sizeof(double) * (size_t)K);
+    for (int64_t n = 0; n < R; ++n) {
+        const double *Pn = per_row ? P + n * K * K : P;
+        const double *mn = per_row ? m + n * K : m;
+        orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, Pn, mn, tau, G, hs,
+                        A + n * (int64_t)K * K, h);
+    }
+    free(G); free(hs); free(h);
+}
+
 int64_t orc_update_side(int64_t R, int32_t K, const int64_t *ptr, const int32_t *idx,
                         const double *val, const double *other, int32_t per_row,
                         const double *P, const double *m, double tau, uint64_t seed,
@@ -282,25 +329,7 @@ int64_t orc_update_side(int64_t R, int32_t K, const int64_t *ptr, const int32_t 
         for (int64_t n = 0; n < R; ++n) {
             const double *Pn = per_row ? P + n * K * K : P;
             const double *mn = per_row ? m + n * K : m;
-            memset(G, 0, sizeof(double) * (size_t)K * K);
-            memset(hs, 0, sizeof(double) * (size_t)K);
-            for (int64_t e = ptr[n]; e < ptr[n + 1]; ++e) {
-                const double *w = other + (int64_t)idx[e] * K;
-                const double r = val[e];
-                for (int a = 0; a < K; ++a) {
-                    for (int b = 0; b < K; ++b)
-                        G[a * K + b] += w[a] * w[b];
-                    hs[a] += r * w[a];
-                }
-            }
-            for (int a = 0; a < K; ++a) {
-                double pm = 0.0;
-                for (int b = 0; b < K; ++b) {
-                    A[a * K + b] = Pn[a * K + b] + tau * G[a * K + b];
-                    pm += Pn[a * K + b] * mn[b];
-                }
-                h[a] = pm + tau * hs[a];
-            }
+            orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, Pn, mn, tau, G, hs, A, h);
             if (orc_chol(K, A, L) != 0) {
                 failures += 1;
                 continue;

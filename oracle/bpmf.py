@@ -229,23 +229,27 @@ class Oracle:
     def aggregate(self):
         """Per-row aggregated means (Algorithm 2) for every row and column block."""
         I, J, K = self.I, self.J, self.K
-        self.mu_x = []
-        self.mu_w = []
+        self.mu_x, self.lam_x = [], []
+        self.mu_w, self.lam_w = [], []
         self.corrections = 0
         for i in range(I):
             base = self.mm[i * J + 0]
             sib = [self.mm[i * J + j] for j in range(1, J)]
+            lam = []
             mu, ncor = aggregate_side(base["x_mu"], base["x_Lam"],
-                                      [s["x_mu"] for s in sib], [s["x_Lam"] for s in sib], K)
+                                      [s["x_mu"] for s in sib], [s["x_Lam"] for s in sib], K, lam)
             self.corrections += ncor
             self.mu_x.append(mu)
+            self.lam_x.append(np.array(lam))
         for j in range(J):
             base = self.mm[0 * J + j]
             sib = [self.mm[i * J + j] for i in range(1, I)]
+            lam = []
             mu, ncor = aggregate_side(base["w_mu"], base["w_Lam"],
-                                      [s["w_mu"] for s in sib], [s["w_Lam"] for s in sib], K)
+                                      [s["w_mu"] for s in sib], [s["w_Lam"] for s in sib], K, lam)
             self.corrections += ncor
             self.mu_w.append(mu)
+            self.lam_w.append(np.array(lam))
 
     def predict(self, row, col):
         p = self.plan
@@ -259,9 +263,12 @@ class Oracle:
         return out
 
 
-def aggregate_side(mu_b, Lam_b, mus, Lams, K):
-    """Algorithm 2 for every row of one side: returns (mu*, #corrections)."""
+def aggregate_side(mu_b, Lam_b, mus, Lams, K, lam_out=None):
+    """Algorithm 2 for every row of one side: returns (mu*, #corrections); the
+    aggregated precisions Lambda* are appended to lam_out when it is a list."""
     if not mus:
+        if lam_out is not None:
+            lam_out.extend(np.array(Lam_b))
         return mu_b.copy(), 0
     R = mu_b.shape[0]
     Jn = len(mus) + 1
@@ -283,4 +290,6 @@ def aggregate_side(mu_b, Lam_b, mus, Lams, K):
             Lstar = Lstar + Lsj
             rhs = rhs + Lsj @ mj[n]
         out[n] = np.linalg.solve(Lstar, rhs)
+        if lam_out is not None:
+            lam_out.append(Lstar)
     return out, ncor

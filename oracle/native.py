@@ -59,6 +59,8 @@ def lib():
     L.orc_update_side.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _d, _u64,
                                   _u32, _u32, _vp, _i32]
     L.orc_update_side.restype = _i64
+    L.orc_cond_precision.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _d, _vp]
+    L.orc_cond_precision.restype = None
     L.orc_sse.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _vp]
     L.orc_sse.restype = _d
     L.orc_tau_draw.argtypes = [_d, _i64, _d, _d, _u64, _u32, _u32]

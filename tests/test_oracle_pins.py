@@ -499,3 +499,236 @@ def test_pp_linear_gaussian_monte_carlo():
         got = o.mu_w[0][o.plan.col_local[d]]
         sd = np.sqrt(np.diag(np.linalg.inv(A)))
         assert np.all(np.abs(got - mu) < 6 * sd / np.sqrt(nsw) + 0.05 * sd)
+
+
+def test_pp_linear_gaussian_monte_carlo_row_side():
+    """The mirror of the I x 1 case: W frozen at the truth, partition 1 x J,
+    X sampled; the X rows of blocks (0, j), j >= 1, run under the
+    moment-matched prior of block (0, 0) (eq. stage2b), and the aggregated
+    X means approach the full-data conditional means (Theorem 1)."""
+    rng = np.random.default_rng(15)
+    N, D, K, J = 8, 66, 2, 3
+    Xt = rng.standard_normal((N, K))
+    W = rng.standard_normal((D, K))
+    mask = rng.random((N, D)) < 0.5
+    row, col = np.nonzero(mask)
+    val = (np.sum(Xt[row] * W[col], 1) + 0.5 * rng.standard_normal(row.size)).astype(np.float32)
+    o = Oracle(N, D, K, row, col, val, I=1, J=J, sample_tau=False, tau_fixed=4.0, seed=4,
+               burnin=0, thin=1)
+    nsw = 3000
+    for s in (1, 2):
+        o.begin_stage(s)
+        for blk in o.stage_blocks(s):
+            assert blk["x_prop"] == (blk["j"] > 0) and not blk["w_prop"]
+            blk["W"] = np.ascontiguousarray(W[o.plan.col_ids[blk["j"]]])
+            for t in range(nsw):
+                o.update_rows(blk, t)
+                blk["samples_x"].append(blk["X"].copy())
+                blk["samples_w"].append(blk["W"].copy())
+        o.finalize_stage()
+    o.aggregate()
+    r = val.astype(np.float64) - o.ybar
+    for n in range(N):
+        sel = row == n
+        A = np.eye(K) + 4.0 * W[col[sel]].T @ W[col[sel]]
+        mu = np.linalg.solve(A, 4.0 * W[col[sel]].T @ r[sel])
+        got = o.mu_x[0][o.plan.row_local[n]]
+        sd = np.sqrt(np.diag(np.linalg.inv(A)))
+        assert np.all(np.abs(got - mu) < 6 * sd / np.sqrt(nsw) + 0.05 * sd)
+
+
+# ------------------------------------------ exact linear-Gaussian propagation
+def _exact_side(ptr_, idx, r, other, prior, tau, K):
+    """Exact Gaussian posterior (precision, mean) of every entity of one side of
+    a block given the other side frozen: Lambda = P + tau G, mean solves
+    Lambda mu = P m + tau s (the conjugate update of Sec. 2.1, in numpy)."""
+    n = ptr_.size - 1
+    P, m = prior
+    lam = np.zeros((n, K, K))
+    mu = np.zeros((n, K))
+    for e in range(n):
+        Pn = P[e] if P.ndim == 3 else P
+        mn = m[e] if m.ndim == 2 else m
+        w = other[idx[ptr_[e]:ptr_[e + 1]]]
+        lam[e] = Pn + tau * w.T @ w
+        mu[e] = np.linalg.solve(lam[e], Pn @ mn + tau * w.T @ r[ptr_[e]:ptr_[e + 1]])
+    return lam, mu
+
+
+def _exact_pp(oracle_mod, seed=16):
+    """Run the three stages of a 3 x 3 partition with exact Gaussian stage
+    posteriors in place of moment-matched samples: the X side of every block
+    given the true W, the W side given the true X, each under the prior the
+    oracle's begin_stage binds (eq. stage1-stage3).  Returns the oracle after
+    aggregation, the truth and the data."""
+    rng = np.random.default_rng(seed)
+    N, D, K, I, J, tau = 43, 31, 2, 3, 3, 2.5
+    X = rng.standard_normal((N, K))
+    W = rng.standard_normal((D, K))
+    mask = rng.random((N, D)) < 0.85
+    row, col = np.nonzero(mask)
+    val = (np.sum(X[row] * W[col], 1) + rng.standard_normal(row.size)).astype(np.float32)
+    o = oracle_mod.Oracle(N, D, K, row, col, val, I=I, J=J, order="random", sample_tau=False,
+                          tau_fixed=tau, seed=seed)
+    for s in (1, 2, 3):
+        o.begin_stage(s)
+        for blk in o.stage_blocks(s):
+            Xb = X[o.plan.row_ids[blk["i"]]]
+            Wb = W[o.plan.col_ids[blk["j"]]]
+            px = blk["x_prior"] if blk["x_prior"] is not None else blk["hx"]
+            pw = blk["w_prior"] if blk["w_prior"] is not None else blk["hw"]
+            xl, xm = _exact_side(blk["csr_ptr"], blk["csr_idx"], blk["csr_val"], Wb, px, tau, K)
+            wl, wm = _exact_side(blk["csc_ptr"], blk["csc_idx"], blk["csc_val"], Xb, pw, tau, K)
+            o.mm[blk["b"]] = dict(x_mu=xm, x_Lam=xl, w_mu=wm, w_Lam=wl, ridged=0)
+    o.aggregate()
+    return o, X, W, row, col, val, tau
+
+
+def _exact_pp_check(o, X, W, row, col, val, tau):
+    """Theorem 1: the aggregated precision and mean of every row and column
+    equal the full-data conditional ones (prior (I, 0), all observed entries)."""
+    K = X.shape[1]
+    r = val.astype(np.float64) - o.ybar
+    assert o.corrections == 0
+    for n in range(o.N):
+        sel = row == n
+        lam = np.eye(K) + tau * W[col[sel]].T @ W[col[sel]]
+        mu = np.linalg.solve(lam, tau * W[col[sel]].T @ r[sel])
+        i, loc = o.plan.row_block[n], o.plan.row_local[n]
+        np.testing.assert_allclose(o.lam_x[i][loc], lam, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(o.mu_x[i][loc], mu, rtol=1e-10, atol=1e-10)
+    for d in range(o.D):
+        sel = col == d
+        lam = np.eye(K) + tau * X[row[sel]].T @ X[row[sel]]
+        mu = np.linalg.solve(lam, tau * X[row[sel]].T @ r[sel])
+        j, loc = o.plan.col_block[d], o.plan.col_local[d]
+        np.testing.assert_allclose(o.lam_w[j][loc], lam, rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(o.mu_w[j][loc], mu, rtol=1e-10, atol=1e-10)
+
+
+def test_pp_exact_gaussian_stages_aggregate_to_full_posterior():
+    """Both prior bindings of begin_stage (X of (i, j) from (i, 0), W from
+    (0, j)) and both loops of Algorithm 2 reproduce the full-data conditional
+    exactly when every stage posterior is the exact Gaussian (Theorem 1)."""
+    from oracle import bpmf
+    _exact_pp_check(*_exact_pp(bpmf))
+
+
+def _mutant(old, new):
+    """The oracle's bpmf module with one planted mistake (CPU only)."""
+    import types
+    from oracle import bpmf
+    src = open(bpmf.__file__).read()
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("oracle._mutant")
+    mod.__package__ = "oracle"
+    mod.__file__ = bpmf.__file__
+    exec(compile(src.replace(old, new), bpmf.__file__ + " (mutant)", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("old,new", [
+    ("src = self.mm[i * self.J + 0]", "src = self.mm[0 * self.J + i]"),          # X binding
+    ("src = self.mm[0 * self.J + j]", "src = self.mm[j * self.J + 0]"),          # W binding
+    ("base = self.mm[i * J + 0]", "base = self.mm[0 * J + i]"),                  # X base
+    ("sib = [self.mm[i * J + j] for j in range(1, J)]",
+     "sib = [self.mm[j * J + i] for j in range(1, J)]"),                         # X siblings
+    ("base = self.mm[0 * J + j]", "base = self.mm[j * J + 0]"),                  # W base
+    ("sib = [self.mm[i * J + j] for i in range(1, I)]",
+     "sib = [self.mm[j * J + i] for i in range(1, I)]"),                         # W siblings
+    ("Lstar = (2 - Jn) * Lb", "Lstar = (1 - Jn) * Lb"),                          # (2 - J) term
+])
+def test_exact_pin_fails_on_planted_index_mistakes(old, new):
+    with pytest.raises((AssertionError, KeyError, IndexError, ValueError, np.linalg.LinAlgError)):
+        _exact_pp_check(*_exact_pp(_mutant(old, new)))
+
+
+# ------------------------------------------------------------- P4, P5, P6
+def test_conditional_precisions_are_spd_above_prior():
+    """Every conditional precision the update forms passes Cholesky, and its
+    smallest eigenvalue is at least the prior's (P + tau G with G PSD)."""
+    rng = np.random.default_rng(17)
+    K, R, C = 5, 40, 30
+    deg = rng.integers(0, 9, size=R)
+    ptr_ = np.zeros(R + 1, dtype=np.int64)
+    np.cumsum(deg, out=ptr_[1:])
+    idx = np.concatenate([np.sort(rng.choice(C, size=k, replace=False)) for k in deg]).astype(np.int32)
+    val = rng.standard_normal(ptr_[-1])
+    W = rng.standard_normal((C, K)) * rng.uniform(0.01, 3.0, size=(C, 1))
+    P = np.zeros((R, K, K))
+    for n in range(R):
+        Q, _ = np.linalg.qr(rng.standard_normal((K, K)))
+        P[n] = Q @ np.diag(10.0 ** rng.uniform(-6, 2, size=K)) @ Q.T
+        P[n] = 0.5 * (P[n] + P[n].T)
+    m = rng.standard_normal((R, K))
+    tau = 0.7
+    A = np.zeros((R, K, K))
+    L().orc_cond_precision(R, K, ptr(ptr_), ptr(idx), ptr(val), ptr(W), 1, ptr(P), ptr(m), tau,
+                           ptr(A))
+    for n in range(R):
+        w = W[idx[ptr_[n]:ptr_[n + 1]]]
+        np.testing.assert_allclose(A[n], P[n] + tau * np.einsum("ea,eb->ab", w, w), rtol=1e-12,
+                                   atol=1e-12 * np.abs(A[n]).max())
+        assert native.cholesky(A[n]) is not None
+        lo = np.linalg.eigvalsh(A[n])[0]
+        assert lo > 0 and lo >= np.linalg.eigvalsh(P[n])[0] * (1 - 1e-9)
+        if deg[n] == 0:
+            assert np.array_equal(A[n], P[n])
+
+
+def test_prediction_invariant_under_sign_flip():
+    """Negating latent coordinate k of every X and W posterior (means, and the
+    precisions conjugated by the sign matrix) leaves the predictions unchanged
+    (the sign ambiguity of Sec. 2.1); negating X alone does not."""
+    d = synth.make("ratings", 120, 70, 3, 3000, 0.8, 2)
+    o = Oracle(d["N"], d["D"], 3, d["row"], d["col"], d["val"], I=2, J=2, order="random", seed=5,
+               burnin=6)
+    o.run_pp(20)
+    o.aggregate()
+    p1 = o.predict(d["test_row"], d["test_col"])
+    k = 1
+    S = np.ones(3)
+    S[k] = -1.0
+    saved = {b: {key: v.copy() if isinstance(v, np.ndarray) else v for key, v in mm.items()}
+             for b, mm in o.mm.items()}
+    for mm in o.mm.values():
+        for side in ("x", "w"):
+            mm[side + "_mu"] = mm[side + "_mu"] * S
+            mm[side + "_Lam"] = mm[side + "_Lam"] * S[:, None] * S[None, :]
+    o.aggregate()
+    p2 = o.predict(d["test_row"], d["test_col"])
+    np.testing.assert_allclose(p2, p1, rtol=1e-12, atol=1e-12)
+    o.mm = saved
+    for mm in o.mm.values():
+        mm["x_mu"] = mm["x_mu"] * S
+        mm["x_Lam"] = mm["x_Lam"] * S[:, None] * S[None, :]
+    o.aggregate()
+    p3 = o.predict(d["test_row"], d["test_col"])
+    assert np.abs(p3 - p1).max() > 1e-3
+
+
+def test_one_block_pp_is_plain_bpmf():
+    """With a 1 x 1 partition, PP's stage 1 is plain BPMF (Theorem 1): the
+    chain run as a PP stage equals the plain sweep loop, and the aggregated
+    posterior mean is the kept-sample mean with its precision the inverse
+    sample covariance."""
+    d = synth.make("ratings", 150, 80, 4, 3000, 0.8, 3)
+    a = Oracle(d["N"], d["D"], 4, d["row"], d["col"], d["val"], seed=9, burnin=5)
+    a.run_pp(25)
+    a.aggregate()
+    b = Oracle(d["N"], d["D"], 4, d["row"], d["col"], d["val"], seed=9, burnin=5)
+    b.begin_stage(1)
+    for _ in range(25):
+        b.sweep_block(b.blocks[0])
+    assert np.array_equal(a.blocks[0]["X"], b.blocks[0]["X"])
+    assert np.array_equal(a.blocks[0]["W"], b.blocks[0]["W"])
+    sx = np.stack(b.blocks[0]["samples_x"])
+    assert sx.shape[0] == 20
+    np.testing.assert_allclose(a.mu_x[0], sx.mean(0), rtol=1e-13, atol=1e-14)
+    for n in (0, 7, 31):
+        np.testing.assert_allclose(a.lam_x[0][n], np.linalg.inv(np.cov(sx[:, n].T)), rtol=1e-9)
+    p = a.predict(d["test_row"], d["test_col"])
+    sw = np.stack(b.blocks[0]["samples_w"])
+    q = a.ybar + np.einsum("ek,ek->e", sx.mean(0)[a.plan.row_local[d["test_row"]]],
+                           sw.mean(0)[a.plan.col_local[d["test_col"]]])
+    np.testing.assert_allclose(p, q, rtol=1e-12)
