@@ -49,21 +49,34 @@ typedef enum {
     BMF_EDEVICE = 3,      /* a HIP call failed, or no usable gfx950 device */
     BMF_ENOTPD = 4,       /* a precision matrix failed its Cholesky in FP64 */
     BMF_ESTATE = 5,       /* call out of order (e.g. stage 3 before stage 2) */
-    BMF_EUNSUPPORTED = 6  /* valid request outside what this build supports (K > 64) */
+    BMF_EUNSUPPORTED = 6, /* valid request outside what this build supports (K > 64) */
+    BMF_EABORT = 7        /* the progress callback asked to stop (bmf_set_progress) */
 } bmf_status;
 
-/* Arithmetic of the row/column conditional updates.  Hyperparameter, tau,
- * moment-matching and aggregation arithmetic is FP64 in every mode.  In the
- * FP32 and BF16 modes with K > 16, an entity with at most eight entries under a
- * propagated (moment-matched) prior skips the Cholesky: its prior's factor,
- * computed once per stage in FP64 and stored in FP32, is applied directly (no
- * entries) or updated by rank-one modifications (one to eight), giving the
- * same factor and draw up to rounding. */
+/* Storage and arithmetic of the row/column conditional updates.
+ * Hyperparameter, tau, moment-matching and aggregation arithmetic is FP64 in
+ * every mode.  In the FP32 and BF16 modes with K > 16, an entity with at most
+ * eight entries under a propagated (moment-matched) prior skips the Cholesky:
+ * its prior's factor, computed once per stage in FP64 and stored in FP32, is
+ * applied directly (no entries) or updated by rank-one modifications (one to
+ * eight), giving the same factor and draw up to rounding.
+ *
+ * BF16 mode stores the chain state itself (every X and W row) in BF16: each
+ * draw is computed in FP32 from BF16 inputs, then rounded to nearest even for
+ * the state, so the Normal-Wishart statistics, the tau residuals, the next
+ * pass's gathers and bmf_get_state all see the rounded values.  The kept
+ * samples (moment matching, prediction) and bmf_get_draw / bmf_get_sample hold
+ * the FP32 draw before rounding.  Against the FP64 conditional draw from the
+ * same (BF16) inputs and noise, the FP32 draw is within about 1e-5 relative
+ * (FP32 arithmetic) and the stored state within 2^-9 relative per entry on
+ * top of that (the rounding). */
 typedef enum {
-    BMF_PREC_FP64 = 0,    /* FP64 gathers, Gram, Cholesky and solves */
-    BMF_PREC_FP32 = 1,    /* FP32 gathers and Gram; FP32 Cholesky with FP64 fallback */
-    BMF_PREC_BF16 = 2     /* BF16 copies of the gathered factors, FP32 accumulation,
-                             FP32 Cholesky with FP64 fallback */
+    BMF_PREC_FP64 = 0,    /* FP64 state, gathers, Gram, Cholesky and solves */
+    BMF_PREC_FP32 = 1,    /* FP32 state and gathers, FP32 Gram; FP32 Cholesky with
+                             FP64 fallback */
+    BMF_PREC_BF16 = 2     /* BF16 state (so BF16 gathers), FP32 accumulation of
+                             exact BF16 products (MFMA for K > 16), FP32 Cholesky
+                             with FP64 fallback, FP32 kept samples */
 } bmf_precision;
 
 /* Row/column ordering before partitioning (Sec. 5.2): the given ids, a random
@@ -76,7 +89,10 @@ typedef enum {
 } bmf_order;
 
 typedef struct {
-    /* data: COO training set, host memory, 0-based, no duplicate (row, col) */
+    /* data: COO training set, host memory, 0-based, no duplicate (row, col).
+     * The largest row or column part times the factor row stride in bytes
+     * (K rounded up to 16 bytes; K at 32 and 64) must stay below 2^32, since
+     * the gather kernels form 32-bit row offsets (BMF_EUNSUPPORTED otherwise). */
     int64_t N, D;                /* matrix shape */
     int32_t K;                   /* rank, 1 <= K <= 64 */
     int64_t nnz;                 /* number of observed training entries */
@@ -225,9 +241,46 @@ bmf_status bmf_get_aggregate(bmf_ctx *c, int32_t side, double *mu);
 /* Counters accumulated since bmf_init: rows redone in FP64 after a failed
  * FP32 pivot test, rows whose FP64 precision failed its Cholesky, rows whose
  * moment-matched covariance needed the ridge, aggregation eigenvalue
- * corrections.  Any output may be NULL. */
+ * corrections; and train_sse, the residual sum of squares of the centred
+ * training values, sum over observed (r_nd - x_n^T w_d)^2, over every block of
+ * the active stage, as evaluated by the last sweep's column pass (the
+ * statistic of the tau draw, eq. BMF_likelihood_normal; FP64; 0 before the
+ * first sweep of a stage).  Any output may be NULL. */
 bmf_status bmf_get_stats(bmf_ctx *c, int64_t *fallback_rows, int64_t *nonpd_rows,
-                         int64_t *mm_ridged, int64_t *agg_corrections);
+                         int64_t *mm_ridged, int64_t *agg_corrections, double *train_sse);
+
+/* Kept sample `slot` (0 = first kept sweep) of block b of the active stage,
+ * side 0 (X rows) or 1 (W columns), in the sample precision (FP64, or the
+ * FP32 draw before any BF16 rounding): x (n x K, FP64 host).  BMF_EINVAL when
+ * the slot has not been written in this stage. */
+bmf_status bmf_get_sample(bmf_ctx *c, int32_t b, int32_t side, int32_t slot, double *x);
+
+/* Progress callback: called on the host before every sweep that
+ * bmf_gibbs_sweep or bmf_pp_stage is about to enqueue, with the stage and the
+ * sweep index within it.  A non-zero return stops the call with BMF_EABORT
+ * before that sweep is enqueued: the context then holds the consistent state
+ * after the previous sweep, which bmf_save_state can write and a later
+ * bmf_gibbs_sweep continues exactly (every draw is addressed by its Philox
+ * counter).  fn = NULL removes the callback. */
+typedef int32_t (*bmf_progress_fn)(void *user, int32_t stage, int64_t sweep);
+bmf_status bmf_set_progress(bmf_ctx *c, bmf_progress_fn fn, void *user);
+
+/* Checkpoint and resume at stage and sweep granularity (the paper's stages
+ * exchange their propagated posteriors through files, Sec. 5.2 footnote).
+ * bmf_save_state writes one flat binary file (host path): a header (magic,
+ * version, N, D, K, nnz, I, J, order, precision, seed, sampling settings and a
+ * 64-bit fingerprint of the training data), the stage bookkeeping (active
+ * stage, moment-matched stages, sweeps run, samples kept, the update
+ * kernels' lane-group sizing), the counters, and the device arrays that the
+ * rest of the chain depends on: every factor row, hyperparameter slot and tau
+ * of the active stage's blocks, its kept samples, the moment-matched rows of
+ * every finished stage and their prior factors.  bmf_load_state restores them
+ * into a context made by bmf_init with the same configuration and data
+ * (BMF_EINVAL on a header or fingerprint mismatch or a short file); the
+ * chain then continues bit for bit as if it had not been interrupted.  Both
+ * synchronise the context's stream. */
+bmf_status bmf_save_state(bmf_ctx *c, const char *path);
+bmf_status bmf_load_state(bmf_ctx *c, const char *path);
 
 /* Per-kernel timing: when enabled, every launch is bracketed by HIP events on
  * the context's stream (sweeps are then launched eagerly, not from the graph).

@@ -81,7 +81,11 @@ def load():
         "bmf_get_draw": [_vp, _i32, _i32, _vp],
         "bmf_aggregate": [_vp],
         "bmf_get_aggregate": [_vp, _i32, _vp],
-        "bmf_get_stats": [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64)],
+        "bmf_get_stats": [_vp, _P(_i64), _P(_i64), _P(_i64), _P(_i64), _P(_d)],
+        "bmf_get_sample": [_vp, _i32, _i32, _i32, _vp],
+        "bmf_set_progress": [_vp, _vp, _vp],
+        "bmf_save_state": [_vp, ctypes.c_char_p],
+        "bmf_load_state": [_vp, ctypes.c_char_p],
         "bmf_enable_timing": [_vp, _i32],
         "bmf_kernel_times": [_vp, _i32, _vp, _vp, _vp, _P(_i32)],
         "bmf_stage_work": [_vp, _P(_i64), _P(_i64)],
@@ -110,7 +114,12 @@ def exported_symbols():
             "bmf_status_string", "bmf_block_info", "bmf_global_mean", "bmf_get_positions",
             "bmf_get_block_csr", "bmf_get_state", "bmf_set_state", "bmf_step", "bmf_get_draw", "bmf_get_mm",
             "bmf_aggregate", "bmf_get_aggregate", "bmf_get_stats", "bmf_enable_timing",
-            "bmf_kernel_times", "bmf_get_schedule", "bmf_stage_work"]
+            "bmf_kernel_times", "bmf_get_schedule", "bmf_stage_work", "bmf_get_sample",
+            "bmf_set_progress", "bmf_save_state", "bmf_load_state"]
+
+
+# int32_t (*bmf_progress_fn)(void *user, int32_t stage, int64_t sweep)
+PROGRESS_FN = ctypes.CFUNCTYPE(_i32, _vp, _i32, _i64)
 
 
 class BMF:
@@ -291,9 +300,33 @@ class BMF:
 
     def stats(self):
         v = [_i64() for _ in range(4)]
-        self._check(self.L.bmf_get_stats(self.ctx, *[ctypes.byref(x) for x in v]))
+        sse = _d()
+        self._check(self.L.bmf_get_stats(self.ctx, *[ctypes.byref(x) for x in v], ctypes.byref(sse)))
         return dict(fallback_rows=v[0].value, nonpd_rows=v[1].value, mm_ridged=v[2].value,
-                    agg_corrections=v[3].value)
+                    agg_corrections=v[3].value, train_sse=sse.value)
+
+    def get_sample(self, b, side, slot):
+        info = self.block_info(b)
+        n = info["R"] if side == 0 else info["C"]
+        x = np.empty((n, self.K))
+        self._check(self.L.bmf_get_sample(self.ctx, b, side, slot, _ptr(x)))
+        return x
+
+    def set_progress(self, fn):
+        """fn(stage, sweep) -> bool; True stops the running call with BMF_EABORT
+        before that sweep.  None removes the callback."""
+        if fn is None:
+            self._progress = None
+            self._check(self.L.bmf_set_progress(self.ctx, None, None))
+            return
+        self._progress = PROGRESS_FN(lambda user, stage, sweep: 1 if fn(stage, sweep) else 0)
+        self._check(self.L.bmf_set_progress(self.ctx, ctypes.cast(self._progress, _vp), None))
+
+    def save_state(self, path):
+        self._check(self.L.bmf_save_state(self.ctx, os.fsencode(path)))
+
+    def load_state(self, path):
+        self._check(self.L.bmf_load_state(self.ctx, os.fsencode(path)))
 
     def enable_timing(self, on=True):
         self._check(self.L.bmf_enable_timing(self.ctx, 1 if on else 0))

@@ -239,6 +239,11 @@ struct bmf_ctx {
     bool agg_valid = false;
     StageLists S;
     int32_t done_stages[4] = {0, 0, 0, 0};
+    // progress callback (checked before each sweep is enqueued)
+    bmf_progress_fn progress = nullptr;
+    void *progress_user = nullptr;
+    // fingerprint of the training data and settings (checkpoint files)
+    uint64_t fingerprint = 0;
     // timing
     bool timing = false;
     struct Pending { int32_t k; hipEvent_t a, b; };
@@ -302,6 +307,46 @@ bool spd_cholesky(int K, const double *A, std::vector<double> &L) {
     return true;
 }
 
+// 64-bit fingerprint of the training data and of every setting that the
+// chain's values depend on (checkpoint files are only loaded into a context
+// with the same one).  Word-wise multiply-xorshift mixing of the raw bytes.
+struct Mix64 {
+    uint64_t h = 0x9E3779B97F4A7C15ull;
+    void word(uint64_t v) {
+        h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 31;
+    }
+    void bytes(const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t v;
+            std::memcpy(&v, b + i, 8);
+            word(v);
+        }
+        uint64_t t = 0;
+        for (size_t k = 0; i + k < n; ++k) t |= (uint64_t)b[i + k] << (8 * k);
+        word(t ^ ((uint64_t)n << 56));
+    }
+    template <typename T> void val(const T &v) { bytes(&v, sizeof(T)); }
+};
+
+uint64_t data_fingerprint(const bmf_config &c) {
+    Mix64 m;
+    m.val(c.N); m.val(c.D); m.val(c.K); m.val(c.nnz); m.val(c.I); m.val(c.J); m.val(c.order);
+    m.val(c.beta0); m.val(c.nu0); m.val(c.sample_tau); m.val(c.tau_a0); m.val(c.tau_b0); m.val(c.tau_fixed);
+    m.val(c.seed); m.val(c.burnin); m.val(c.thin); m.val(c.max_kept); m.val(c.precision); m.val(c.pivot_theta);
+    if (c.mu0) m.bytes(c.mu0, 8 * (size_t)c.K);
+    if (c.W0) m.bytes(c.W0, 8 * (size_t)c.K * c.K);
+    if (c.nnz > 0) {
+        m.bytes(c.row, 4 * (size_t)c.nnz);
+        m.bytes(c.col, 4 * (size_t)c.nnz);
+        m.bytes(c.val, 4 * (size_t)c.nnz);
+    }
+    return m.h;
+}
+
 bmf_status validate(const bmf_config *cfg, std::string &err) {
     if (!cfg) { err = "null config"; return BMF_EINVAL; }
     const bmf_config &c = *cfg;
@@ -326,6 +371,18 @@ bmf_status validate(const bmf_config *cfg, std::string &err) {
     if (c.precision < BMF_PREC_FP64 || c.precision > BMF_PREC_BF16) { err = "bad precision"; return BMF_EINVAL; }
     if (c.pivot_theta < 0.0 || c.pivot_theta >= 1.0) { err = "pivot_theta must be in [0, 1)"; return BMF_EINVAL; }
     if (c.lane_nnz < 0) { err = "lane_nnz must be >= 0"; return BMF_EINVAL; }
+    {
+        // the gather kernels address a gathered row by a 32-bit byte offset from
+        // its block's first row: the largest part times the row stride must fit
+        const int64_t ebytes = c.precision == BMF_PREC_FP64 ? 8 : (c.precision == BMF_PREC_BF16 ? 2 : 4);
+        const int64_t rowb = (int64_t)stride_for(capacity_for(c.K), (int32_t)ebytes) * ebytes;
+        const int64_t part = std::max((c.N + c.I - 1) / c.I, (c.D + c.J - 1) / c.J);
+        if (part * rowb >= ((int64_t)1 << 32)) {
+            err = "a part of " + std::to_string(part) + " rows at " + std::to_string(rowb) +
+                  " bytes per factor row exceeds the 32-bit gather offsets";
+            return BMF_EUNSUPPORTED;
+        }
+    }
     for (int64_t e = 0; e < c.nnz; ++e)
         if (!std::isfinite(c.val[e])) { err = "non-finite value at entry " + std::to_string(e); return BMF_EINVAL; }
     if (c.W0) {
@@ -983,16 +1040,17 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
     StageLists &S = c->S;
     bmf_status st;
     const int32_t nbs = (int32_t)S.blocks.size();
-    const bool tau = c->cfg.sample_tau != 0;
+    // the column pass always evaluates the residual SSE of every block (the tau
+    // statistic when tau is sampled; the training fit, bmf_get_stats, always)
     if (c->cfg.batched) {
         // one launch per step; the SSE and statistics reductions share a launch
         // (their jobs are contiguous), and the hyperparameter launch advances
         // the sweep state in its last block
         if ((st = run_pass(c, true, 0, nullptr, -1, true))) return st;
-        if ((st = run_pass(c, false, 0, nullptr, -1, true, tau))) return st;
+        if ((st = run_pass(c, false, 0, nullptr, -1, true, true))) return st;
         if ((st = run_stats(c, 0, 2 * nbs, false))) return st;
-        const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce) + (tau ? 0 : nbs);
-        const int32_t nr = (tau ? nbs : 0) + 2 * nbs;
+        const ReduceJob *rj = c->dev<ReduceJob>(c->L.m_reduce);
+        const int32_t nr = 3 * nbs;
         // the reduction launch also draws the Normal-Wishart noise of every
         // hyper job (extra blocks), off the hyperparameter launch's path
         NoiseArgs na{};
@@ -1009,8 +1067,8 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
     } else {
         for (int32_t k = 0; k < nbs; ++k) {
             if ((st = run_pass(c, true, 0, nullptr, k, true))) return st;
-            if ((st = run_pass(c, false, 0, nullptr, k, true, tau))) return st;
-            if (tau && (st = reduce_sse(c, k))) return st;
+            if ((st = run_pass(c, false, 0, nullptr, k, true, true))) return st;
+            if ((st = reduce_sse(c, k))) return st;
             if ((st = run_stats(c, k, k + 1))) return st;
             if ((st = run_stats(c, nbs + k, nbs + k + 1))) return st;
             if ((st = run_hyper(c, S.hyper_begin[k], S.hyper_begin[k + 1], 0, true))) return st;
@@ -1069,6 +1127,19 @@ static bmf_status sweep_once(bmf_ctx *c) {
     if (keep) c->kept += 1;
     c->t += 1;
     c->agg_valid = false;
+    return BMF_OK;
+}
+
+// n sweeps of the active stage; the progress callback may stop the loop
+// before a sweep is enqueued (BMF_EABORT, state after the previous sweep).
+static bmf_status run_sweeps(bmf_ctx *c, int32_t n) {
+    for (int32_t q = 0; q < n; ++q) {
+        if (c->progress && c->progress(c->progress_user, c->stage, c->t) != 0)
+            return fail(c, BMF_EABORT, "stopped by the progress callback before sweep " + std::to_string(c->t) +
+                                           " of stage " + std::to_string(c->stage));
+        bmf_status st = sweep_once(c);
+        if (st) return st;
+    }
     return BMF_OK;
 }
 
@@ -1193,6 +1264,11 @@ static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
         build_tiles(c, v, v);
         if ((st = upload_tiles(c))) return st;
     }
+    {
+        std::vector<double> z(S.blocks.size(), 0.0);
+        if ((st = upload(c, L.sse_final, z.data(), 8 * z.size()))) return st;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     if ((st = write_sweep_state(c, 0, 0))) return st;
     c->stage = s;
     c->t = 0;
@@ -1285,6 +1361,7 @@ const char *bmf_status_string(bmf_status s) {
     case BMF_ENOTPD: return "BMF_ENOTPD";
     case BMF_ESTATE: return "BMF_ESTATE";
     case BMF_EUNSUPPORTED: return "BMF_EUNSUPPORTED";
+    case BMF_EABORT: return "BMF_EABORT";
     }
     return "unknown status";
 }
@@ -1351,6 +1428,7 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     double s = 0.0;
     for (int64_t e = 0; e < cfg->nnz; ++e) s += (double)cfg->val[e];
     c->ybar = cfg->nnz > 0 ? s / (double)cfg->nnz : 0.0;
+    c->fingerprint = data_fingerprint(*cfg);
     st = build_plan(*cfg, c->plan, err);
     if (st) {
         *out = c;
@@ -1488,9 +1566,7 @@ bmf_status bmf_gibbs_sweep(bmf_ctx *c, int32_t nsweeps) {
     bmf_status st;
     if (c->stage == 0 && (st = begin_stage(c, 1))) return st;
     if (c->finalized >= c->stage) c->finalized = c->stage - 1;   // more samples: redo MM later
-    for (int32_t q = 0; q < nsweeps; ++q)
-        if ((st = sweep_once(c))) return st;
-    return BMF_OK;
+    return run_sweeps(c, nsweeps);
 }
 
 bmf_status bmf_pp_stage(bmf_ctx *c, int32_t stage, int32_t nsweeps) {
@@ -1511,9 +1587,7 @@ bmf_status bmf_pp_stage(bmf_ctx *c, int32_t stage, int32_t nsweeps) {
     }
     bmf_status st = begin_stage(c, stage);
     if (st) return st;
-    for (int32_t q = 0; q < nsweeps; ++q)
-        if ((st = sweep_once(c))) return st;
-    return BMF_OK;
+    return run_sweeps(c, nsweeps);
 }
 
 bmf_status bmf_aggregate(bmf_ctx *c) {
@@ -1857,12 +1931,21 @@ bmf_status bmf_get_aggregate(bmf_ctx *c, int32_t side, double *mu) {
 }
 
 bmf_status bmf_get_stats(bmf_ctx *c, int64_t *fallback_rows, int64_t *nonpd_rows, int64_t *mm_ridged,
-                         int64_t *agg_corrections) {
+                         int64_t *agg_corrections, double *train_sse) {
     if (!c) return BMF_EINVAL;
     if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
     int32_t h[kNumCounters];
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipMemcpy(h, c->base + c->L.counters, sizeof(h), hipMemcpyDeviceToHost));
+    if (train_sse) {
+        *train_sse = 0.0;
+        const size_t nbs = c->stage > 0 ? c->S.blocks.size() : 0;
+        if (nbs > 0) {
+            std::vector<double> v(nbs);
+            HIPCHK(c, hipMemcpy(v.data(), c->base + c->L.sse_final, 8 * nbs, hipMemcpyDeviceToHost));
+            for (double x : v) *train_sse += x;
+        }
+    }
     if (fallback_rows) *fallback_rows = h[kFbTotal];
     if (nonpd_rows) *nonpd_rows = h[kNonPD];
     if (mm_ridged) *mm_ridged = h[kRidged];
@@ -1909,6 +1992,237 @@ bmf_status bmf_stage_work(const bmf_ctx *c, int64_t *row_updates, int64_t *ratin
     if (!c) return BMF_EINVAL;
     if (row_updates) *row_updates = c->S.row_updates;
     if (ratings) *ratings = c->S.ratings;
+    return BMF_OK;
+}
+
+bmf_status bmf_get_sample(bmf_ctx *c, int32_t b, int32_t side, int32_t slot, double *x) {
+    if (!c || !x || side < 0 || side > 1) return BMF_EINVAL;
+    if (!c->device || c->stage == 0) return fail(c, BMF_ESTATE, "no active stage");
+    const int32_t k = stage_index(c, b);
+    if (k < 0) return fail(c, BMF_EINVAL, "block is not in the active stage");
+    if (slot < 0 || slot >= c->kept) return fail(c, BMF_EINVAL, "sample slot not written in this stage");
+    const Layout &L = c->L;
+    const int32_t nbs = (int32_t)c->S.blocks.size();
+    const SideDesc &sd = c->S.sides[side == 0 ? k : nbs + k];
+    const int32_t K = c->cfg.K;
+    const int64_t slot_bytes = L.Emax * L.ks_p * L.sp;
+    std::vector<char> buf((size_t)((int64_t)sd.n * L.ks_p * L.sp));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(buf.data(), c->base + L.sample + slot * slot_bytes + sd.sample_off * L.ks_p * L.sp,
+                        buf.size(), hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < sd.n; ++r)
+        for (int q = 0; q < K; ++q)
+            x[r * K + q] = c->fp64() ? reinterpret_cast<double *>(buf.data())[r * L.ks_p + q]
+                                     : (double)reinterpret_cast<float *>(buf.data())[r * L.ks_p + q];
+    return BMF_OK;
+}
+
+bmf_status bmf_set_progress(bmf_ctx *c, bmf_progress_fn fn, void *user) {
+    if (!c) return BMF_EINVAL;
+    c->progress = fn;
+    c->progress_user = user;
+    return BMF_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// checkpoint files
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr char kCkptMagic[8] = {'B', 'M', 'F', 'C', 'K', 'P', 'T', 0};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    int64_t N, D, nnz;
+    int32_t K, I, J, order, precision, max_kept;
+    uint64_t seed, fingerprint;
+    // layout the arrays were written with
+    int64_t Emax, ks_m, ss, ks_p, sp, prow, pfrow, hy;
+    // stage bookkeeping
+    int32_t stage, finalized, kept, lane_row, lane_col, done[4], pad;
+    int64_t t;
+};
+
+CkptHeader header_of(const bmf_ctx *c) {
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.version = kCkptVersion;
+    h.header_bytes = (uint32_t)sizeof(CkptHeader);
+    h.N = c->cfg.N;
+    h.D = c->cfg.D;
+    h.nnz = c->cfg.nnz;
+    h.K = c->cfg.K;
+    h.I = c->cfg.I;
+    h.J = c->cfg.J;
+    h.order = c->cfg.order;
+    h.precision = c->cfg.precision;
+    h.max_kept = c->cfg.max_kept;
+    h.seed = c->cfg.seed;
+    h.fingerprint = c->fingerprint;
+    h.Emax = c->L.Emax;
+    h.ks_m = c->L.ks_m;
+    h.ss = c->L.ss;
+    h.ks_p = c->L.ks_p;
+    h.sp = c->L.sp;
+    h.prow = c->L.prow;
+    h.pfrow = c->L.pfrow;
+    h.hy = c->L.hy;
+    return h;
+}
+
+// One device byte range, written to or read from the file through a host buffer.
+struct Span {
+    int64_t off, bytes;
+};
+
+// Every device range a checkpoint holds, in file order: counters, sweep state;
+// for the active stage per block the X and W rows, the hyperparameter slots,
+// tau and the last SSE, then its kept samples; the moment-matched rows of
+// every finished stage's blocks; the prior factors.
+std::vector<Span> ckpt_spans(const bmf_ctx *c, int32_t stage, int32_t finalized, int32_t kept) {
+    const Layout &L = c->L;
+    const Plan &P = c->plan;
+    std::vector<Span> v;
+    v.push_back({L.counters, 4 * (int64_t)kNumCounters});
+    v.push_back({L.sweep, (int64_t)sizeof(SweepState)});
+    if (stage > 0) {
+        int64_t ents = 0;
+        int32_t k = 0;
+        for (int32_t b = 0; b < (int32_t)P.blocks.size(); ++b) {
+            const PlanBlock &B = P.blocks[b];
+            if (B.stage != stage) continue;
+            v.push_back({L.X + c->x_off[b] * L.ks_m * L.ss, B.R * L.ks_m * L.ss});
+            v.push_back({L.W + c->w_off[b] * L.ks_m * L.ss, B.C * L.ks_m * L.ss});
+            v.push_back({L.hyper + (int64_t)b * 2 * L.hy * 8, 16 * (int64_t)L.hy});
+            v.push_back({L.tau + 8 * (int64_t)b, 8});
+            v.push_back({L.sse_final + 8 * (int64_t)k, 8});
+            ents += B.R + B.C;
+            ++k;
+        }
+        const int64_t slot_bytes = L.Emax * L.ks_p * L.sp;
+        for (int32_t q = 0; q < kept; ++q) v.push_back({L.sample + q * slot_bytes, ents * L.ks_p * L.sp});
+    }
+    for (int32_t b = 0; b < (int32_t)P.blocks.size(); ++b) {
+        const PlanBlock &B = P.blocks[b];
+        if (B.stage > finalized) continue;
+        v.push_back({L.mm + c->x_off[b] * L.prow * 8, B.R * L.prow * 8});
+        v.push_back({L.mm + (L.E_r + c->w_off[b]) * L.prow * 8, B.C * L.prow * 8});
+    }
+    if (L.pfrow) v.push_back({L.pfac, 4 * (P.N + P.D) * (int64_t)L.pfrow});
+    return v;
+}
+
+constexpr int64_t kCkptChunk = 64 << 20;
+
+}  // namespace
+
+extern "C" {
+
+bmf_status bmf_save_state(bmf_ctx *c, const char *path) {
+    if (!c) return BMF_EINVAL;
+    if (!path) return fail(c, BMF_EINVAL, "null path");
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    CkptHeader h = header_of(c);
+    h.stage = c->stage;
+    h.finalized = c->finalized;
+    h.kept = c->kept;
+    h.lane_row = c->S.lane_row;
+    h.lane_col = c->S.lane_col;
+    for (int q = 0; q < 4; ++q) h.done[q] = c->done_stages[q];
+    h.t = c->t;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(c, BMF_EINVAL, std::string("cannot open ") + path + " for writing");
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+    std::vector<char> buf;
+    for (const Span &sp : ckpt_spans(c, h.stage, h.finalized, h.kept)) {
+        for (int64_t o = 0; ok && o < sp.bytes; o += kCkptChunk) {
+            const int64_t n = std::min(kCkptChunk, sp.bytes - o);
+            buf.resize((size_t)n);
+            if (hipMemcpy(buf.data(), c->base + sp.off + o, (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) {
+                std::fclose(f);
+                return fail(c, BMF_EDEVICE, "device read for the checkpoint failed");
+            }
+            ok = std::fwrite(buf.data(), 1, (size_t)n, f) == (size_t)n;
+        }
+        if (!ok) break;
+    }
+    if (std::fclose(f) != 0) ok = false;
+    if (!ok) return fail(c, BMF_EINVAL, std::string("write to ") + path + " failed");
+    return BMF_OK;
+}
+
+bmf_status bmf_load_state(bmf_ctx *c, const char *path) {
+    if (!c) return BMF_EINVAL;
+    if (!path) return fail(c, BMF_EINVAL, "null path");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(c, BMF_EINVAL, std::string("cannot open ") + path);
+    CkptHeader h{};
+    const bool got = std::fread(&h, sizeof(h), 1, f) == 1;
+    const CkptHeader want = header_of(c);
+    std::string why;
+    if (!got || std::memcmp(h.magic, kCkptMagic, 8) != 0) why = "not a checkpoint file";
+    else if (h.version != kCkptVersion || h.header_bytes != sizeof(CkptHeader)) why = "checkpoint version differs";
+    else if (h.N != want.N || h.D != want.D || h.nnz != want.nnz || h.K != want.K || h.I != want.I ||
+             h.J != want.J || h.order != want.order || h.precision != want.precision ||
+             h.max_kept != want.max_kept || h.seed != want.seed)
+        why = "checkpoint was written for another configuration";
+    else if (h.fingerprint != want.fingerprint) why = "checkpoint was written for other training data or settings";
+    else if (h.Emax != want.Emax || h.ks_m != want.ks_m || h.ss != want.ss || h.ks_p != want.ks_p ||
+             h.sp != want.sp || h.prow != want.prow || h.pfrow != want.pfrow || h.hy != want.hy)
+        why = "checkpoint layout differs";
+    else if (h.stage < 0 || h.stage > 3 || h.finalized < 0 || h.finalized > h.stage || h.kept < 0 ||
+             h.kept > want.max_kept || h.t < 0 || (h.stage > 0 && !stage_has_blocks(c, h.stage)))
+        why = "checkpoint bookkeeping is out of range";
+    if (!why.empty()) {
+        std::fclose(f);
+        return fail(c, BMF_EINVAL, why + ": " + path);
+    }
+    if (!c->device) {
+        std::fclose(f);
+        return fail(c, BMF_ESTATE, "context has no device state");
+    }
+    bmf_status st = BMF_OK;
+    drop_graph(c);
+    c->stage = 0;
+    c->agg_valid = false;
+    if (h.stage > 0) {
+        build_stage_lists(c, h.stage);
+        if ((st = upload_stage(c)) == BMF_OK) {
+            build_tiles(c, h.lane_row > 0 ? h.lane_row : 32, h.lane_col > 0 ? h.lane_col : 32);
+            st = upload_tiles(c);
+        }
+        if (st) {
+            std::fclose(f);
+            return st;
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<char> buf;
+    bool ok = true;
+    for (const Span &sp : ckpt_spans(c, h.stage, h.finalized, h.kept)) {
+        for (int64_t o = 0; ok && o < sp.bytes; o += kCkptChunk) {
+            const int64_t n = std::min(kCkptChunk, sp.bytes - o);
+            buf.resize((size_t)n);
+            ok = std::fread(buf.data(), 1, (size_t)n, f) == (size_t)n;
+            if (ok && hipMemcpy(c->base + sp.off + o, buf.data(), (size_t)n, hipMemcpyHostToDevice) != hipSuccess) {
+                std::fclose(f);
+                return fail(c, BMF_EDEVICE, "device write from the checkpoint failed");
+            }
+        }
+        if (!ok) break;
+    }
+    std::fclose(f);
+    if (!ok) return fail(c, BMF_EINVAL, std::string("checkpoint is truncated: ") + path);
+    c->stage = h.stage;
+    c->finalized = h.finalized;
+    c->kept = h.kept;
+    c->t = h.t;
+    for (int q = 0; q < 4; ++q) c->done_stages[q] = h.done[q];
     return BMF_OK;
 }
 

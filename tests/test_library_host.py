@@ -156,3 +156,39 @@ def test_workspace_size_grows_with_problem():
         assert L.bmf_workspace_size(ctypes.byref(c), ctypes.byref(s)) == 0
         sizes.append(s.value)
     assert sizes[0] < sizes[1] < sizes[2] < sizes[3]
+
+
+def test_gather_offsets_that_would_wrap_are_rejected():
+    # FP32, K = 16: 64-byte factor rows; a part of 2^26 rows reaches 2^32 bytes
+    N, D, row, col, val = _data(seed=9)
+    _expect("BMF_EUNSUPPORTED", N=1 << 26, K=16, nu0=16.0, precision="fp32")
+    _expect("BMF_EUNSUPPORTED", D=1 << 27, K=16, nu0=16.0, precision="bf16")   # 32-byte rows
+    # the same part split in two fits
+    m = BMF(1 << 26, D, 16, row, col, val, I=2, nu0=16.0, precision="fp32", device=False)
+    assert m.block_info(0)["R"] == 1 << 25
+
+
+def test_checkpoint_header_checked_before_device(tmp_path):
+    N, D, row, col, val = _data(seed=10)
+    m = BMF(N, D, 4, row, col, val, device=False)
+    with pytest.raises(BMFError) as e:
+        m.load_state(str(tmp_path / "missing.bin"))
+    assert e.value.status == "BMF_EINVAL"
+    junk = tmp_path / "junk.bin"
+    junk.write_bytes(b"not a checkpoint" * 40)
+    with pytest.raises(BMFError) as e:
+        m.load_state(str(junk))
+    assert e.value.status == "BMF_EINVAL" and "not a checkpoint" in str(e.value)
+    with pytest.raises(BMFError) as e:
+        m.save_state(str(tmp_path / "x.bin"))
+    assert e.value.status == "BMF_ESTATE"
+
+
+def test_progress_callback_registers_on_host_context():
+    N, D, row, col, val = _data(seed=11)
+    m = BMF(N, D, 4, row, col, val, device=False)
+    seen = []
+    m.set_progress(lambda stage, sweep: seen.append((stage, sweep)) or False)
+    m.set_progress(None)
+    assert seen == []
+    assert load().bmf_status_string(7).decode() == "BMF_EABORT"
