@@ -1,12 +1,18 @@
-"""Benchmark: Gibbs sweeps of BPMF on one MI355X.
+"""Benchmark: Gibbs sweeps of BPMF under posterior propagation on one MI355X.
 
-A step is one full sweep of the hot path over the workload: every row given
-W, every column given the new X, the Normal-Wishart draws, the tau draw and
-the sample store.  Default workload: the ratings-shaped single block
-N = 70,000, D = 10,700, K = 10, 10M observed entries (9M train), Zipf(1.2)
-degrees (synthetic, seeded).  The headline arm runs in BF16 state precision,
-batched; the plain FP32 arm is timed beside it and both chains' test RMSE
-after burn-in are reported.
+Default workload: the ratings-shaped 480,000 x 17,800 matrix, K = 32, 100M
+observed entries (90M train), Zipf(1.2) degrees with a heavy head, partitioned
+8 x 8 in decreasing order of observations (synthetic, seeded).  A step is one
+sweep of each of the three PP stages: all 64 blocks once (every row given W,
+every column given the new X, the Normal-Wishart draws of the non-propagated
+sides, the tau draw and the sample store), so the whole job's throughput is
+the training entries of all blocks over the summed per-sweep times of the
+stages (stages run in order: each needs the previous one's moment-matched
+priors).  The headline arm keeps the chain state in BF16 and runs every stage
+batched (one launch per pass over all of the stage's blocks, each sweep
+replayed from a captured HIP graph); the plain FP32 arm (FP32 state, one launch
+sequence per block, no graph) is timed beside it, and both arms' test RMSE
+after their full chains (three chain seeds) are reported.
 
 Prints one JSON line.  `--gpus N` with N > 1 is not supported (one GPU).
 """
@@ -28,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # entities with at most this many entries under a propagated prior take the
 # low-rank kernel (the library's own threshold)
 LOWRANK_NNZ = 8
+CHAIN_SEEDS = (101, 102, 103)
 
 
 def parse():
@@ -35,20 +42,29 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--config", type=int, default=2)
+    p.add_argument("--config", type=int, default=5)
     p.add_argument("--seed", type=int, default=1)
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--no-rmse", action="store_true", help="skip the equal-RMSE chains")
-    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--chains", type=int, default=3, help="chain seeds per arm for the RMSE")
+    p.add_argument("--cpu-seconds", type=float, default=24.0,
+                   help="oracle time budget with all host threads (the 1-thread run gets half)")
     p.add_argument("--batched-only", action="store_true",
                    help="skip the plain FP32 arm (for profiler runs)")
+    p.add_argument("--trace", default="",
+                   help="write a per-sweep JSONL trace (train RMSE, tau, counters) of the first "
+                        "headline chain to this path")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run 5 device-to-device copies of MIB MiB (to scale the HBM "
                         "traffic counters), then exit")
     return p.parse_args()
 
 
-def algorithmic_bytes(kind, M, n, K, state_bytes, kept, n_prop=0, n_empty=0, n_lowrank=0):
+def say(m):
+    print("bench: " + m, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(M, n, K, state_bytes, kept, n_prop=0, n_empty=0, n_lowrank=0):
     """Bytes one update pass must move: per entry a column index and a value
     (8 B) plus the K-element factor row it gathers; per entity its pointer
     pair and its written state row (and sample row when the sweep is kept);
@@ -76,8 +92,8 @@ def kernel_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kclass, config, precision):
-    """HBM bytes per launch of an update pass, from the rocprofv3 FETCH_SIZE and
+def measured_traffic(kclass, config, stage, precision):
+    """HBM bytes per pass of an update pass, from the rocprofv3 FETCH_SIZE and
     WRITE_SIZE counter passes summarised under profiles/ (each counter scaled by
     what it reads for a device copy of known size).  None when no summary covers
     this pass, or when the kernel sources have changed since the counters were
@@ -94,8 +110,8 @@ def measured_traffic(kclass, config, precision):
                 if not line.startswith("traffic-record: "):
                     continue
                 r = json.loads(line[len("traffic-record: "):])
-                if (r["kclass"] == kclass and r["config"] == config and r["precision"] == precision
-                        and r["sources"] == want):
+                if (r["kclass"] == kclass and r["config"] == config and r.get("stage", 1) == stage
+                        and r["precision"] == precision and r["sources"] == want):
                     return r["hbm_bytes_per_launch"]
     return None
 
@@ -110,27 +126,25 @@ def stages_of(cfg):
     return st
 
 
-def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
-    """For every PP stage of the configuration: `warmup` sweeps, then `steps`
-    timed sweeps as launched in production (graph replays when batched), then
-    as many sweeps launched eagerly with HIP events around every kernel.  Every
-    sweep stores a sample (so the next stage has its moment-matched priors).
-    Then, in a second context, the configuration's own chain (sweeps per stage,
-    burn-in) and the test RMSE of its posterior-mean prediction."""
-    import torch
+def _ctx(d, cfg, precision, batched, seed, burnin, kept):
     from paper_1703_00734_amd import BMF
+    return BMF(d["N"], d["D"], d["K"], d["row"], d["col"], d["val"], I=cfg["I"], J=cfg["J"],
+               order=cfg["order"], seed=seed, burnin=burnin, thin=1, max_kept=kept,
+               precision=precision, batched=batched)
 
-    def ctx(burnin, kept):
-        return BMF(d["N"], d["D"], d["K"], d["row"], d["col"], d["val"], I=cfg["I"], J=cfg["J"],
-                   order=cfg["order"], seed=seed, burnin=burnin, thin=1, max_kept=kept,
-                   precision=precision, batched=batched)
 
+def time_stages(d, cfg, precision, batched, steps, warmup):
+    """For every PP stage: `warmup` sweeps, then `steps` timed sweeps as
+    launched in production (graph replays when batched), then as many sweeps
+    launched eagerly with HIP events around every kernel.  Every sweep stores a
+    sample (so the next stage has its moment-matched priors)."""
+    import torch
     stream = torch.cuda.current_stream()
     # moment matching needs more kept samples than the rank: stages that feed a
     # next stage top up their samples with untimed sweeps
     need = 2 * d["K"] + 2
     extra = max(0, need - (warmup + 2 * steps))
-    g = ctx(0, warmup + 2 * steps + extra)
+    g = _ctx(d, cfg, precision, batched, CHAIN_SEEDS[0], 0, warmup + 2 * steps + extra)
     per_stage = {}
     stages = stages_of(cfg)
     for s in stages:
@@ -157,89 +171,188 @@ def run_arm(d, cfg, precision, batched, steps, warmup, rmse, seed):
         row_updates, ratings = g.stage_work()
         # entities with no entries (or at most LOWRANK_NNZ) under a propagated
         # prior: the prior-factor paths take them in FP32/BF16 passes with K > 16
-        empty, lowrank = [0, 0], [0, 0]
-        if precision != "fp64" and d["K"] > 16 and cfg["I"] * cfg["J"] > 1:
-            for b in range(g.nblocks()):
-                info = g.block_info(b)
-                if info["stage"] != s:
+        empty, lowrank, prop = [0, 0], [0, 0], [0, 0]
+        ents = [0, 0]
+        for b in range(g.nblocks()):
+            info = g.block_info(b)
+            if info["stage"] != s:
+                continue
+            bi, bj = divmod(b, cfg["J"])
+            ents[0] += info["R"]
+            ents[1] += info["C"]
+            for side, is_prop in ((0, bj > 0), (1, bi > 0)):
+                if not is_prop:
                     continue
-                bi, bj = divmod(b, cfg["J"])
-                for side, prop in ((0, bj > 0), (1, bi > 0)):
-                    if prop:
-                        deg = np.diff(g.block_csr(b, side)[0])
-                        empty[side] += int(np.count_nonzero(deg == 0))
-                        lowrank[side] += int(np.count_nonzero((deg >= 1) & (deg <= LOWRANK_NNZ)))
-        print("bench: stage %d timed, %.4f ms per sweep" % (s, ms), file=sys.stderr, flush=True)
+                deg = np.diff(g.block_csr(b, side)[0])
+                prop[side] += deg.size
+                if precision != "fp64" and d["K"] > 16:
+                    empty[side] += int(np.count_nonzero(deg == 0))
+                    lowrank[side] += int(np.count_nonzero((deg >= 1) & (deg <= LOWRANK_NNZ)))
+        say("stage %d timed, %.4f ms per sweep" % (s, ms))
         if s != stages[-1] and extra:
             g.gibbs_sweep(extra)
             torch.cuda.synchronize()
         per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
                             ktimes=ktimes, row_updates=row_updates, ratings=ratings,
-                            schedule=g.schedule(), empty_prop=empty, lowrank_prop=lowrank)
+                            schedule=g.schedule(), empty_prop=empty, lowrank_prop=lowrank,
+                            prop=prop, ents=ents)
     out = dict(per_stage=per_stage, stats=g.stats())
     g.close()
-    if rmse:
-        sweeps, burnin = cfg["sweeps"], cfg["burnin"]
-        h = ctx(burnin, sweeps - burnin)
-        t0 = time.perf_counter()
-        for s in stages_of(cfg):
-            h.pp_stage(s, sweeps)
-            torch.cuda.synchronize()
-            print("bench: chain stage %d done" % s, file=sys.stderr, flush=True)
-        p = h.predict(d["test_row"], d["test_col"])
-        torch.cuda.synchronize()
-        out["chain_wall_s"] = time.perf_counter() - t0
-        out["rmse"] = float(np.sqrt(np.mean((p - d["test_val"]) ** 2)))
-        out["rmse_sweeps"] = sweeps
-        out["rmse_burnin"] = burnin
-        h.close()
     return out
 
 
-def rows_cols_of_stage(d, cfg, s, propagated=False):
-    """Rows and columns updated per sweep by the blocks of stage s (with
-    propagated=True: only those under a propagated prior, the rows of blocks
-    off the first block column and the columns of blocks off the first block
-    row)."""
-    N, D, I, J = d["N"], d["D"], cfg["I"], cfg["J"]
-    bs_r, bs_c = -(-N // I), -(-D // J)
-    R = [min(bs_r, N - i * bs_r) for i in range(I)]
-    C = [min(bs_c, D - j * bs_c) for j in range(J)]
-    rows = cols = 0
-    for i in range(I):
-        for j in range(J):
-            st = 1 if (i == 0 and j == 0) else (2 if (i == 0 or j == 0) else 3)
-            if st == s:
-                if not propagated or j > 0:
-                    rows += R[i]
-                if not propagated or i > 0:
-                    cols += C[j]
-    return rows, cols
+def run_chains(d, cfg, precision, batched, nchains, trace=""):
+    """The configuration's own chain (sweeps per stage, burn-in) for each chain
+    seed, and the test RMSE of its posterior-mean prediction (Sec. 5.2)."""
+    import torch
+    sweeps, burnin = cfg["sweeps"], cfg["burnin"]
+    out = []
+    for q, seed in enumerate(CHAIN_SEEDS[:nchains]):
+        h = _ctx(d, cfg, precision, batched, seed, burnin, sweeps - burnin)
+        tf = open(trace, "w") if (trace and q == 0) else None
+        t0 = time.perf_counter()
+        for s in stages_of(cfg):
+            if tf is None:
+                h.pp_stage(s, sweeps)
+            else:
+                h.pp_stage(s, 0)
+                M = h.stage_work()[1]
+                for t in range(sweeps):
+                    h.gibbs_sweep(1)
+                    st = h.stats()
+                    tf.write(json.dumps({"stage": s, "sweep": t, "train_rmse": float(np.sqrt(st["train_sse"] / M)),
+                                         "tau_block0": h.get_tau(min(b for b in range(h.nblocks())
+                                                                     if h.block_info(b)["stage"] == s)),
+                                         "fallback_rows": st["fallback_rows"],
+                                         "nonpd_rows": st["nonpd_rows"]}) + "\n")
+            torch.cuda.synchronize()
+        p = h.predict(d["test_row"], d["test_col"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = h.stats()
+        out.append(dict(seed=seed, rmse=float(np.sqrt(np.mean((p - d["test_val"]) ** 2))), chain_wall_s=wall,
+                        mm_ridged=st["mm_ridged"], agg_corrections=st["agg_corrections"],
+                        fallback_rows=st["fallback_rows"]))
+        if tf is not None:
+            tf.close()
+        h.close()
+        say("%s chain seed %d: rmse %.6f, %.2f s" % (precision, seed, out[-1]["rmse"], wall))
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(d, cfg, seconds, seed):
-    """The FP64 oracle's sweeps on the host cores for a bounded time."""
+    """The FP64 oracle's sweeps on the host cores, bounded in time.  Every PP
+    stage is sampled: its blocks are swept in order (each block's full sweep:
+    rows, columns, hyperparameter and tau draws) until the stage's share of the
+    time budget is used, at least one block per stage.  The propagated priors
+    of stages 2 and 3 are placeholders (identity precision, zero mean): the
+    oracle's arithmetic per sweep does not depend on their values.  Its whole-job
+    rate is the training entries of all blocks over the sum of the per-stage
+    sweep times this gives (the same definition as the GPU value).  With all
+    host threads, then with one thread on stage 3 alone."""
     from oracle.bpmf import Oracle
+    t0 = time.perf_counter()
     o = Oracle(d["N"], d["D"], d["K"], d["row"], d["col"], d["val"], I=cfg["I"], J=cfg["J"],
                order=cfg["order"], seed=seed)
-    o.begin_stage(1)
-    blocks = o.stage_blocks(1)
-    M = sum(b["M"] for b in blocks)
-    n = sum(b["R"] + b["C"] for b in blocks)
-    o.sweep(1)                                 # warm-up
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        o.sweep(1)
-        k += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or k >= 1000:
-            break
+    K = d["K"]
+    say("oracle built in %.1f s" % (time.perf_counter() - t0))
+
+    eye = {}
+
+    def placeholder(n):
+        # one identity-precision array per size, shared by the blocks that bind it
+        if n not in eye:
+            eye[n] = (np.zeros((n, K)), np.ascontiguousarray(np.broadcast_to(np.eye(K), (n, K, K))))
+        return eye[n]
+
+    def sample(stage, budget, nthreads):
+        o.nthreads = nthreads
+        if stage > 1:
+            for blk in o.blocks:
+                if blk["stage"] < stage and blk["b"] not in o.mm:
+                    (xm, xl), (wm, wl) = placeholder(blk["R"]), placeholder(blk["C"])
+                    o.mm[blk["b"]] = dict(x_mu=xm, x_Lam=xl, w_mu=wm, w_Lam=wl, ridged=0)
+        o.begin_stage(stage)
+        blocks = o.stage_blocks(stage)
+        M = n = nb = 0
+        t1 = time.perf_counter()
+        for blk in blocks:
+            o.sweep_block(blk)
+            M += blk["M"]
+            n += blk["R"] + blk["C"]
+            nb += 1
+            if time.perf_counter() - t1 >= budget:
+                break
+        el = time.perf_counter() - t1
+        return dict(stage=stage, blocks=nb, of=len(blocks), ratings=M, row_updates=n, seconds=el,
+                    ratings_per_s=M / el, row_updates_per_s=n / el,
+                    stage_ratings=sum(b["M"] for b in blocks),
+                    stage_row_updates=sum(b["R"] + b["C"] for b in blocks))
+
     cores = len(os.sched_getaffinity(0))
-    return dict(value=M * k / el, unit="ratings/s", cores=cores, kind="oracle",
-                row_updates_per_s=n * k / el,
-                sample="%d full FP64 oracle sweeps of stage 1 (%d blocks) of the same workload, "
-                       "%.1f s, OpenMP over rows" % (k, len(blocks), el))
+    stages = stages_of(cfg)
+    all_thr = [sample(s, seconds / len(stages), 0) for s in stages]
+    t_step = sum(r["stage_ratings"] / r["ratings_per_s"] for r in all_thr)
+    M_tot = sum(r["stage_ratings"] for r in all_thr)
+    RU_tot = sum(r["stage_row_updates"] for r in all_thr)
+    one = sample(stages[-1], seconds / 2, 1)
+    desc = "; ".join("stage %d: %d of %d blocks, %d entries, %.1f s" % (r["stage"], r["blocks"], r["of"],
+                                                                        r["ratings"], r["seconds"])
+                     for r in all_thr)
+    return dict(value=M_tot / t_step, unit="ratings/s", cores=cores, kind="oracle",
+                row_updates_per_s=RU_tot / t_step, cpu_model=cpu_model(),
+                sample="FP64 oracle (C, OpenMP over rows, %d threads) full block sweeps per PP stage of "
+                       "the same workload (%s), placeholder propagated priors; whole-job rate = all "
+                       "training entries over the summed per-stage sweep times" % (cores, desc),
+                per_stage=all_thr,
+                single_thread=dict(value=one["ratings_per_s"], unit="ratings/s", cores=1,
+                                   row_updates_per_s=one["row_updates_per_s"],
+                                   sample="stage %d only: %d of %d blocks, %d entries, %.1f s"
+                                          % (one["stage"], one["blocks"], one["of"], one["ratings"],
+                                             one["seconds"])))
+
+
+def pass_rooflines(d, cfg, arm, steps, state_bytes, config_id, precision):
+    """Achieved algorithmic bandwidth of every update pass (stage, rows or
+    columns) of the per-kernel region: the pass's bytes over its summed
+    launch time per sweep (the segment Grams of heavy entities, which serve
+    both passes, are charged to each pass, so the rate is a lower bound)."""
+    K = d["K"]
+    out = []
+    for s, m in arm["per_stage"].items():
+        kt = m["ktimes"]
+        seg_ms = kt.get("gram_segments", (0, 0.0))[1]
+        for side, kcls in ((0, "update_rows"), (1, "update_cols")):
+            if kcls not in kt or kt[kcls][0] == 0:
+                continue
+            launches, tot_ms = kt[kcls]
+            n = m["ents"][side]
+            n_empty = m["empty_prop"][side]
+            n_lowrank = m["lowrank_prop"][side]
+            n_prop = m["prop"][side] - n_empty - n_lowrank
+            nbytes = algorithmic_bytes(m["ratings"], n, K, state_bytes, True, n_prop, n_empty, n_lowrank)
+            avg_ms = (tot_ms + seg_ms) / steps
+            ach = nbytes / (avg_ms / 1000.0) / 1e9
+            traffic = measured_traffic(kcls, config_id, s, precision)
+            r = dict(kernel="%s (stage %d pass)" % (kcls, s), stage=s, bound="hbm", achieved=ach,
+                     peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS, traffic=traffic,
+                     avg_launch_ms=avg_ms, launches_per_pass=launches / steps,
+                     algorithmic_bytes_per_launch=nbytes, pass_ms_share=avg_ms / m["ms_per_step"])
+            if traffic:
+                r["traffic_frac"] = traffic / (avg_ms / 1000.0) / 1e9 / HBM_PEAK_GBS
+            out.append(r)
+    return out
 
 
 def main():
@@ -261,54 +374,34 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n, "copies": 5}))
         return
     cfg = dict(synth.CONFIGS[a.config])
-    say = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
     say("drawing workload %d" % a.config)
     d = synth.config(a.config, seed=a.seed, progress=say)
     K = d["K"]
     main_prec = "bf16" if cfg["precision"] in ("fp32", "bf16") else cfg["precision"]
-    arms = {}
-    arms["batched_" + main_prec] = run_arm(d, cfg, main_prec, True, a.steps, a.warmup,
-                                           not a.no_rmse, 101)
-    print("arm batched %s done" % main_prec, file=sys.stderr, flush=True)
-    if main_prec != "fp64" and not a.batched_only:
-        arms["plain_fp32"] = run_arm(d, cfg, "fp32", False, a.steps, a.warmup, not a.no_rmse, 101)
-        print("arm plain fp32 done", file=sys.stderr, flush=True)
-    stages = stages_of(cfg)
-    head = stages[-1]                          # the largest, most parallel stage
-    m = arms["batched_" + main_prec]["per_stage"][head]
-    ms = m["ms_per_step"]
-    value = m["ratings"] / (ms / 1000.0)
-    # dominant kernel of the per-kernel region of the headline stage
-    kt = {k: v for k, v in m["ktimes"].items() if v[0] > 0}
-    dom = max(kt, key=lambda k: kt[k][1])
-    launches, tot_ms = kt[dom]
     state_bytes = {"fp64": 8, "fp32": 4, "bf16": 2}[main_prec]
-    roof = None
-    if dom in ("update_rows", "update_cols"):
-        M = m["ratings"]
-        # entities of the pass: rows (or columns) of every block of the stage
-        side = 0 if dom == "update_rows" else 1
-        n = rows_cols_of_stage(d, cfg, head)[side]
-        n_empty = m["empty_prop"][side]
-        n_lowrank = m["lowrank_prop"][side]
-        n_prop = rows_cols_of_stage(d, cfg, head, propagated=True)[side] - n_empty - n_lowrank
-        # a pass is one launch (K <= 16) or a few: heavy entities, light ones
-        # (K > 16), segment Grams apart; the rate is the pass's bytes over the
-        # pass's summed launch time
-        per_pass = algorithmic_bytes(dom, M, n, K, state_bytes, True, n_prop, n_empty, n_lowrank)
-        passes = a.steps
-        # the partial Grams of heavy entities (both passes) count against this pass
-        seg_ms = kt.get("gram_segments", (0, 0.0))[1]
-        avg_ms = (tot_ms + seg_ms) / passes
-        ach = per_pass / (avg_ms / 1000.0) / 1e9
-        roof = dict(kernel=dom, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS,
-                    traffic=measured_traffic(dom, a.config, main_prec), avg_launch_ms=avg_ms,
-                    launches_per_pass=launches / passes,
-                    algorithmic_bytes_per_launch=per_pass)
+    stages = stages_of(cfg)
+    arms = {"batched_" + main_prec: time_stages(d, cfg, main_prec, True, a.steps, a.warmup)}
+    say("arm batched %s timed" % main_prec)
+    if main_prec != "fp64" and not a.batched_only:
+        arms["plain_fp32"] = time_stages(d, cfg, "fp32", False, a.steps, a.warmup)
+        say("arm plain fp32 timed")
+    head = arms["batched_" + main_prec]
+    ms = sum(head["per_stage"][s]["ms_per_step"] for s in stages)
+    ratings = sum(head["per_stage"][s]["ratings"] for s in stages)
+    row_updates = sum(head["per_stage"][s]["row_updates"] for s in stages)
+    roofs = pass_rooflines(d, cfg, head, a.steps, state_bytes, a.config, main_prec)
+    roof = max(roofs, key=lambda r: r["avg_launch_ms"]) if roofs else None
+    if roof is not None:
+        roof = {k: v for k, v in roof.items() if k != "pass_ms_share"}
+    kernel_ms = {}
+    for s in stages:
+        for k, v in head["per_stage"][s]["ktimes"].items():
+            if v[0] > 0:
+                kernel_ms["stage%d.%s" % (s, k)] = v[1] / a.steps
+    partition = "%dx%d" % (cfg["I"], cfg["J"])
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": ratings / (ms / 1000.0),
         "unit": "ratings/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -319,33 +412,52 @@ def main():
         "vs_baseline": None,
         "dtype": main_prec,
         "data": "synthetic",
-        "config": {"workload": "%s N=%d D=%d K=%d, %d train entries, Zipf(1.2) degrees, %dx%d "
-                               "partition, %s order; step = one sweep of PP stage %d"
+        "config": {"workload": "%s N=%d D=%d K=%d, %d train entries, Zipf(1.2) degrees, %s partition, %s "
+                               "order; step = one sweep of each PP stage (%s)"
                                % ("ratings-shaped" if cfg["kind"] == "ratings" else cfg["kind"],
-                                  d["N"], d["D"], K, d["row"].size, cfg["I"], cfg["J"],
-                                  cfg["order"], head),
+                                  d["N"], d["D"], K, d["row"].size, partition, cfg["order"],
+                                  ", ".join("stage %d" % s for s in stages)),
                    "N": d["N"], "D": d["D"], "K": K, "train_nnz": int(d["row"].size),
-                   "partition": "%dx%d" % (cfg["I"], cfg["J"]), "stage": head},
-        "row_updates_per_s": m["row_updates"] / (ms / 1000.0),
+                   "partition": partition, "stages": stages},
+        "row_updates_per_s": row_updates / (ms / 1000.0),
         "roofline": roof,
-        "kernel_ms_per_step": {k: v[1] / a.steps for k, v in kt.items()},
-        "timing": "ms_per_step: HIP events around the timed sweeps (graph replays in the batched "
-                  "arm); kernel times and roofline: a second region of as many sweeps launched "
-                  "eagerly with HIP events around every kernel",
+        "roofline_passes": roofs,
+        "kernel_ms_per_step": kernel_ms,
+        "timing": "ms_per_step: per stage, HIP events around `steps` timed sweeps (graph replays in the "
+                  "batched arm), summed over the stages; kernel times and roofline: a second region of as "
+                  "many sweeps per stage launched eagerly with HIP events around every kernel",
         "arms": {},
     }
     for k, v in arms.items():
-        arm = {"test_rmse": v.get("rmse"), "chain_wall_s": v.get("chain_wall_s"),
+        t_arm = sum(v["per_stage"][s]["ms_per_step"] for s in stages)
+        arm = {"ms_per_step": t_arm, "ratings_per_s": ratings / (t_arm / 1000.0),
+               "row_updates_per_s": row_updates / (t_arm / 1000.0),
                "fallback_rows": v["stats"]["fallback_rows"], "stages": {}}
         for s_, ps in v["per_stage"].items():
             arm["stages"][str(s_)] = {
-                "ms_per_step": ps["ms_per_step"],
+                "ms_per_step": ps["ms_per_step"], "ratings": ps["ratings"], "row_updates": ps["row_updates"],
                 "ratings_per_s": ps["ratings"] / (ps["ms_per_step"] / 1000.0),
                 "row_updates_per_s": ps["row_updates"] / (ps["ms_per_step"] / 1000.0),
                 "schedule": ps["schedule"]}
         out["arms"][k] = arm
+    if "plain_fp32" in arms:
+        out["speedup_vs_plain_fp32"] = out["arms"]["plain_fp32"]["ms_per_step"] / ms
+    if not a.no_rmse:
+        rm = {}
+        for k in arms:
+            prec = main_prec if k.startswith("batched") else "fp32"
+            rm[k] = run_chains(d, cfg, prec, k.startswith("batched"), a.chains,
+                               a.trace if k.startswith("batched") else "")
+            out["arms"][k]["chains"] = rm[k]
+            out["arms"][k]["test_rmse"] = float(np.mean([c["rmse"] for c in rm[k]]))
+        if "plain_fp32" in rm:
+            r0 = out["arms"]["batched_" + main_prec]["test_rmse"]
+            r1 = out["arms"]["plain_fp32"]["test_rmse"]
+            out["equal_rmse"] = {"relative_difference": abs(r0 - r1) / r1, "bound": 0.005,
+                                 "holds": abs(r0 - r1) / r1 <= 0.005,
+                                 "chains_per_arm": a.chains}
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(d, cfg, a.cpu_seconds, 101)
+        out["cpu_baseline"] = cpu_baseline(d, cfg, a.cpu_seconds, CHAIN_SEEDS[0])
     print(json.dumps(out))
 
 

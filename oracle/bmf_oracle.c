@@ -290,16 +290,24 @@ void orc_cond_precision(int64_t R, int32_t K, const int64_t *ptr, const int32_t 
                         const double *val, const double *other, int32_t per_row,
                         const double *P, const double *m, double tau, double *A)
 {
-    double *G = (double *)malloc(sizeof(double) * (size_t)K * K);
-    double *hs = (double *)malloc(sizeof(double) * (size_t)K);
-    double *h = (double *)malloc(sizeof(double) * (size_t)K);
-    for (int64_t n = 0; n < R; ++n) {
-        const double *Pn = per_row ? P + n * K * K : P;
-        const double *mn = per_row ? m + n * K : m;
-        orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, Pn, mn, tau, G, hs,
-                        A + n * (int64_t)K * K, h);
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        double *G = (double *)malloc(sizeof(double) * (size_t)K * K);
+        double *hs = (double *)malloc(sizeof(double) * (size_t)K);
+        double *h = (double *)malloc(sizeof(double) * (size_t)K);
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+        for (int64_t n = 0; n < R; ++n) {
+            const double *Pn = per_row ? P + n * K * K : P;
+            const double *mn = per_row ? m + n * K : m;
+            orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, Pn, mn, tau, G, hs,
+                            A + n * (int64_t)K * K, h);
+        }
+        free(G); free(hs); free(h);
     }
-    free(G); free(hs); free(h);
 }
 
 int64_t orc_update_side(int64_t R, int32_t K, const int64_t *ptr, const int32_t *idx,

@@ -270,6 +270,11 @@ class BMF:
         t = None if tau is None else ctypes.byref(_d(float(tau)))
         self._check(self.L.bmf_set_state(self.ctx, b, _ptr(Xa), _ptr(Wa), _ptr(hyp), t))
 
+    def get_tau(self, b):
+        tau = _d()
+        self._check(self.L.bmf_get_state(self.ctx, b, None, None, None, ctypes.byref(tau)))
+        return tau.value
+
     def step(self, b, which, t):
         w = STEP[which] if isinstance(which, str) else int(which)
         self._check(self.L.bmf_step(self.ctx, int(b), w, int(t)))

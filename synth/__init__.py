@@ -20,6 +20,8 @@ shapes, sparsity and degree skew):
   y = K^-1/2 x^T w + N(0, noise^2).
 * Split: a uniformly random 90 % of the observed cells are training data.
 """
+import os
+
 import numpy as np
 
 CONFIGS = {
@@ -62,6 +64,20 @@ def _dedupe(keys):
     return np.unique(keys)
 
 
+def _union(keys, new):
+    """Sorted set union of a sorted unique key array and new keys: the new keys
+    are deduplicated on their own, those already present dropped by binary
+    search, and the two sorted runs merged (a stable sort of two runs is a
+    linear merge), instead of re-sorting the whole set."""
+    new = np.unique(new)
+    if keys.size:
+        pos = np.minimum(np.searchsorted(keys, new), keys.size - 1)
+        new = new[keys[pos] != new]
+    out = np.concatenate([keys, new])
+    out.sort(kind="stable")
+    return out
+
+
 def _quiet(msg):
     pass
 
@@ -85,7 +101,7 @@ def ratings_cells(N, D, nnz, s, dmin, rng, progress=_quiet):
         extra = int((nnz - keys.size) * 1.3) + 1024
         r = rng.choice(N, size=extra, p=pr)
         c = rng.choice(D, size=extra, p=pc)
-        keys = _dedupe(np.concatenate([keys, r * D + c]))
+        keys = _union(keys, r * D + c)
         progress("cells: topped up to %d distinct" % keys.size)
     if keys.size > nnz:
         keys = np.sort(keys[rng.permutation(keys.size)[:nnz]])
@@ -106,7 +122,7 @@ def ratings_cells(N, D, nnz, s, dmin, rng, progress=_quiet):
         if need_c.size:
             cc = np.repeat(need_c, dmin)
             add.append(rng.choice(N, size=cc.size, p=pr) * D + cc)
-        keys = _dedupe(np.concatenate([keys] + add))
+        keys = _union(keys, np.concatenate(add))
         progress("cells: minimum degree pass, %d distinct" % keys.size)
     return keys // D, keys % D
 
@@ -158,7 +174,37 @@ def make(kind, N, D, K, nnz, noise, seed, zipf_s=1.2, dmin=5, train_frac=0.9, pr
                 test_val=y[te].astype(np.float32))
 
 
+_CACHE = {}
+
+
 def config(cid, seed=1, progress=_quiet):
-    """Workload of one of the five benchmark configurations."""
+    """Workload of one of the five benchmark configurations.  Draws are kept for
+    the life of the process (the caller gets a fresh dict over the same arrays,
+    which must not be written in place); with BMF_SYNTH_CACHE set to a
+    directory they are also kept there as .npz files between processes."""
+    key = (int(cid), int(seed))
+    if key in _CACHE:
+        return dict(_CACHE[key])
+    path = None
+    cache_dir = os.environ.get("BMF_SYNTH_CACHE")
+    if cache_dir:
+        path = os.path.join(cache_dir, "config%d_seed%d.npz" % key)
+        if os.path.exists(path):
+            with np.load(path, allow_pickle=False) as z:
+                d = {k: (z[k].item() if z[k].ndim == 0 else z[k]) for k in z.files}
+            progress("loaded %s" % path)
+            _CACHE[key] = d
+            return dict(d)
     c = CONFIGS[cid]
-    return make(c["kind"], c["N"], c["D"], c["K"], c["nnz"], c["noise"], seed, progress=progress)
+    d = make(c["kind"], c["N"], c["D"], c["K"], c["nnz"], c["noise"], seed, progress=progress)
+    for k, v in d.items():
+        if isinstance(v, np.ndarray):
+            v.flags.writeable = False
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        tmp = path + ".tmp%d.npz" % os.getpid()
+        np.savez(tmp, **d)
+        os.replace(tmp, path)
+    _CACHE.clear()                       # one large workload at a time
+    _CACHE[key] = d
+    return dict(d)

@@ -5,7 +5,12 @@ import synth
 from oracle.bpmf import Oracle
 from paper_1703_00734_amd import BMF
 
-TOL = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 3e-3}
+# single conditional step from an identical state and identical noise, the
+# draw before any rounding to the state precision: in BF16 mode the inputs are
+# the same BF16 values on both sides and the arithmetic is FP32, so the FP32
+# bound applies (the stored BF16 state adds its own rounding, 2^-9 per entry,
+# checked bit for bit as the rounding of the draw)
+TOL = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-4}
 
 
 def small_data(K, seed=1, N=600, D=300, nnz=20000, empty_rows=7, kind="ratings"):
