@@ -940,7 +940,12 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         const int32_t fp = c->bf() ? kPFB16 : kPFB32;
         if ((st = timed(c, kKFallback, [&] { return launch_update_wave(L.kc, fp, f, kFallbackGrid, c->ls); })))
             return st;
-        if (!use_ss) {
+        // the queue holds this pass's entities only: a single step clears it
+        // here, a batched sweep (one pass over every block) in the sweep-state
+        // advance, and a per-block sweep after each block's pass (else the next
+        // block's redo would take this block's queued entities again, with the
+        // other side's factors already redrawn)
+        if (!use_ss || k >= 0) {
             int32_t *fb = a.fb_count;
             if ((st = timed(c, kKFill, [&] { return launch_fill_i32(fb, 0, 1, c->ls); }))) return st;
         }

@@ -64,3 +64,28 @@ def test_conditional_precisions_stay_positive_definite(precision):
     p = g.predict(d["test_row"], d["test_col"])
     assert np.all(np.isfinite(p))
     g.close()
+
+
+@pytest.mark.parametrize("precision,K", [("fp32", 10), ("bf16", 10), ("fp32", 32)])
+def test_per_block_sweeps_equal_batched_with_fp64_redo(precision, K):
+    """The plain per-block launches and the batched graph give the same chain
+    bit for bit through all three stages, also when many rows take the FP64
+    redo (propagated priors from fewer kept samples than K are ridged and
+    badly conditioned): each block's redo takes only its own pass's rows."""
+    print("case per-block redo", precision, K, flush=True)
+    d = small_data(K, seed=40 + K, N=700, D=330, nnz=24000)
+    runs = []
+    for batched in (True, False):
+        g, _ = pair(d, K, precision, I=2, J=3, order="decreasing", batched=batched, burnin=2,
+                    max_kept=6, lane_nnz=16)
+        for s in (1, 2, 3):
+            g.pp_stage(s, 8)
+        st = g.stats()
+        assert st["fallback_rows"] > 0 and st["nonpd_rows"] == 0
+        runs.append((g.predict(d["test_row"], d["test_col"]), g.get_state(4), st))
+        g.close()
+    (pa, sa, ta), (pb, sb, tb) = runs
+    assert np.array_equal(pa, pb)
+    for key in ("X", "W", "tau"):
+        assert np.array_equal(sa[key], sb[key]), key
+    assert ta["fallback_rows"] == tb["fallback_rows"]
