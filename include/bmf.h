@@ -68,8 +68,9 @@ typedef enum {
  * samples (moment matching, prediction) and bmf_get_draw / bmf_get_sample hold
  * the FP32 draw before rounding.  Against the FP64 conditional draw from the
  * same (BF16) inputs and noise, the FP32 draw is within about 1e-5 relative
- * (FP32 arithmetic) and the stored state within 2^-9 relative per entry on
- * top of that (the rounding). */
+ * (FP32 arithmetic; measured at most 3e-6 per row at the benchmark sizes) and
+ * the stored state is its round-to-nearest-even, within 2^-8 relative per
+ * entry on top of that (the BF16 unit roundoff). */
 typedef enum {
     BMF_PREC_FP64 = 0,    /* FP64 state, gathers, Gram, Cholesky and solves */
     BMF_PREC_FP32 = 1,    /* FP32 state and gathers, FP32 Gram; FP32 Cholesky with

@@ -8,7 +8,7 @@ from paper_1703_00734_amd import BMF
 # single conditional step from an identical state and identical noise, the
 # draw before any rounding to the state precision: in BF16 mode the inputs are
 # the same BF16 values on both sides and the arithmetic is FP32, so the FP32
-# bound applies (the stored BF16 state adds its own rounding, 2^-9 per entry,
+# bound applies (the stored BF16 state adds its own rounding, 2^-8 per entry,
 # checked bit for bit as the rounding of the draw)
 TOL = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 1e-4}
 
