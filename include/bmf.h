@@ -182,6 +182,22 @@ bmf_status bmf_pp_stage(bmf_ctx *c, int32_t stage, int32_t nsweeps);
 bmf_status bmf_predict(bmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
                        float *out);
 
+/* Allocation-free prediction, for callers that cannot allocate device memory
+ * (tight serving loops, code that must not call hipMalloc).  Same arguments,
+ * ids and result as bmf_predict (the same kernel arithmetic, bit for bit), but
+ * it allocates nothing: the pairs' ids and the outputs are staged through one
+ * fixed device array owned by the library (12 MiB per GPU, held until the
+ * process ends), and it launches only the prediction itself.  So:
+ *   - n <= 1048576 pairs per call (BMF_EINVAL above that: split the request);
+ *   - the aggregated means must already be current (bmf_aggregate, or a
+ *     bmf_predict, since the last sweep), else BMF_ESTATE;
+ *   - every context on one GPU shares that array: calls that overlap in time on
+ *     one GPU (from several threads, or on streams not ordered with each other)
+ *     race and must be serialised by the caller.
+ * Synchronises the context's stream before returning. */
+bmf_status bmf_predict_noalloc(bmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col,
+                               float *out);
+
 /* Release the context (and the device memory it allocated itself). */
 bmf_status bmf_free(bmf_ctx *c);
 

@@ -69,6 +69,7 @@ def load():
         "bmf_gibbs_sweep": [_vp, _i32],
         "bmf_pp_stage": [_vp, _i32, _i32],
         "bmf_predict": [_vp, _i64, _vp, _vp, _vp],
+        "bmf_predict_noalloc": [_vp, _i64, _vp, _vp, _vp],
         "bmf_free": [_vp],
         "bmf_block_info": [_vp, _i32, _P(_i64), _P(_i64), _P(_i64), _P(_i32)],
         "bmf_global_mean": [_vp, _P(_d)],
@@ -115,7 +116,7 @@ def exported_symbols():
             "bmf_get_block_csr", "bmf_get_state", "bmf_set_state", "bmf_step", "bmf_get_draw", "bmf_get_mm",
             "bmf_aggregate", "bmf_get_aggregate", "bmf_get_stats", "bmf_enable_timing",
             "bmf_kernel_times", "bmf_get_schedule", "bmf_stage_work", "bmf_get_sample",
-            "bmf_set_progress", "bmf_save_state", "bmf_load_state"]
+            "bmf_set_progress", "bmf_save_state", "bmf_load_state", "bmf_predict_noalloc"]
 
 
 # int32_t (*bmf_progress_fn)(void *user, int32_t stage, int64_t sweep)
@@ -210,6 +211,13 @@ class BMF:
         c = np.ascontiguousarray(col, dtype=np.int32)
         out = np.empty(r.size, dtype=np.float32)
         self._check(self.L.bmf_predict(self.ctx, r.size, _ptr(r), _ptr(c), _ptr(out)))
+        return out
+
+    def predict_noalloc(self, row, col):
+        r = np.ascontiguousarray(row, dtype=np.int32)
+        c = np.ascontiguousarray(col, dtype=np.int32)
+        out = np.empty(r.size, dtype=np.float32)
+        self._check(self.L.bmf_predict_noalloc(self.ctx, r.size, _ptr(r), _ptr(c), _ptr(out)))
         return out
 
     def nblocks(self):

@@ -54,7 +54,7 @@ struct Layout {
         W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
         m_items, m_items2, m_stats, m_hyper, m_mmout, pfac, m_pfout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
-        p_out, total;
+        p_out, rowpos, colpos, total;
     int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
     bool mfma = false;
 };
@@ -161,6 +161,8 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.p_xslot = take(8 * kPredictChunk);
     L.p_wslot = take(8 * kPredictChunk);
     L.p_out = take(4 * kPredictChunk);
+    L.rowpos = take(8 * c.N);
+    L.colpos = take(8 * c.D);
     L.total = off;
     return true;
 }
@@ -239,6 +241,9 @@ struct bmf_ctx {
     bool agg_valid = false;
     StageLists S;
     int32_t done_stages[4] = {0, 0, 0, 0};
+    // device address of the allocation-free entry point's scratch array on the
+    // context's device (looked up once per device at bmf_init)
+    char *scratch = nullptr;
     // progress callback (checked before each sweep is enqueued)
     bmf_progress_fn progress = nullptr;
     void *progress_user = nullptr;
@@ -1539,6 +1544,13 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     if ((st = upload(c, L.colsq, colsq.data(), colsq.size() * 8))) return st;
+    if ((st = upload(c, L.rowpos, P.row_pos.data(), 8 * P.row_pos.size()))) return st;
+    if ((st = upload(c, L.colpos, P.col_pos.data(), 8 * P.col_pos.size()))) return st;
+    {
+        void *sp = nullptr;
+        HIPCHK(c, scratch_address(&sp));
+        c->scratch = static_cast<char *>(sp);
+    }
     if ((st = upload(c, L.mu0, c->mu0.data(), 8 * K))) return st;
     if ((st = upload(c, L.W0inv, c->W0inv.data(), 8 * K * K))) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1676,6 +1688,36 @@ bmf_status bmf_predict(bmf_ctx *c, int64_t n, const int32_t *row, const int32_t 
         HIPCHK(c, hipMemcpyAsync(out + a, c->base + L.p_out, 4 * m, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    return BMF_OK;
+}
+
+bmf_status bmf_predict_noalloc(bmf_ctx *c, int64_t n, const int32_t *row, const int32_t *col, float *out) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (n < 0 || (n > 0 && (!row || !col || !out))) return fail(c, BMF_EINVAL, "bad prediction arrays");
+    if (n > kNoallocMaxPairs)
+        return fail(c, BMF_EINVAL, "bmf_predict_noalloc takes at most 1048576 pairs per call (its staging "
+                                   "array is fixed); split the request");
+    if (!c->agg_valid)
+        return fail(c, BMF_ESTATE, "bmf_predict_noalloc needs the aggregated means: call bmf_aggregate first");
+    const Plan &P = c->plan;
+    for (int64_t q = 0; q < n; ++q)
+        if (row[q] < 0 || row[q] >= P.N || col[q] < 0 || col[q] >= P.D)
+            return fail(c, BMF_EINVAL, "prediction id out of range");
+    if (n == 0) return BMF_OK;
+    // staging: [row ids | column ids | outputs], kNoallocMaxPairs entries each
+    int32_t *srow = reinterpret_cast<int32_t *>(c->scratch);
+    int32_t *scol = srow + kNoallocMaxPairs;
+    float *sout = reinterpret_cast<float *>(scol + kNoallocMaxPairs);
+    const Layout &L = c->L;
+    HIPCHK(c, hipMemcpyAsync(srow, row, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(scol, col, 4 * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    PredictIdsArgs pa{srow, scol, n, c->dev<int64_t>(L.rowpos), c->dev<int64_t>(L.colpos), c->dev<double>(L.agg_x),
+                      c->dev<double>(L.agg_w), c->cfg.K, c->ybar, sout};
+    bmf_status st = timed(c, kKPredict, [&] { return launch_predict_ids(pa, c->ls); });
+    if (st) return st;
+    HIPCHK(c, hipMemcpyAsync(out, sout, 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return BMF_OK;
 }
 

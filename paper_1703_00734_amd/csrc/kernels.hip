@@ -22,6 +22,8 @@
 //     registers, one matrix row per lane, with lane broadcasts.  Also runs the
 //     FP64 redo of rows whose FP32 pivot test failed.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <math.h>
 
 #include "kernels.hpp"
@@ -2714,16 +2716,31 @@ __global__ __launch_bounds__(64) void k_agg(const AggArgs a) {
 // --------------------------------------------------------------------------
 // k_predict: y_hat = y_bar + mu*_x^T mu*_w (FP64), one thread per pair.
 // --------------------------------------------------------------------------
+__device__ __forceinline__ float predict_one(const double *x, const double *w, int K, double ybar) {
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) s += x[k] * w[k];
+    return (float)(ybar + s);
+}
+
 __global__ __launch_bounds__(256) void k_predict(const PredictArgs a) {
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.n;
-         q += (int64_t)gridDim.x * blockDim.x) {
-        const double *x = a.mux + a.xslot[q] * a.K;
-        const double *w = a.muw + a.wslot[q] * a.K;
-        double s = 0.0;
-        for (int k = 0; k < a.K; ++k) s += x[k] * w[k];
-        a.out[q] = (float)(a.ybar + s);
-    }
+         q += (int64_t)gridDim.x * blockDim.x)
+        a.out[q] = predict_one(a.mux + a.xslot[q] * a.K, a.muw + a.wslot[q] * a.K, a.K, a.ybar);
 }
+
+// The same from original ids, mapped to positions on the device.
+__global__ __launch_bounds__(256) void k_predict_ids(const PredictIdsArgs a) {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < a.n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        a.out[q] = predict_one(a.mux + a.row_pos[a.row[q]] * a.K, a.muw + a.col_pos[a.col[q]] * a.K, a.K,
+                               a.ybar);
+}
+
+// Staging of the allocation-free prediction entry point: one array per device,
+// held until the process ends.  Host code never passes this name to a kernel
+// (on the host it is only a stand-in for the symbol): it takes the device
+// address from scratch_address().
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // End of a sweep: next sweep index and its sample slot (kept when
 // t >= burnin, (t - burnin) % thin == 0 and the store is not full).
@@ -3014,6 +3031,31 @@ hipError_t launch_predict(const PredictArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_predict, dim3(grid_for(a.n, 256, 65536)), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_predict_ids(const PredictIdsArgs &a, hipStream_t s) {
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_predict_ids, dim3(grid_for(a.n, 256, 65536)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t scratch_address(void **p) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *q = nullptr;
+        e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = q;
+    }
+    *p = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_advance(SweepState *ss, int32_t *fb_counts, hipStream_t s) {

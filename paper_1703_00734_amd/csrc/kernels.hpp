@@ -191,6 +191,29 @@ struct PredictArgs {
     float *out;
 };
 
+// Predictions for pairs given by original ids: the ids are mapped to slots on
+// the device through the position arrays (original id -> position).
+struct PredictIdsArgs {
+    const int32_t *row;
+    const int32_t *col;
+    int64_t n;
+    const int64_t *row_pos;
+    const int64_t *col_pos;
+    const double *mux;
+    const double *muw;
+    int32_t K;
+    double ybar;
+    float *out;
+};
+
+// File-scope device scratch of the allocation-free entry point
+// (bmf_predict_noalloc): its pairs' ids and outputs are staged there.
+constexpr int64_t kNoallocMaxPairs = (int64_t)1 << 20;
+constexpr int64_t kScratchBytes = kNoallocMaxPairs * (4 + 4 + 4);
+// Device address of the scratch array on the current device: looked up with
+// hipGetSymbolAddress on the first call per device and kept.
+hipError_t scratch_address(void **p);
+
 hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t ntiles,
                              hipStream_t s);
 // Two entities with at most 16 entries per wavefront, 16 < K <= 32, FP32 or
@@ -225,6 +248,7 @@ hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
 hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s);
 hipError_t launch_agg(const AggArgs &a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s);
+hipError_t launch_predict_ids(const PredictIdsArgs &a, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_advance(SweepState *ss, int32_t *fb_counts, hipStream_t s);
 
