@@ -54,6 +54,10 @@ def parse():
     p.add_argument("--trace", default="",
                    help="write a per-sweep JSONL trace (train RMSE, tau, counters) of the first "
                         "headline chain to this path")
+    p.add_argument("--paper-sim", action="store_true",
+                   help="instead of the headline: the paper's simulated workload (Sec. 5.3) with its "
+                        "1200/800/2 schedule at partitions 1x1 .. 30x30, both orders, both missingness "
+                        "scenarios; prints one JSON line of test RMSE and chain times beside Table 4")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                    help="only run 5 device-to-device copies of MIB MiB (to scale the HBM "
                         "traffic counters), then exit")
@@ -355,8 +359,56 @@ def pass_rooflines(d, cfg, arm, steps, state_bytes, config_id, precision):
     return out
 
 
+TABLE4_SIM = {1: (1.008, 1.008), 3: (1.008, 1.008), 5: (1.008, 1.008), 10: (1.009, 1.009), 30: (1.018, 1.020)}
+TABLE4_SIM_SECONDS_1X1 = 118124.0      # the paper's 1x1 run (R, one node), decreasing order
+
+
+def paper_sim():
+    """Test RMSE and wall-clock of full PP chains on the paper's simulated data
+    (K = 5, tau = 1 fixed, 1200 sweeps, 800 burn-in, thin 2), batched BF16."""
+    import torch
+    import synth
+    from paper_1703_00734_amd import BMF
+    out = {"metric": "test RMSE and chain wall-clock, paper's simulated workload", "runs": []}
+    for missing in ("mar", "structured"):
+        d = synth.simulated(1, missing)
+        for IJ in (1, 3, 5, 10, 30):
+            for order in ("decreasing", "random"):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g = BMF(d["N"], d["D"], 5, d["row"], d["col"], d["val"], I=IJ, J=IJ, order=order,
+                        sample_tau=False, tau_fixed=1.0, seed=101, burnin=800, thin=2, max_kept=200,
+                        precision="bf16", batched=True)
+                stage_s = {}
+                for s in (1, 2, 3):
+                    ts = time.perf_counter()
+                    g.pp_stage(s, 1200)
+                    torch.cuda.synchronize()
+                    stage_s[s] = time.perf_counter() - ts
+                ta = time.perf_counter()
+                g.aggregate()
+                torch.cuda.synchronize()
+                agg_s = time.perf_counter() - ta
+                wall = time.perf_counter() - t0
+                p = g.predict(d["test_row"], d["test_col"])
+                g.close()
+                rmse = float(np.sqrt(np.mean((p.astype(np.float64) - d["test_val"]) ** 2)))
+                r = dict(missing=missing, partition="%dx%d" % (IJ, IJ), order=order, rmse=rmse,
+                         chain_wall_s=wall, stage_s=stage_s, aggregate_s=agg_s,
+                         train_entries=int(d["row"].size))
+                if missing == "mar":
+                    r["paper_rmse"] = TABLE4_SIM[IJ][0 if order == "decreasing" else 1]
+                out["runs"].append(r)
+                say("sim %s %dx%d %s: rmse %.5f, %.2f s" % (missing, IJ, IJ, order, rmse, wall))
+    out["paper_1x1_seconds"] = TABLE4_SIM_SECONDS_1X1
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
+    if a.paper_sim:
+        paper_sim()
+        return
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus,
               file=sys.stderr)

@@ -252,14 +252,22 @@ class Oracle:
             self.lam_w.append(np.array(lam))
 
     def predict(self, row, col):
+        """y_hat = y_bar + mu*_x^T mu*_w for every pair (original ids)."""
         p = self.plan
         row = np.asarray(row, dtype=np.int64)
         col = np.asarray(col, dtype=np.int64)
+        # aggregated means of every row and column, indexed by original id
+        mx = np.empty((self.N, self.K))
+        mw = np.empty((self.D, self.K))
+        for i in range(self.I):
+            mx[p.row_ids[i]] = self.mu_x[i]
+        for j in range(self.J):
+            mw[p.col_ids[j]] = self.mu_w[j]
         out = np.empty(row.size, dtype=np.float64)
-        for q in range(row.size):
-            i, n = p.row_block[row[q]], p.row_local[row[q]]
-            j, d = p.col_block[col[q]], p.col_local[col[q]]
-            out[q] = self.ybar + float(np.dot(self.mu_x[i][n], self.mu_w[j][d]))
+        step = 1 << 20
+        for a in range(0, row.size, step):
+            b = min(row.size, a + step)
+            out[a:b] = self.ybar + np.einsum("qk,qk->q", mx[row[a:b]], mw[col[a:b]])
         return out
 
 

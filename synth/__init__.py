@@ -174,6 +174,45 @@ def make(kind, N, D, K, nnz, noise, seed, zipf_s=1.2, dmin=5, train_frac=0.9, pr
                 test_val=y[te].astype(np.float32))
 
 
+def simulated(seed, missing="mar", N=6040, D=3706, K=5, observed=0.2, progress=_quiet):
+    """The simulated data of the paper's experiments (Sec. 5.3): X, W with
+    standard-normal entries, Y = X W^T + E with standard-normal noise (so the
+    true tau is 1), N = 6040 rows, D = 3706 columns, K = 5.  Missingness:
+
+    * "mar": a uniformly random 80 % of the cells is missing (the test set),
+      the remaining 20 % is the training set;
+    * "structured": rows and columns get weights equally spaced from 0.9 down
+      to 0.005, and cell (n, d) is observed (training) with probability
+      w_n w_d, which leaves about 80 % missing (the paper's text says the
+      product is the probability of being assigned to the test set, which
+      would leave about 20 % missing; its own figure of 80 % fixes this
+      reading).
+
+    Every missing cell is a test cell.  Returns the COO train and test sets as
+    ``make`` does."""
+    rng = _rng(seed)
+    X = rng.standard_normal((N, K))
+    W = rng.standard_normal((D, K))
+    Y = X @ W.T + rng.standard_normal((N, D))
+    if missing == "mar":
+        obs = np.zeros(N * D, dtype=bool)
+        obs[rng.permutation(N * D)[:int(round(observed * N * D))]] = True
+        obs = obs.reshape(N, D)
+    elif missing == "structured":
+        wn = np.linspace(0.9, 0.005, N)
+        wd = np.linspace(0.9, 0.005, D)
+        obs = rng.random((N, D)) < np.outer(wn, wd)
+    else:
+        raise ValueError(missing)
+    progress("simulated %s: %d observed of %d cells" % (missing, int(obs.sum()), N * D))
+    tr_r, tr_c = np.nonzero(obs)
+    te_r, te_c = np.nonzero(~obs)
+    return dict(N=int(N), D=int(D), K=int(K),
+                row=tr_r.astype(np.int32), col=tr_c.astype(np.int32), val=Y[tr_r, tr_c].astype(np.float32),
+                test_row=te_r.astype(np.int32), test_col=te_c.astype(np.int32),
+                test_val=Y[te_r, te_c].astype(np.float32))
+
+
 _CACHE = {}
 
 

@@ -732,3 +732,36 @@ def test_one_block_pp_is_plain_bpmf():
     q = a.ybar + np.einsum("ek,ek->e", sx.mean(0)[a.plan.row_local[d["test_row"]]],
                            sw.mean(0)[a.plan.col_local[d["test_col"]]])
     np.testing.assert_allclose(p, q, rtol=1e-12)
+
+
+# ------------------------------------------------- the paper's simulated data
+def _table4(golden_dir):
+    out = {}
+    for l in open(os.path.join(golden_dir, "table4_simulated_rmse.txt")):
+        if l.startswith("#") or not l.strip():
+            continue
+        p, dec, rnd = l.split()
+        out[int(p)] = {"decreasing": float(dec), "random": float(rnd)}
+    return out
+
+
+@pytest.mark.parametrize("IJ", [1, 3])
+def test_simulated_data_rmse_in_table4_band(golden_dir, IJ):
+    """The paper's simulated workload (Sec. 5.3: K = 5, tau = 1 fixed, 80 %
+    missing at random) through the oracle's PP chain: the test RMSE of the
+    posterior-mean prediction lies within 0.01 of the published value (Table 4)
+    for the 1 x 1 and 3 x 3 partitions.  A shortened schedule (300 sweeps, 200
+    burn-in, every second kept) keeps this CPU test short; the posterior of
+    this data concentrates within far fewer sweeps."""
+    want = _table4(golden_dir)[IJ]["random"]
+    d = synth.simulated(1, "mar")
+    o = Oracle(d["N"], d["D"], 5, d["row"], d["col"], d["val"], I=IJ, J=IJ, order="random",
+               sample_tau=False, tau_fixed=1.0, seed=101, burnin=200, thin=2)
+    o.run_pp(300)
+    o.aggregate()
+    p = o.predict(d["test_row"], d["test_col"])
+    rmse = float(np.sqrt(np.mean((p - d["test_val"]) ** 2)))
+    print("partition %dx%d: rmse %.5f (paper %.3f)" % (IJ, IJ, rmse, want))
+    assert abs(rmse - want) <= 0.01
+    # the noise floor: no predictor beats the noise standard deviation by much
+    assert rmse > 0.99
