@@ -135,6 +135,11 @@ class BMF:
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
                  seed=0, burnin=0, thin=1, max_kept=1, precision="fp32", pivot_theta=0.0,
                  batched=True, lane_nnz=0, device=True, stream=None):
+        if device:
+            # torch's HIP runtime is initialised before the library's is loaded
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no GPU visible to torch")
         self.L = load()
         self.K = int(K)
         self.N, self.D = int(N), int(D)
@@ -166,9 +171,6 @@ class BMF:
         self.ctx = _vp()
         self.workspace = None
         if device:
-            import torch
-            if not torch.cuda.is_available():
-                raise RuntimeError("no GPU visible to torch")
             size = ctypes.c_size_t()
             self._check(self.L.bmf_workspace_size(ctypes.byref(c), ctypes.byref(size)), None)
             self.workspace = torch.empty(max(int(size.value), 1), dtype=torch.uint8, device="cuda")

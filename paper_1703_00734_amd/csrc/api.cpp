@@ -54,7 +54,7 @@ struct Layout {
         W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
         m_items, m_items2, m_stats, m_hyper, m_mmout, pfac, m_pfout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
-        p_out, rowpos, colpos, total;
+        p_out, rowpos, colpos, m_gitems, m_gstart, total;
     int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
     bool mfma = false;
 };
@@ -161,6 +161,8 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.p_xslot = take(8 * kPredictChunk);
     L.p_wslot = take(8 * kPredictChunk);
     L.p_out = take(4 * kPredictChunk);
+    L.m_gitems = take(sizeof(int2) * L.n_items_cap);
+    L.m_gstart = take(4 * (L.n_items_cap + 8));
     L.rowpos = take(8 * c.N);
     L.colpos = take(8 * c.D);
     L.total = off;
@@ -182,15 +184,11 @@ struct StageLists {
     // the same per block (block item lists are in decreasing degree order)
     int64_t i_row_light = 0, i_col_light = 0;
     std::vector<int64_t> row_item_light, col_item_light;
-    // first item of the heavy-first order (and per block) that the low-rank
-    // kernel takes (at most lowrank_max_nnz() entries under a per-row prior with
-    // a factor; these sort after every other item, by decreasing degree), and
-    // the first of those that the empty-entity kernel takes (no entries)
-    int64_t i_row_lowrank = 0, i_col_lowrank = 0, i_row_empty = 0, i_col_empty = 0;
-    std::vector<int64_t> row_item_lowrank, col_item_lowrank, row_item_empty, col_item_empty;
-    // first low-rank item with at most lowrank_small_nnz() entries (the small instance's)
-    int64_t i_row_lowsmall = 0, i_col_lowsmall = 0;
-    std::vector<int64_t> row_item_lowsmall, col_item_lowsmall;
+    // first item of the heavy-first order (and per block) under a per-row prior
+    // with a factor and at most lowrank_max_nnz() entries (these sort after every
+    // other item, by decreasing degree; the prior-group kernel takes them)
+    int64_t i_row_lowrank = 0, i_col_lowrank = 0;
+    std::vector<int64_t> row_item_lowrank, col_item_lowrank;
     // per side: prior-factor rows this stage's moment matching writes (or null)
     std::vector<float *> pfout;
     std::vector<int64_t> row_item_begin, col_item_begin;
@@ -199,6 +197,15 @@ struct StageLists {
     // parallel to `items`, each item's (first partial slot, segment count)
     std::vector<SegItem> segs;
     std::vector<int2> splits;
+    // prior groups (k_update_group): the copies with at most lowrank_max_nnz()
+    // entries under a factored per-row prior, grouped by the prior row they
+    // share; gstart[g] is group g's first copy in gitems (one more entry ends
+    // the last group).  Per block (groups of one copy) and batched (one group
+    // per propagated entity across the stage's sibling blocks), per pass.
+    std::vector<int2> gitems;
+    std::vector<int32_t> gstart;
+    std::vector<int64_t> g_row_blk, g_col_blk;      // per stage block: first group (size nbs + 1)
+    int64_t g_row_b0 = 0, g_row_b1 = 0, g_col_b0 = 0, g_col_b1 = 0;
     int64_t s_row = 0, s_col = 0, s_end = 0;
     std::vector<int64_t> row_seg_begin, col_seg_begin;   // per stage block, within the pass
     std::vector<std::vector<int32_t>> ord_row, ord_col;   // degree orders per stage block
@@ -533,19 +540,13 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
             sbeg.push_back((int64_t)slot);
             std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
             std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
-            std::vector<int64_t> &blows = rows ? S.row_item_lowsmall : S.col_item_lowsmall;
-            std::vector<int64_t> &bempty = rows ? S.row_item_empty : S.col_item_empty;
             blight.push_back(-1);
             blowr.push_back(-1);
-            blows.push_back(-1);
-            bempty.push_back(-1);
             const bool fast = S.sides[side].pfac != nullptr;
             for (int32_t e : (rows ? S.ord_row[k] : S.ord_col[k])) {
                 const int64_t deg = ptr[e + 1] - ptr[e];
                 if (blight.back() < 0 && deg <= kLightNnz) blight.back() = (int64_t)igrp.size();
                 if (fast && blowr.back() < 0 && deg <= nlr) blowr.back() = (int64_t)igrp.size();
-                if (fast && blows.back() < 0 && deg <= nls) blows.back() = (int64_t)igrp.size();
-                if (fast && bempty.back() < 0 && deg == 0) bempty.back() = (int64_t)igrp.size();
                 igrp.push_back(make_int2(side, e));
                 ideg.push_back(deg);
                 ifast.push_back(fast && deg <= nlr);
@@ -574,13 +575,9 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         {
             std::vector<int64_t> &blight = rows ? S.row_item_light : S.col_item_light;
             std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
-            std::vector<int64_t> &blows = rows ? S.row_item_lowsmall : S.col_item_lowsmall;
-            std::vector<int64_t> &bempty = rows ? S.row_item_empty : S.col_item_empty;
             for (int32_t k = 0; k < nbs; ++k) {
                 if (blight[k] < 0) blight[k] = ibeg[k + 1];
                 if (blowr[k] < 0) blowr[k] = ibeg[k + 1];
-                if (blows[k] < 0) blows[k] = ibeg[k + 1];
-                if (bempty[k] < 0) bempty[k] = ibeg[k + 1];
             }
         }
         // heavy-first: decreasing degree, the low-rank and empty-entity kernels'
@@ -597,25 +594,63 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         (rows ? S.i_row_heavy : S.i_col_heavy) = (int64_t)S.items.size();
         int64_t &light = rows ? S.i_row_light : S.i_col_light;
         int64_t &lowr = rows ? S.i_row_lowrank : S.i_col_lowrank;
-        int64_t &lows = rows ? S.i_row_lowsmall : S.i_col_lowsmall;
-        int64_t &empty = rows ? S.i_row_empty : S.i_col_empty;
         light = -1;
         lowr = -1;
-        lows = -1;
-        empty = -1;
         for (int64_t q : iperm) {
             if (light < 0 && ideg[q] <= kLightNnz) light = (int64_t)S.items.size();
             if (lowr < 0 && ifast[q]) lowr = (int64_t)S.items.size();
-            if (lows < 0 && ifast[q] && ideg[q] <= nls) lows = (int64_t)S.items.size();
-            if (empty < 0 && ifast[q] && ideg[q] == 0) empty = (int64_t)S.items.size();
             S.items.push_back(igrp[q]);
             S.splits.push_back(sgrp[q]);
         }
         if (light < 0) light = (int64_t)S.items.size();
         if (lowr < 0) lowr = (int64_t)S.items.size();
-        if (lows < 0) lows = (int64_t)S.items.size();
-        if (empty < 0) empty = (int64_t)S.items.size();
+        // prior groups of this pass: per block, one copy each (the tail of
+        // the block's decreasing-degree list); batched, the copies of one
+        // propagated entity n of source part p (row part i for X rows, column
+        // part j for W columns) across the sibling blocks, ordered by entry
+        // count kind (none, one or two, more) and then by block
+        {
+            std::vector<int64_t> &gblk = rows ? S.g_row_blk : S.g_col_blk;
+            const std::vector<int64_t> &blowr = rows ? S.row_item_lowrank : S.col_item_lowrank;
+            struct FastCopy {
+                int32_t part, n, kind, k;
+                int2 item;
+            };
+            std::vector<FastCopy> fc;
+            for (int32_t k = 0; k < nbs; ++k) {
+                const PlanBlock &B = P.blocks[S.blocks[k]];
+                gblk.push_back((int64_t)S.gstart.size());
+                for (int64_t q = blowr[k]; q < ibeg[k + 1]; ++q) {
+                    S.gstart.push_back((int32_t)S.gitems.size());
+                    S.gitems.push_back(igrp[q]);
+                    const int64_t d = ideg[q];
+                    fc.push_back(FastCopy{rows ? B.i : B.j, igrp[q].y, d == 0 ? 0 : (d <= nls ? 1 : 2), k, igrp[q]});
+                }
+            }
+            gblk.push_back((int64_t)S.gstart.size());
+            std::stable_sort(fc.begin(), fc.end(), [](const FastCopy &x, const FastCopy &y) {
+                if (x.part != y.part) return x.part < y.part;
+                if (x.n != y.n) return x.n < y.n;
+                if (x.kind != y.kind) return x.kind < y.kind;
+                return x.k < y.k;
+            });
+            (rows ? S.g_row_b0 : S.g_col_b0) = (int64_t)S.gstart.size();
+            // a group holds at most one wavefront's lanes of copies (the kernel
+            // counts their kinds with one ballot); a longer run is split, each
+            // piece still sorted by kind
+            int32_t in_group = 0;
+            for (size_t q = 0; q < fc.size(); ++q) {
+                if (q == 0 || fc[q].part != fc[q - 1].part || fc[q].n != fc[q - 1].n || in_group == 64) {
+                    S.gstart.push_back((int32_t)S.gitems.size());
+                    in_group = 0;
+                }
+                S.gitems.push_back(fc[q].item);
+                ++in_group;
+            }
+            (rows ? S.g_row_b1 : S.g_col_b1) = (int64_t)S.gstart.size();
+        }
     }
+    S.gstart.push_back((int32_t)S.gitems.size());
     S.s_end = (int64_t)S.segs.size();
     S.i_end = (int64_t)S.items.size();
     // every entity, for init and moment matching
@@ -739,6 +774,10 @@ static bmf_status upload_stage(bmf_ctx *c) {
     if ((st = upload(c, L.m_splits, S.splits.data(), S.splits.size() * sizeof(int2)))) return st;
     if ((st = upload(c, L.m_segs, S.segs.data(), S.segs.size() * sizeof(SegItem)))) return st;
     if ((st = upload(c, L.m_items2, S.ents.data(), S.ents.size() * sizeof(int2)))) return st;
+    if ((int64_t)S.gitems.size() > L.n_items_cap || (int64_t)S.gstart.size() > L.n_items_cap + 8)
+        return fail(c, BMF_ENOMEM, "prior group lists exceed their reserved space");
+    if ((st = upload(c, L.m_gitems, S.gitems.data(), S.gitems.size() * sizeof(int2)))) return st;
+    if ((st = upload(c, L.m_gstart, S.gstart.data(), S.gstart.size() * 4))) return st;
     if ((st = upload(c, L.m_stats, S.stats.data(), S.stats.size() * sizeof(StatsJob)))) return st;
     if ((st = upload(c, L.m_hyper, S.hyper.data(), S.hyper.size() * sizeof(HyperJob)))) return st;
     std::vector<double *> outs(S.sides.size());
@@ -867,59 +906,57 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         // the empty-entity kernel.
         const bool duo = L.kc == 32 && (c->prec() == kP32 || c->prec() == kPBF);
         const bool lsplit = L.mfma || duo;
-        enum { kWave = 0, kLight = 1, kLowRank = 2, kLowSmall = 3, kEmpty = 4 };
+        enum { kWave = 0, kLight = 1, kGroup = 2 };
         std::vector<std::pair<int64_t, int64_t>> split;
         std::vector<int> kind;
         for (size_t ri = 0; ri < ranges.size(); ++ri) {
-            int64_t light, lowr, lows, empty;
+            int64_t light, lowr;
             if (batched) {
                 light = rows ? S.i_row_light : S.i_col_light;
                 lowr = rows ? S.i_row_lowrank : S.i_col_lowrank;
-                lows = rows ? S.i_row_lowsmall : S.i_col_lowsmall;
-                empty = rows ? S.i_row_empty : S.i_col_empty;
             } else {
                 const int32_t q = k < 0 ? (int32_t)ri : k;
                 const int64_t base = rows ? S.i_row_blk : S.i_col_blk;
                 light = base + (rows ? S.row_item_light : S.col_item_light)[q];
                 lowr = base + (rows ? S.row_item_lowrank : S.col_item_lowrank)[q];
-                lows = base + (rows ? S.row_item_lowsmall : S.col_item_lowsmall)[q];
-                empty = base + (rows ? S.row_item_empty : S.col_item_empty)[q];
             }
             const int64_t lo = ranges[ri].first, hi = ranges[ri].second;
             lowr = std::min(std::max(lowr, lo), hi);
-            empty = std::min(std::max(empty, lowr), hi);
-            lows = std::min(std::max(lows, lowr), empty);
             light = lsplit ? std::min(std::max(light, lo), lowr) : lowr;
             split.push_back({lo, light});
             kind.push_back(kWave);
             split.push_back({light, lowr});
             kind.push_back(kLight);
-            split.push_back({lowr, lows});
-            kind.push_back(kLowRank);
-            split.push_back({lows, empty});
-            kind.push_back(kLowSmall);
-            split.push_back({empty, hi});
-            kind.push_back(kEmpty);
+            // the copies under a factored per-row prior with few entries: one
+            // launch over their prior groups (range of groups, not of items)
+            int64_t g0, g1;
+            if (batched) {
+                g0 = rows ? S.g_row_b0 : S.g_col_b0;
+                g1 = rows ? S.g_row_b1 : S.g_col_b1;
+            } else {
+                const int32_t q = k < 0 ? (int32_t)ri : k;
+                const std::vector<int64_t> &gb = rows ? S.g_row_blk : S.g_col_blk;
+                g0 = gb[q];
+                g1 = gb[q + 1];
+            }
+            split.push_back({g0, g1});
+            kind.push_back(kGroup);
         }
         for (size_t ri = 0; ri < split.size(); ++ri) {
             const auto &r = split[ri];
             if (r.second <= r.first) continue;
             UpdArgs b = a;
-            b.items = c->dev<int2>(L.m_items) + r.first;
-            b.nitems = (int32_t)(r.second - r.first);
-            if (kind[ri] == kEmpty || kind[ri] == kLowRank || kind[ri] == kLowSmall) {
-                const int32_t per = 64 / L.kc;
-                const int32_t g = (int32_t)std::min<int64_t>((b.nitems + per - 1) / per, kWaveGridCap);
-                if (kind[ri] == kEmpty) {
-                    if ((st = timed(c, kcls, [&] { return launch_update_empty(L.kc, c->prec(), b, g, c->ls); })))
-                        return st;
-                } else {
-                    const bool small = kind[ri] == kLowSmall;
-                    if ((st = timed(c, kcls, [&] { return launch_update_lowrank(L.kc, c->prec(), b, g, c->ls, small); })))
-                        return st;
-                }
+            if (kind[ri] == kGroup) {
+                b.items = c->dev<int2>(L.m_gitems);
+                b.gstart = c->dev<int32_t>(L.m_gstart) + r.first;
+                b.ngroups = (int32_t)(r.second - r.first);
+                const int32_t g = (int32_t)std::min<int64_t>(b.ngroups, kWaveGridCap);
+                if ((st = timed(c, kcls, [&] { return launch_update_group(L.kc, c->prec(), b, g, c->ls); })))
+                    return st;
                 continue;
             }
+            b.items = c->dev<int2>(L.m_items) + r.first;
+            b.nitems = (int32_t)(r.second - r.first);
             if (L.mfma) {
                 b.splits = c->dev<int2>(L.m_splits) + r.first;
                 b.gpart = c->dev<float>(L.gpart);

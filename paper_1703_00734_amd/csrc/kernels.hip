@@ -1559,84 +1559,9 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// k_update_empty: entities with no entries in their block under a propagated
-// per-row prior.  With no likelihood term the conditional precision is the
-// prior's own, A = Lambda, and A^-1 h = mu, so the conditional draw reduces to
-// x = mu + L^-T z with L the Cholesky factor of Lambda: the factor is the
-// prior's, computed once per stage (k_pfac), and U = L^-T is applied as a
-// triangular product.  sd.pfac row j (j = 0 .. K-1) holds U[r][r + j] for
-// r < K - j, so lane r of an entity reads one float per row, coalesced over
-// the entity's lanes.  64 / KP entities per wavefront.  An entity whose prior
-// precision was not positive definite (flag at K(K+1)/2 is 0) goes to the
-// FP64 redo queue, as a failed factorisation would.
-// --------------------------------------------------------------------------
-template <int P, int KP>
-__global__ __launch_bounds__(64) void k_update_empty(const UpdArgs a) {
-    using Ts = typename PrecT<P>::s;
-    using Tp = typename PrecT<P>::p;
-    constexpr int G = 64 / KP;
-    __shared__ float sz[64];
-    const int K = a.K;
-    const int kk2 = K * (K + 1) / 2;
-    const int nitems = a.nitems;
-    uint32_t t_sw = a.t;
-    void *sample = a.sample;
-    if (a.ss) {
-        t_sw = a.ss->t;
-        sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
-    }
-    Ts *self = reinterpret_cast<Ts *>(a.self);
-    for (int pit = blockIdx.x; G * pit < nitems; pit += gridDim.x) {
-        const int lane = threadIdx.x;
-        const int h = lane / KP, r = lane % KP;
-        const int it = G * pit + h;
-        const bool valid = it < nitems;              // uniform per entity
-        const int2 item = a.items[valid ? it : G * pit];
-        const SideDesc &sd = a.sides[item.x];
-        const int n = item.y;
-        const float *pf = sd.pfac + (int64_t)n * a.pfrow;
-        const bool ok = pf[kk2] > 0.0f;
-        __syncthreads();                             // the previous entities' noise is read
-        if (4 * r < K) {
-            float z[4];
-            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (4 * r + c < K) sz[h * KP + 4 * r + c] = z[c];
-        }
-        __syncthreads();
-        float acc = 0.0f;
-        int off = 0;                                 // start of stored row j
-#pragma unroll 8
-        for (int j = 0; j < K; ++j) {
-            if (r + j < K) acc += pf[off + r] * sz[h * KP + r + j];
-            off += K - j;
-        }
-        const double *mu = sd.prior + (int64_t)n * a.prow + kk2 + K;
-        const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
-        const bool wr = valid && ok;
-        if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
-        if (wr && sample && r < a.ks_sample)
-            reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
-        // an empty column's residual SSE is its (zero) sum of squared values
-        if (wr && a.sse_col && r < 4)
-            a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? a.colsq[sd.self_off + n] : 0.0;
-        if (valid && !ok && r == 0) {
-            if (a.fb_list) {
-                const int slot = atomicAdd(a.fb_count, 1);
-                a.fb_list[slot] = make_int2(item.x, n);
-                atomicAdd(a.fb_total, 1);
-            } else {
-                atomicAdd(a.nonpd, 1);
-            }
-        }
-    }
-}
-
-// --------------------------------------------------------------------------
-// k_update_lowrank: entities with 1 .. kLowRankNnz entries under a propagated
-// per-row prior whose factor U = L_P^-T (Lambda = L_P L_P^T) was computed at
-// stage begin.  With v_e = L_P^-1 w_e,
+// The low-rank update of an entity with 1 .. kLowRankNnz entries under a
+// propagated per-row prior whose factor U = L_P^-T (Lambda = L_P L_P^T) was
+// computed at stage begin.  With v_e = L_P^-1 w_e,
 //     A = Lambda + tau sum_e w_e w_e^T = L_P (I + tau sum_e v_e v_e^T) L_P^T,
 // and the Cholesky factor of A is L_P M_1 ... M_nc with M_e the factor of the
 // rank-one modification I + tau u_e u_e^T, u_e = (M_1 ... M_(e-1))^-1 v_e (the
@@ -1651,8 +1576,13 @@ __global__ __launch_bounds__(64) void k_update_empty(const UpdArgs a) {
 // and the same noise as the factorising kernels, at O(nc K) segment scans and
 // nc + 2 triangular products instead of a K^3 / 3 factorisation.  64 / KP
 // entities per wavefront; a half with fewer entries than the other applies
-// identity factors (u = 0), so that every lane runs the same scans.  The
-// column pass computes the residual SSE directly from the few entries.
+// identity factors (u = 0, which leave every value unchanged), so that every
+// lane runs the same scans.  The column pass computes the residual SSE
+// directly from the few entries.  An entity with no entries needs no update:
+// its conditional precision is the prior's, A = Lambda, and A^-1 h = mu, so
+// its draw is x = mu + U z.  An entity whose prior precision was not positive
+// definite (flag at K(K+1)/2 of the factor row is 0) goes to the FP64 redo
+// queue, as a failed factorisation would.
 // --------------------------------------------------------------------------
 constexpr int kLowRankNnz = 8;
 constexpr int kLowRankSmall = 2;                 // a second instance for 1 .. 2 entries
@@ -1697,166 +1627,244 @@ __device__ __forceinline__ float seg_suffix(float x, int lane) {
 __device__ __forceinline__ float from_prev(float x) { return dpp0<0x138>(x); }
 __device__ __forceinline__ float from_next(float x) { return dpp0<0x130>(x); }
 
+// --------------------------------------------------------------------------
+// k_update_group: the copies of one propagated row (or column) n in the
+// sibling blocks of a stage -- the blocks whose prior for n is the same
+// moment-matched row of the same source block (X rows of blocks (i, j), j > 0,
+// from (i, 0); W columns of (i, j), i > 0, from (0, j)) -- that have at most
+// kLowRankNnz entries in their block.  They share the prior's stored factor
+// U = L^-T and its mean, so one wavefront stages U in LDS once and draws
+// every copy from it, 64 / KP copies at a time: copies without entries as
+// x = mu + U z, the others by the product-form rank-one update above.  The
+// host orders a group's copies by entry count (none, one or two, three to
+// eight), so the copies run side by side take the same number of scans, and
+// the two short kinds run a two-vector form.  A copy's arithmetic does not
+// depend on which
+// copy runs beside it (a shorter partner applies identity factors), so
+// per-block launches, whose groups hold one copy, give the same draws.
+// --------------------------------------------------------------------------
 template <int P, int KP, int NC>
-__global__ __launch_bounds__(64) void k_update_lowrank(const UpdArgs a) {
+__device__ __forceinline__ void group_lowrank_copy(
+    const UpdArgs &a, const int2 item, const bool valid, const int n, const float *su, const double *pr,
+    float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz], float (&sb)[KP], float (&sz)[KP],
+    const uint32_t t_sw, void *sample, const bool ok, const int lane) {
     using Tw = typename PrecT<P>::w;
     using Tv = typename PrecT<P>::v;
     using Ts = typename PrecT<P>::s;
     using Tp = typename PrecT<P>::p;
-    constexpr int G = 64 / KP;
-    __shared__ float sw[G][NC][KP];                  // the entries' rows of the other side
-    __shared__ float sy[G][NC];                      // their values
-    __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
-    __shared__ float sz[G][KP];                      // noise
-    __shared__ float su[G][KP * (KP + 1) / 2];       // the stored factor U
+    const int r = lane % KP;
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
-    const int nitems = a.nitems;
+    const SideDesc &sd = a.sides[item.x];
+    const int64_t p0 = a.ptr[sd.ptr_off + n];
+    const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
+    const int nc = valid && deg <= NC ? deg : 0;
+    const float tau = (float)(*sd.tau);
+    const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * a.ks_other;
+    const Tv *val = reinterpret_cast<const Tv *>(a.val);
+    __syncthreads();                                 // the previous copies' LDS is read
+#pragma unroll
+    for (int e = 0; e < NC; ++e)
+        sw[e][r] = (e < nc && r < K) ? to_acc<float>(other[(int64_t)a.idx[p0 + e] * a.ks_other + r]) : 0.0f;
+    if (r < NC) sy[r] = r < nc ? (float)val[p0 + r] : 0.0f;
+    if (4 * r < K) {
+        float z[4];
+        normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (4 * r + c < K) sz[4 * r + c] = z[c];
+    }
+    __syncthreads();
+    // h = Lambda mu + tau sum_e y_e w_e
+    float hs = 0.0f;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) hs += sy[e] * sw[e][r];
+    sb[r] = r < K ? (float)pr[kk2 + r] + tau * hs : 0.0f;
+    __syncthreads();
+    // y = U^T h and v_e = U^T w_e: lane c sums U[c - j][c] b[c - j] over j <= c
+    float y = 0.0f, v[NC];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) v[e] = 0.0f;
+    {
+        int off = 0;
+#pragma unroll 4
+        for (int j = 0; j < K; ++j) {
+            if (j <= r && r < K) {
+                const int q = r - j;
+                const float u = su[off + q];
+                y += u * sb[q];
+#pragma unroll
+                for (int e = 0; e < NC; ++e) v[e] += u * sw[e][q];
+            }
+            off += K - j;
+        }
+    }
+    int ncw = nc;
+    if (64 / KP == 2) ncw = max(nc, __shfl_xor(nc, 32));
+    float fu[NC], ft[NC], fitm[NC], fid[NC];
+#pragma unroll
+    for (int e = 0; e < NC; ++e) {
+        fu[e] = 0.0f;
+        ft[e] = fitm[e] = fid[e] = 1.0f;
+        if (e >= ncw) continue;
+        const float u = v[e];
+        const float t = 1.0f + tau * seg_prefix<KP>(u * u);
+        const float tp = from_prev(t);
+        const float itm = r == 0 ? 1.0f : __builtin_amdgcn_rcpf(tp);
+        const float id = __builtin_amdgcn_rsqf(t * itm);
+        fu[e] = u;
+        ft[e] = t;
+        fitm[e] = itm;
+        fid[e] = id;
+        {
+            const float pp = from_prev(seg_prefix<KP>(u * y));
+            const float pe = r == 0 ? 0.0f : pp;
+            y = (y - tau * u * pe * itm) * id;
+        }
+#pragma unroll
+        for (int f = e + 1; f < NC; ++f) {
+            if (f >= ncw) continue;
+            const float pp = from_prev(seg_prefix<KP>(u * v[f]));
+            const float pe = r == 0 ? 0.0f : pp;
+            v[f] = (v[f] - tau * u * pe * itm) * id;
+        }
+    }
+    y += r < K ? sz[r] : 0.0f;
+#pragma unroll
+    for (int e = NC - 1; e >= 0; --e) {
+        if (e >= ncw) continue;
+        const float u = fu[e], t = ft[e], itm = fitm[e], id = fid[e];
+        const float sn = from_next(seg_suffix<KP>(u * y * id * itm, lane));
+        const float se = r == KP - 1 ? 0.0f : sn;
+        y = (y - tau * u * id * itm * t * se) * id;
+    }
+    __syncthreads();                                 // h is read
+    sb[r] = r < K ? y : 0.0f;
+    __syncthreads();
+    // x = U y: U[r][r + j] is entry r of stored row j
+    float acc = 0.0f;
+    {
+        int off = 0;
+#pragma unroll 8
+        for (int j = 0; j < K; ++j) {
+            if (r + j < K) acc += su[off + r] * sb[r + j];
+            off += K - j;
+        }
+    }
+    const float xv = r < K ? acc : 0.0f;
+    const bool wr = valid && ok;
+    Ts *self = reinterpret_cast<Ts *>(a.self);
+    if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
+    if (wr && sample && r < a.ks_sample)
+        reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
+    if (a.sse_col) {
+        // residual SSE over the entries, FP64, from the state-rounded draw
+        __syncthreads();
+        sb[r] = r < K ? (float)elem_to_d(elem_from<Ts>((double)xv)) : 0.0f;
+        __syncthreads();
+        double res = 0.0;
+        if (r < nc) {
+            double dot = 0.0;
+            for (int k = 0; k < K; ++k) dot += (double)sb[k] * (double)sw[r][k];
+            res = (double)sy[r] - dot;
+            res *= res;
+        }
+#pragma unroll
+        for (int o = 1; o < NC; o <<= 1) res += __shfl_down(res, o, KP);
+        if (wr && r < 4) a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? res : 0.0;
+    }
+}
+
+template <int P, int KP>
+__global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
+    using Ts = typename PrecT<P>::s;
+    using Tp = typename PrecT<P>::p;
+    constexpr int G = 64 / KP;
+    __shared__ float su[KP * (KP + 1) / 2];          // the group's stored factor U
+    __shared__ float sw[G][kLowRankNnz][KP];         // a copy's entries' rows of the other side
+    __shared__ float sy[G][kLowRankNnz];             // their values
+    __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
+    __shared__ float sz[G][KP];                      // noise
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
     uint32_t t_sw = a.t;
     void *sample = a.sample;
     if (a.ss) {
         t_sw = a.ss->t;
         sample = a.ss->slot >= 0 ? reinterpret_cast<char *>(a.sample) + a.ss->slot * a.ss->slot_bytes : nullptr;
     }
-    const Tw *otherb = reinterpret_cast<const Tw *>(a.other);
-    const Tv *val = reinterpret_cast<const Tv *>(a.val);
     Ts *self = reinterpret_cast<Ts *>(a.self);
-    for (int pit = blockIdx.x; G * pit < nitems; pit += gridDim.x) {
-        const int lane = threadIdx.x;
-        const int h = lane / KP, r = lane % KP;
-        const int it = G * pit + h;
-        const bool valid = it < nitems;              // uniform per entity
-        const int2 item = a.items[valid ? it : G * pit];
-        const SideDesc &sd = a.sides[item.x];
-        const int n = item.y;
-        const int64_t p0 = a.ptr[sd.ptr_off + n];
-        const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
-        const int nc = deg <= NC ? deg : 0;          // more: the FP64 redo takes it
-        const float *pf = sd.pfac + (int64_t)n * a.pfrow;
-        const bool ok = deg <= NC && pf[kk2] > 0.0f;
-        const double *pr = sd.prior + (int64_t)n * a.prow;
-        const float tau = (float)(*sd.tau);
-        const Tw *other = otherb + sd.other_off * a.ks_other;
-        __syncthreads();                             // the previous entities' LDS is read
-#pragma unroll
-        for (int e = 0; e < NC; ++e)
-            sw[h][e][r] = (e < nc && r < K) ? to_acc<float>(other[(int64_t)a.idx[p0 + e] * a.ks_other + r]) : 0.0f;
-        if (r < NC) sy[h][r] = r < nc ? (float)val[p0 + r] : 0.0f;
-#pragma unroll 6
-        for (int q = r; q < kk2; q += KP) su[h][q] = pf[q];
-        if (4 * r < K) {
-            float z[4];
-            normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                if (4 * r + c < K) sz[h][4 * r + c] = z[c];
+    const int lane = threadIdx.x;
+    const int h = lane / KP, r = lane % KP;
+    for (int g = blockIdx.x; g < a.ngroups; g += gridDim.x) {
+        const int i0 = a.gstart[g];
+        const int cnt = a.gstart[g + 1] - i0;        // copies in the group (at most 64)
+        const int2 first = a.items[i0];
+        const SideDesc &sd0 = a.sides[first.x];
+        const int n = first.y;
+        const float *pf = sd0.pfac + (int64_t)n * a.pfrow;
+        const double *pr = sd0.prior + (int64_t)n * a.prow;
+        const bool ok = pf[kk2] > 0.0f;
+        // the copies' entry counts: none, one or two, three to eight (in that order)
+        int dl = 0;
+        if (lane < cnt) {
+            const int2 it = a.items[i0 + lane];
+            const int64_t po = a.sides[it.x].ptr_off + n;
+            dl = (int)(a.ptr[po + 1] - a.ptr[po]);
         }
+        const int n0 = __popcll(__ballot(lane < cnt && dl == 0));
+        const int n2 = __popcll(__ballot(lane < cnt && dl >= 1 && dl <= kLowRankSmall));
+        __syncthreads();                             // the previous group's factor is read
+        for (int q = lane; q < kk2; q += 64) su[q] = pf[q];
         __syncthreads();
-        // h = Lambda mu + tau sum_e y_e w_e
-        float hs = 0.0f;
+        // copies without entries: x = mu + U z
+        for (int c = 0; c < n0; c += G) {
+            const bool valid = c + h < n0;
+            const int2 item = a.items[i0 + (valid ? c + h : c)];
+            const SideDesc &sd = a.sides[item.x];
+            __syncthreads();
+            if (4 * r < K) {
+                float z[4];
+                normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
 #pragma unroll
-        for (int e = 0; e < NC; ++e) hs += sy[h][e] * sw[h][e][r];
-        sb[h][r] = r < K ? (float)pr[kk2 + r] + tau * hs : 0.0f;
-        __syncthreads();
-        // y = U^T h and v_e = U^T w_e: lane c sums U[c - j][c] b[c - j] over j <= c,
-        // U[c - j][c] being entry c - j of stored row j (coalesced over c)
-        float y = 0.0f, v[NC];
-#pragma unroll
-        for (int e = 0; e < NC; ++e) v[e] = 0.0f;
-        {
-            int off = 0;                             // start of stored row j
-#pragma unroll 4
-            for (int j = 0; j < K; ++j) {
-                if (j <= r && r < K) {
-                    const int q = r - j;
-                    const float u = su[h][off + q];
-                    y += u * sb[h][q];
-#pragma unroll
-                    for (int e = 0; e < NC; ++e) v[e] += u * sw[h][e][q];
-                }
-                off += K - j;
+                for (int e = 0; e < 4; ++e)
+                    if (4 * r + e < K) sz[h][4 * r + e] = z[e];
             }
-        }
-        // the rank-one factors, each applied forward to y and to the later v;
-        // ncw (the most entries of the wavefront's entities) keeps the scans uniform
-        int ncw = nc;
-        if (G == 2) ncw = max(nc, __shfl_xor(nc, 32));
-        float fu[NC], ft[NC], fitm[NC], fid[NC];
-#pragma unroll
-        for (int e = 0; e < NC; ++e) {
-            fu[e] = 0.0f;
-            ft[e] = fitm[e] = fid[e] = 1.0f;
-            if (e >= ncw) continue;
-            const float u = v[e];
-            const float t = 1.0f + tau * seg_prefix<KP>(u * u);
-            const float tp = from_prev(t);
-            const float itm = r == 0 ? 1.0f : __builtin_amdgcn_rcpf(tp);      // 1 / t_(j-1)
-            const float id = __builtin_amdgcn_rsqf(t * itm);                   // 1 / d_j
-            fu[e] = u;
-            ft[e] = t;
-            fitm[e] = itm;
-            fid[e] = id;
-            {
-                const float pp = from_prev(seg_prefix<KP>(u * y));
-                const float pe = r == 0 ? 0.0f : pp;
-                y = (y - tau * u * pe * itm) * id;
-            }
-#pragma unroll
-            for (int f = e + 1; f < NC; ++f) {
-                if (f >= ncw) continue;
-                const float pp = from_prev(seg_prefix<KP>(u * v[f]));
-                const float pe = r == 0 ? 0.0f : pp;
-                v[f] = (v[f] - tau * u * pe * itm) * id;
-            }
-        }
-        y += r < K ? sz[h][r] : 0.0f;
-#pragma unroll
-        for (int e = NC - 1; e >= 0; --e) {
-            if (e >= ncw) continue;
-            const float u = fu[e], t = ft[e], itm = fitm[e], id = fid[e];
-            const float sn = from_next(seg_suffix<KP>(u * y * id * itm, lane));
-            const float se = r == KP - 1 ? 0.0f : sn;
-            // tau beta_j t_j S_j with beta_j = u_j / sqrt(t_j t_(j-1)) = u_j id itm
-            y = (y - tau * u * id * itm * t * se) * id;
-        }
-        __syncthreads();                             // h is read
-        sb[h][r] = r < K ? y : 0.0f;
-        __syncthreads();
-        // x = U y (h carried the prior mean): U[r][r + j] is entry r of stored row j
-        float acc = 0.0f;
-        {
+            __syncthreads();
+            float acc = 0.0f;
             int off = 0;
 #pragma unroll 8
             for (int j = 0; j < K; ++j) {
-                if (r + j < K) acc += su[h][off + r] * sb[h][r + j];
+                if (r + j < K) acc += su[off + r] * sz[h][r + j];
                 off += K - j;
             }
+            const double *mu = pr + kk2 + K;
+            const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
+            const bool wr = valid && ok;
+            if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
+            if (wr && sample && r < a.ks_sample)
+                reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
+            if (wr && a.sse_col && r < 4)
+                a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? a.colsq[sd.self_off + n] : 0.0;
         }
-        const float xv = r < K ? acc : 0.0f;
-        const bool wr = valid && ok;
-        if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
-        if (wr && sample && r < a.ks_sample)
-            reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
-        if (a.sse_col) {
-            // residual SSE over the entries, FP64, from the state-rounded draw
-            __syncthreads();
-            sb[h][r] = r < K ? (float)elem_to_d(elem_from<Ts>((double)xv)) : 0.0f;
-            __syncthreads();
-            double res = 0.0;
-            if (r < nc) {
-                double dot = 0.0;
-                for (int k = 0; k < K; ++k) dot += (double)sb[h][k] * (double)sw[h][r][k];
-                res = (double)sy[h][r] - dot;
-                res *= res;
-            }
-#pragma unroll
-            for (int o = 1; o < NC; o <<= 1) res += __shfl_down(res, o, KP);
-            if (wr && r < 4) a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? res : 0.0;
+        // one or two entries, then three to eight
+        for (int c = n0; c < n0 + n2; c += G) {
+            const bool valid = c + h < n0 + n2;
+            const int2 item = a.items[i0 + (valid ? c + h : c)];
+            group_lowrank_copy<P, KP, kLowRankSmall>(a, item, valid, n, su, pr, sw[h], sy[h], sb[h], sz[h], t_sw,
+                                                     sample, ok, lane);
         }
-        if (valid && !ok && r == 0) {
+        for (int c = n0 + n2; c < cnt; c += G) {
+            const bool valid = c + h < cnt;
+            const int2 item = a.items[i0 + (valid ? c + h : c)];
+            group_lowrank_copy<P, KP, kLowRankNnz>(a, item, valid, n, su, pr, sw[h], sy[h], sb[h], sz[h], t_sw,
+                                                   sample, ok, lane);
+        }
+        if (!ok && lane < cnt) {
+            const int2 it = a.items[i0 + lane];
             if (a.fb_list) {
                 const int slot = atomicAdd(a.fb_count, 1);
-                a.fb_list[slot] = make_int2(item.x, n);
+                a.fb_list[slot] = make_int2(it.x, n);
                 atomicAdd(a.fb_total, 1);
             } else {
                 atomicAdd(a.nonpd, 1);
@@ -2444,7 +2452,7 @@ __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// k_pfac: the factor k_update_empty applies, from one moment-matched row
+// k_pfac: the factor k_update_group applies, from one moment-matched row
 // [Lambda packed, Lambda mu, mu] (FP64): L = chol(Lambda), U = L^-T, written
 // as FP32 rows j = 0 .. K-1 of U[r][r + j] (r < K - j, row j at offset
 // j K - j (j - 1) / 2), then a flag (1: Lambda positive definite).  Items are
@@ -2840,44 +2848,21 @@ hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_update_empty(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
-    if (grid <= 0) return hipSuccess;
+hipError_t launch_update_group(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+    if (grid <= 0 || a.ngroups <= 0) return hipSuccess;
     if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
     switch (prec) {
     case kP32:
-        if (kp == 32) hipLaunchKernelGGL((k_update_empty<kP32, 32>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_update_empty<kP32, 64>), dim3(grid), dim3(64), 0, s, a);
+        if (kp == 32) hipLaunchKernelGGL((k_update_group<kP32, 32>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_group<kP32, 64>), dim3(grid), dim3(64), 0, s, a);
         break;
     case kPBF:
-        if (kp == 32) hipLaunchKernelGGL((k_update_empty<kPBF, 32>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_update_empty<kPBF, 64>), dim3(grid), dim3(64), 0, s, a);
+        if (kp == 32) hipLaunchKernelGGL((k_update_group<kPBF, 32>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_group<kPBF, 64>), dim3(grid), dim3(64), 0, s, a);
         break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-template <int NC>
-static hipError_t lowrank_nc(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
-    switch (prec) {
-    case kP32:
-        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kP32, 32, NC>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_update_lowrank<kP32, 64, NC>), dim3(grid), dim3(64), 0, s, a);
-        break;
-    case kPBF:
-        if (kp == 32) hipLaunchKernelGGL((k_update_lowrank<kPBF, 32, NC>), dim3(grid), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_update_lowrank<kPBF, 64, NC>), dim3(grid), dim3(64), 0, s, a);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
-                                 bool small) {
-    if (grid <= 0) return hipSuccess;
-    if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
-    return small ? lowrank_nc<kLowRankSmall>(kp, prec, a, grid, s) : lowrank_nc<kLowRankNnz>(kp, prec, a, grid, s);
 }
 
 int32_t lowrank_max_nnz() { return kLowRankNnz; }

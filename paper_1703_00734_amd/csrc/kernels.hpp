@@ -55,6 +55,8 @@ struct UpdArgs {
     const double *colsq;      // column pass: per column the sum of its squared values
     const int2 *splits;       // per item (first partial slot, count); count 0: not split
     const float *gpart;       // partial Grams + right-hand sides (KP*KP + KP floats each)
+    const int32_t *gstart;    // prior groups: group g holds items [gstart[g], gstart[g+1])
+    int32_t ngroups;
 };
 
 // Partial Grams of heavy-entity segments (BF16 state, MFMA).
@@ -219,17 +221,11 @@ hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t
 // Two entities with at most 16 entries per wavefront, 16 < K <= 32, FP32 or
 // BF16 state (items in pairs: grid counts pairs).
 hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
-// Entities with no entries under a per-row prior whose factor is in pfac
-// (FP32 or BF16 state, K <= kp): x = mu + L^-T z without a factorisation;
-// 64 / kp entities per wavefront (grid counts wavefronts).
-hipError_t launch_update_empty(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
-// Entities with 1 .. lowrank_max_nnz() entries under a per-row prior whose factor
-// is in pfac (FP32 or BF16 state, K <= kp): the factor of the prior updated by
-// product-form rank-one modifications; 64 / kp entities per wavefront.  small:
-// every item has at most lowrank_small_nnz() entries (an instance that carries
-// that many entry vectors; the results are the same bit for bit).
-hipError_t launch_update_lowrank(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s,
-                                 bool small);
+// The copies of propagated rows in the sibling blocks of a stage that have at
+// most lowrank_max_nnz() entries, one prior group (copies sharing one stored
+// prior factor) per wavefront; a.items holds the copies grouped, sorted within
+// a group by entry count (0, 1 .. lowrank_small_nnz(), more).
+hipError_t launch_update_group(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
 int32_t lowrank_max_nnz();
 int32_t lowrank_small_nnz();
 // vgram: BF16 state with K > 16 takes the VALU-Gram kernel instead of the MFMA one
