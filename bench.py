@@ -68,23 +68,22 @@ def say(m):
     print("bench: " + m, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(M, n, K, state_bytes, kept, n_prop=0, n_empty=0, n_lowrank=0):
+def algorithmic_bytes(M, n, K, state_bytes, kept, n_prior=0, n_factor=0):
     """Bytes one update pass must move: per entry a column index and a value
     (8 B) plus the K-element factor row it gathers; per entity its pointer
-    pair and its written state row (and sample row when the sweep is kept);
-    per entity under a propagated prior (PP stages 2-3) that is factored its
-    packed FP64 prior, K(K+1)/2 precision entries and K of the
-    precision-weighted mean; per entity with no entries under a propagated
-    prior whose factor was computed at stage begin (n_empty) the FP32 factor,
-    K(K+1)/2 entries, and the K FP64 entries of the mean; per entity with a
-    few entries under such a prior (n_lowrank) the factor, the mean and the
-    precision-weighted mean."""
+    pair and its written state row (and sample row when the sweep is kept).
+    Propagated priors (PP stages 2-3) are charged once per distinct
+    propagated row, however many sibling blocks hold a copy of it: n_prior
+    rows whose packed FP64 prior (K(K+1)/2 precision entries and K of the
+    precision-weighted mean) some copy's factorisation reads, and n_factor
+    rows whose stored FP32 prior factor (K(K+1)/2 entries) and FP64 mean and
+    precision-weighted mean (2K entries) the copies with at most eight
+    entries read."""
     b = M * (8 + K * state_bytes) + n * (8 + K * state_bytes)
     if kept:
         b += n * K * 4
-    b += n_prop * (K * (K + 1) // 2 + K) * 8
-    b += n_empty * (K * (K + 1) // 2 * 4 + K * 8)
-    b += n_lowrank * (K * (K + 1) // 2 * 4 + 2 * K * 8)
+    b += n_prior * (K * (K + 1) // 2 + K) * 8
+    b += n_factor * (K * (K + 1) // 2 * 4 + 2 * K * 8)
     return b
 
 
@@ -173,10 +172,14 @@ def time_stages(d, cfg, precision, batched, steps, warmup):
         ktimes = {k: (after[k][0] - before.get(k, (0, 0.0))[0], after[k][1] - before.get(k, (0, 0.0))[1])
                   for k in after}
         row_updates, ratings = g.stage_work()
-        # entities with no entries (or at most LOWRANK_NNZ) under a propagated
-        # prior: the prior-factor paths take them in FP32/BF16 passes with K > 16
-        empty, lowrank, prop = [0, 0], [0, 0], [0, 0]
+        # propagated rows, once each across the sibling blocks that hold a
+        # copy: those some copy factorises (reading the packed FP64 prior) and
+        # those some copy with at most LOWRANK_NNZ entries takes on the
+        # prior-factor path (FP32/BF16 passes with K > 16)
+        fast = precision != "fp64" and d["K"] > 16
+        copies, prop, pfac = [0, 0], [0, 0], [0, 0]
         ents = [0, 0]
+        parts = [{}, {}]
         for b in range(g.nblocks()):
             info = g.block_info(b)
             if info["stage"] != s:
@@ -184,22 +187,26 @@ def time_stages(d, cfg, precision, batched, steps, warmup):
             bi, bj = divmod(b, cfg["J"])
             ents[0] += info["R"]
             ents[1] += info["C"]
-            for side, is_prop in ((0, bj > 0), (1, bi > 0)):
-                if not is_prop:
-                    continue
-                deg = np.diff(g.block_csr(b, side)[0])
-                prop[side] += deg.size
-                if precision != "fp64" and d["K"] > 16:
-                    empty[side] += int(np.count_nonzero(deg == 0))
-                    lowrank[side] += int(np.count_nonzero((deg >= 1) & (deg <= LOWRANK_NNZ)))
+            for side, is_prop, part in ((0, bj > 0, bi), (1, bi > 0, bj)):
+                if is_prop:
+                    parts[side].setdefault(part, []).append(np.diff(g.block_csr(b, side)[0]))
+        for side in (0, 1):
+            for degs in parts[side].values():
+                dm = np.stack(degs)
+                copies[side] += dm.size
+                if fast:
+                    prop[side] += int(np.count_nonzero((dm > LOWRANK_NNZ).any(axis=0)))
+                    pfac[side] += int(np.count_nonzero((dm <= LOWRANK_NNZ).any(axis=0)))
+                else:
+                    prop[side] += dm.shape[1]
         say("stage %d timed, %.4f ms per sweep" % (s, ms))
         if s != stages[-1] and extra:
             g.gibbs_sweep(extra)
             torch.cuda.synchronize()
         per_stage[s] = dict(ms_per_step=ms, wall_ms_per_step=1000 * wall / steps,
                             ktimes=ktimes, row_updates=row_updates, ratings=ratings,
-                            schedule=g.schedule(), empty_prop=empty, lowrank_prop=lowrank,
-                            prop=prop, ents=ents)
+                            schedule=g.schedule(), prop_copies=copies, prior_rows=prop,
+                            factor_rows=pfac, ents=ents)
     out = dict(per_stage=per_stage, stats=g.stats())
     g.close()
     return out
@@ -216,10 +223,15 @@ def run_chains(d, cfg, precision, batched, nchains, trace=""):
         tf = open(trace, "w") if (trace and q == 0) else None
         t0 = time.perf_counter()
         for s in stages_of(cfg):
+            # stage begin (the previous stage's moment matching and prior
+            # factors, this stage's initial state) with per-kernel timing;
+            # the sweeps run as captured graphs without it
+            h.enable_timing(True)
+            h.pp_stage(s, 0)
+            h.enable_timing(False)
             if tf is None:
-                h.pp_stage(s, sweeps)
+                h.gibbs_sweep(sweeps)
             else:
-                h.pp_stage(s, 0)
                 M = h.stage_work()[1]
                 for t in range(sweeps):
                     h.gibbs_sweep(1)
@@ -230,13 +242,18 @@ def run_chains(d, cfg, precision, batched, nchains, trace=""):
                                          "fallback_rows": st["fallback_rows"],
                                          "nonpd_rows": st["nonpd_rows"]}) + "\n")
             torch.cuda.synchronize()
+        h.enable_timing(True)
+        h.aggregate()                      # the last stage's moment matching, then Algorithm 2
+        h.enable_timing(False)
         p = h.predict(d["test_row"], d["test_col"])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st = h.stats()
+        kt = h.kernel_times()
         out.append(dict(seed=seed, rmse=float(np.sqrt(np.mean((p - d["test_val"]) ** 2))), chain_wall_s=wall,
                         mm_ridged=st["mm_ridged"], agg_corrections=st["agg_corrections"],
-                        fallback_rows=st["fallback_rows"]))
+                        fallback_rows=st["fallback_rows"],
+                        stage_end_ms={k: kt[k][1] for k in ("moment_match", "aggregate", "init") if k in kt}))
         if tf is not None:
             tf.close()
         h.close()
@@ -342,10 +359,8 @@ def pass_rooflines(d, cfg, arm, steps, state_bytes, config_id, precision):
                 continue
             launches, tot_ms = kt[kcls]
             n = m["ents"][side]
-            n_empty = m["empty_prop"][side]
-            n_lowrank = m["lowrank_prop"][side]
-            n_prop = m["prop"][side] - n_empty - n_lowrank
-            nbytes = algorithmic_bytes(m["ratings"], n, K, state_bytes, True, n_prop, n_empty, n_lowrank)
+            nbytes = algorithmic_bytes(m["ratings"], n, K, state_bytes, True, m["prior_rows"][side],
+                                       m["factor_rows"][side])
             avg_ms = (tot_ms + seg_ms) / steps
             ach = nbytes / (avg_ms / 1000.0) / 1e9
             traffic = measured_traffic(kcls, config_id, s, precision)

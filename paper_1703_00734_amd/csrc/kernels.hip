@@ -1646,8 +1646,8 @@ __device__ __forceinline__ float from_next(float x) { return dpp0<0x130>(x); }
 template <int P, int KP, int NC>
 __device__ __forceinline__ void group_lowrank_copy(
     const UpdArgs &a, const int2 item, const bool valid, const int n, const float *su, const double *pr,
-    float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz], float (&sb)[KP], float (&sz)[KP],
-    const uint32_t t_sw, void *sample, const bool ok, const int lane) {
+    float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz], float (&sb)[KP], const float *sz,
+    void *sample, const bool ok, const int lane) {
     using Tw = typename PrecT<P>::w;
     using Tv = typename PrecT<P>::v;
     using Ts = typename PrecT<P>::s;
@@ -1667,13 +1667,6 @@ __device__ __forceinline__ void group_lowrank_copy(
     for (int e = 0; e < NC; ++e)
         sw[e][r] = (e < nc && r < K) ? to_acc<float>(other[(int64_t)a.idx[p0 + e] * a.ks_other + r]) : 0.0f;
     if (r < NC) sy[r] = r < nc ? (float)val[p0 + r] : 0.0f;
-    if (4 * r < K) {
-        float z[4];
-        normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (4 * r + c < K) sz[4 * r + c] = z[c];
-    }
     __syncthreads();
     // h = Lambda mu + tau sum_e y_e w_e
     float hs = 0.0f;
@@ -1780,11 +1773,15 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
     using Ts = typename PrecT<P>::s;
     using Tp = typename PrecT<P>::p;
     constexpr int G = 64 / KP;
+    constexpr int WIN = 8;                           // copies whose noise is drawn together
+    constexpr int LPC = KP / 4;                      // lanes per copy in a draw (4 normals each)
+    constexpr int CPD = 64 / LPC;                    // copies per draw
+    static_assert(WIN % G == 0 && WIN % CPD == 0, "whole copies per window");
     __shared__ float su[KP * (KP + 1) / 2];          // the group's stored factor U
     __shared__ float sw[G][kLowRankNnz][KP];         // a copy's entries' rows of the other side
     __shared__ float sy[G][kLowRankNnz];             // their values
     __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
-    __shared__ float sz[G][KP];                      // noise
+    __shared__ float sz[WIN][KP];                    // noise of the window's copies
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
     uint32_t t_sw = a.t;
@@ -1816,49 +1813,64 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
         const int n2 = __popcll(__ballot(lane < cnt && dl >= 1 && dl <= kLowRankSmall));
         __syncthreads();                             // the previous group's factor is read
         for (int q = lane; q < kk2; q += 64) su[q] = pf[q];
-        __syncthreads();
-        // copies without entries: x = mu + U z
-        for (int c = 0; c < n0; c += G) {
-            const bool valid = c + h < n0;
-            const int2 item = a.items[i0 + (valid ? c + h : c)];
-            const SideDesc &sd = a.sides[item.x];
-            __syncthreads();
-            if (4 * r < K) {
-                float z[4];
-                normals4((uint32_t)n, t_sw, sd.c2, (uint32_t)r, a.k0, a.k1, z);
+        // windows of WIN copies: their noise in one draw per lane, then the
+        // window's copies of each kind, G side by side (the kinds stay in order
+        // inside a window, and a copy's draw does not depend on its partner)
+        for (int w0 = 0; w0 < cnt; w0 += WIN) {
+            const int w1 = min(cnt, w0 + WIN);
+            __syncthreads();                         // the previous window's noise is read
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (4 * r + e < K) sz[h][4 * r + e] = z[e];
+            for (int d0 = 0; d0 < WIN; d0 += CPD) {
+                const int cw = d0 + lane / LPC, q = lane % LPC;
+                if (w0 + cw < w1 && 4 * q < K) {
+                    const int2 it = a.items[i0 + w0 + cw];
+                    float z[4];
+                    normals4((uint32_t)n, t_sw, a.sides[it.x].c2, (uint32_t)q, a.k0, a.k1, z);
+#pragma unroll
+                    for (int e2 = 0; e2 < 4; ++e2)
+                        if (4 * q + e2 < K) sz[cw][4 * q + e2] = z[e2];
+                }
             }
             __syncthreads();
-            float acc = 0.0f;
-            int off = 0;
+            // copies without entries: x = mu + U z
+            const int e0 = min(n0, w1);
+            for (int c = w0; c < e0; c += G) {
+                const bool valid = c + h < e0;
+                const int ci = valid ? c + h : c;
+                const int2 item = a.items[i0 + ci];
+                const SideDesc &sd = a.sides[item.x];
+                const float *zc = sz[ci - w0];
+                float acc = 0.0f;
+                int off = 0;
 #pragma unroll 8
-            for (int j = 0; j < K; ++j) {
-                if (r + j < K) acc += su[off + r] * sz[h][r + j];
-                off += K - j;
+                for (int j = 0; j < K; ++j) {
+                    if (r + j < K) acc += su[off + r] * zc[r + j];
+                    off += K - j;
+                }
+                const double *mu = pr + kk2 + K;
+                const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
+                const bool wr = valid && ok;
+                if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
+                if (wr && sample && r < a.ks_sample)
+                    reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
+                if (wr && a.sse_col && r < 4)
+                    a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? a.colsq[sd.self_off + n] : 0.0;
             }
-            const double *mu = pr + kk2 + K;
-            const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
-            const bool wr = valid && ok;
-            if (wr && r < a.ks_self) self[(sd.self_off + n) * a.ks_self + r] = elem_from<Ts>((double)xv);
-            if (wr && sample && r < a.ks_sample)
-                reinterpret_cast<Tp *>(sample)[(sd.sample_off + n) * a.ks_sample + r] = (Tp)xv;
-            if (wr && a.sse_col && r < 4)
-                a.sse_col[4 * (sd.self_off + n) + r] = r == 0 ? a.colsq[sd.self_off + n] : 0.0;
-        }
-        // one or two entries, then three to eight
-        for (int c = n0; c < n0 + n2; c += G) {
-            const bool valid = c + h < n0 + n2;
-            const int2 item = a.items[i0 + (valid ? c + h : c)];
-            group_lowrank_copy<P, KP, kLowRankSmall>(a, item, valid, n, su, pr, sw[h], sy[h], sb[h], sz[h], t_sw,
-                                                     sample, ok, lane);
-        }
-        for (int c = n0 + n2; c < cnt; c += G) {
-            const bool valid = c + h < cnt;
-            const int2 item = a.items[i0 + (valid ? c + h : c)];
-            group_lowrank_copy<P, KP, kLowRankNnz>(a, item, valid, n, su, pr, sw[h], sy[h], sb[h], sz[h], t_sw,
-                                                   sample, ok, lane);
+            // one or two entries, then three to eight
+            const int s0 = max(n0, w0), s1 = min(n0 + n2, w1);
+            for (int c = s0; c < s1; c += G) {
+                const bool valid = c + h < s1;
+                const int ci = valid ? c + h : c;
+                group_lowrank_copy<P, KP, kLowRankSmall>(a, a.items[i0 + ci], valid, n, su, pr, sw[h], sy[h], sb[h],
+                                                         sz[ci - w0], sample, ok, lane);
+            }
+            const int b0 = max(n0 + n2, w0);
+            for (int c = b0; c < w1; c += G) {
+                const bool valid = c + h < w1;
+                const int ci = valid ? c + h : c;
+                group_lowrank_copy<P, KP, kLowRankNnz>(a, a.items[i0 + ci], valid, n, su, pr, sw[h], sy[h], sb[h],
+                                                       sz[ci - w0], sample, ok, lane);
+            }
         }
         if (!ok && lane < cnt) {
             const int2 it = a.items[i0 + lane];
@@ -2452,54 +2464,226 @@ __global__ __launch_bounds__(64) void k_mm(const MmArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// k_pfac: the factor k_update_group applies, from one moment-matched row
+// k_mm_rows: moment matching for K <= KP <= 32, one covariance row per lane
+// and 64 / KP entities per wavefront (lanes KP h .. KP h + KP - 1 hold entity
+// h; padding rows and columns beyond K hold the identity).  The mean and the
+// two-pass covariance sum the kept samples in sample order; a chunk of
+// centred samples passes through LDS and every lane reads it back by
+// broadcast.  Lambda_hat = Sigma_hat^-1 comes from the symmetric sweep
+// operator (Goodnight, 1979) applied to pivots 0 .. K-1: after each sweep the
+// working matrix is still symmetric, so pivot row k is the column k that the
+// lanes hold, and the full sweep leaves -Sigma_hat^-1.  The pivots are the
+// successive Schur complements of Sigma_hat (the squares of its Cholesky
+// pivots), so a pivot that is not positive is the factorisation failing: the
+// entity is computed again with the ridge.  The output row is staged in LDS
+// and stored contiguously.
+// --------------------------------------------------------------------------
+template <typename Ts, int KP>
+__global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
+    constexpr int G = 64 / KP;
+    constexpr int MC = KP == 32 ? 20 : 12;          // samples per LDS chunk
+    static_assert(MC * KP >= KP * (KP + 1) / 2 + 2 * KP, "the output row is staged in the chunk buffer");
+    __shared__ __align__(16) double xs[G][MC * KP];
+    __shared__ __align__(16) double bc[G][KP];
+    const int lane = threadIdx.x;
+    const int h = lane / KP, r = lane % KP;
+    const int K = a.K, S = a.S;
+    const int kk2 = K * (K + 1) / 2;
+    for (int pit = blockIdx.x; G * pit < a.nitems; pit += gridDim.x) {
+        const int it = G * pit + h;
+        const bool valid = it < a.nitems;           // uniform per entity
+        const int2 item = a.items[valid ? it : G * pit];
+        const SideDesc &sd = a.sides[item.x];
+        const int n = item.y;
+        const Ts *smp = reinterpret_cast<const Ts *>(a.sample) + (sd.sample_off + n) * a.ks;
+        double *out = a.out[item.x] + (int64_t)n * a.prow;
+        double mu = 0.0;
+        if (r < K) {
+            double s = 0.0;
+            for (int q = 0; q < S; ++q) s += (double)smp[(int64_t)q * a.slot_elems + r];
+            mu = s / (double)S;
+        }
+        double row[KP];
+#pragma unroll
+        for (int c = 0; c < KP; ++c) row[c] = 0.0;
+        bool ridge = S <= K;
+        for (int pass = 0; pass < 2 && S >= 2; ++pass) {
+#pragma unroll
+            for (int c = 0; c < KP; ++c) row[c] = 0.0;
+            for (int t0 = 0; t0 < S; t0 += MC) {
+                const int nt = min(MC, S - t0);
+                __syncthreads();                    // the previous chunk is read
+                for (int t = 0; t < nt; ++t)
+                    xs[h][t * KP + r] = r < K ? (double)smp[(int64_t)(t0 + t) * a.slot_elems + r] - mu : 0.0;
+                __syncthreads();
+                for (int t = 0; t < nt; ++t) {
+                    const double xr = xs[h][t * KP + r];
+#pragma unroll
+                    for (int c = 0; c < KP; ++c) row[c] += xr * xs[h][t * KP + c];
+                }
+            }
+            const double inv_s1 = 1.0 / (double)(S - 1);
+#pragma unroll
+            for (int c = 0; c < KP; ++c) row[c] = r < K ? row[c] * inv_s1 : (c == r ? 1.0 : 0.0);
+            if (ridge) {
+                double dg = 0.0;
+#pragma unroll
+                for (int c = 0; c < KP; ++c) dg = c == r ? row[c] : dg;
+                double tr = 0.0;
+                for (int k = 0; k < K; ++k) tr += __shfl(dg, h * KP + k, 64);   // in index order
+                const double delta = 1e-6 * tr / (double)K + 1e-300;
+#pragma unroll
+                for (int c = 0; c < KP; ++c) row[c] += (c == r && r < K) ? delta : 0.0;
+            }
+            // sweep pivots 0 .. K-1
+            int bad = 0;
+#pragma unroll
+            for (int k = 0; k < KP; ++k) {
+                if (k < K) {
+                    __syncthreads();                // the previous pivot column is read
+                    bc[h][r] = row[k];
+                    __syncthreads();
+                    const double p = bc[h][k];
+                    bad |= !(p > 0.0);
+                    const double ip = 1.0 / (p > 0.0 ? p : 1.0);
+                    const double f = row[k] * ip;
+                    const bool own = r == k;
+#pragma unroll
+                    for (int j = 0; j < KP; ++j) {
+                        if (j == k) continue;
+                        const double bj = bc[h][j];
+                        row[j] = own ? bj * ip : row[j] - f * bj;
+                    }
+                    row[k] = own ? -ip : f;
+                }
+            }
+            const bool again = !ridge && bad;       // the factorisation failed: take the ridge
+            if (valid && ridge && r == 0) atomicAdd(a.ridged, 1);
+            if (__ballot(valid && again) == 0) break;
+            ridge = ridge || again;
+            if (pass == 1) break;
+        }
+        // Lambda_hat mu_hat, then the packed row through LDS
+        __syncthreads();
+        bc[h][r] = mu;
+        __syncthreads();
+        double eta = 0.0;
+#pragma unroll
+        for (int c = 0; c < KP; ++c) eta -= row[c] * bc[h][c];
+        __syncthreads();                            // the chunk buffer is free
+        if (r < K) {
+            const int base = r * (r + 1) / 2;
+#pragma unroll
+            for (int c = 0; c < KP; ++c)
+                if (c <= r) xs[h][base + c] = S >= 2 ? -row[c] : 0.0;
+            xs[h][kk2 + r] = S >= 2 ? eta : 0.0;
+            xs[h][kk2 + K + r] = mu;
+        }
+        __syncthreads();
+        if (valid)
+            for (int q = r; q < a.prow; q += KP) out[q] = xs[h][q];
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_pfac_rows: the factor k_update_group applies, from one moment-matched row
 // [Lambda packed, Lambda mu, mu] (FP64): L = chol(Lambda), U = L^-T, written
 // as FP32 rows j = 0 .. K-1 of U[r][r + j] (r < K - j, row j at offset
 // j K - j (j - 1) / 2), then a flag (1: Lambda positive definite).  Items are
 // (side, entity); sides whose rows seed no later stage have no output.
+// 64 / KP entities per wavefront, lane r of a group holding row r.  With
+// Lambda = L L^T, the factor
+// U = L^-T is the upper-triangular factor of Sigma = Lambda^-1 = U U^T, which
+// is unique with a positive diagonal; so Sigma comes from the symmetric sweep
+// of Lambda over pivots 0 .. K-1 (it leaves -Sigma), and U from Sigma by the
+// Cholesky elimination taken from the last pivot to the first:
+// U[k][k] = sqrt(S[k][k]), U[r][k] = S[r][k] / U[k][k] (r < k), then
+// S[r][j] -= U[r][k] U[j][k] for r, j < k.  The flag is 1 when every pivot of
+// both eliminations is positive (Lambda positive definite).  The packed input
+// row and the output row pass through LDS so that both are moved contiguously.
 // --------------------------------------------------------------------------
 template <int KP>
-__global__ __launch_bounds__(64) void k_pfac(const PfacArgs a) {
-    constexpr int LD = KP + 1;
-    __shared__ double lin[KP * LD];
-    __shared__ double inv[KP * LD];
-    __shared__ int flag;
+__global__ __launch_bounds__(64) void k_pfac_rows(const PfacArgs a) {
+    constexpr int G = 64 / KP;
+    constexpr int NP = KP * (KP + 1) / 2;
+    __shared__ __align__(16) double pk[G][NP];
+    __shared__ __align__(16) float po[G][NP + 1];
+    __shared__ double bc[G][KP];
     const int lane = threadIdx.x;
+    const int h = lane / KP, r = lane % KP;
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
-    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
-        const int2 item = a.items[it];
+    for (int pit = blockIdx.x; G * pit < a.nitems; pit += gridDim.x) {
+        const int it = G * pit + h;
+        const bool valid = it < a.nitems;
+        const int2 item = a.items[valid ? it : G * pit];
         float *pfo = a.pfout[item.x];
-        if (pfo == nullptr) continue;                // uniform over the block
-        pfo += (int64_t)item.y * a.pfrow;
-        const double *row = a.out[item.x] + (int64_t)item.y * a.prow;
-        for (int q = lane; q < K * K; q += 64) {
-            const int r = q / K, c = q - r * K;
-            lin[r * LD + c] = c <= r ? row[tri(r, c)] : 0.0;
+        const bool act = valid && pfo != nullptr;          // uniform per group
+        if (__ballot(act) == 0) continue;                   // uniform per wavefront
+        __syncthreads();                                    // the previous rows are read
+        if (act) {
+            const double *row = a.out[item.x] + (int64_t)item.y * a.prow;
+            for (int q = r; q < kk2; q += KP) pk[h][q] = row[q];
         }
         __syncthreads();
-        const bool ok = chol_lds<double>(lin, K, LD, 0.0, nullptr, lane, &flag);
-        // inv <- L^-1, column c by lane c
-        for (int c = lane; c < K; c += 64) {
-            for (int i = 0; i < K; ++i) {
-                if (i < c) {
-                    inv[i * LD + c] = 0.0;
-                } else {
-                    double s = (i == c) ? 1.0 : 0.0;
-                    for (int p = c; p < i; ++p) s -= lin[i * LD + p] * inv[p * LD + c];
-                    inv[i * LD + c] = s / lin[i * LD + i];
+        double m[KP];
+#pragma unroll
+        for (int c = 0; c < KP; ++c)
+            m[c] = (act && r < K && c < K) ? pk[h][r >= c ? tri(r, c) : tri(c, r)] : (c == r ? 1.0 : 0.0);
+        int bad = 0;
+        // sweep: m <- -Lambda^-1
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+            if (k < K) {
+                __syncthreads();
+                bc[h][r] = m[k];
+                __syncthreads();
+                const double p = bc[h][k];
+                bad |= !(p > 0.0);
+                const double ip = 1.0 / (p > 0.0 ? p : 1.0);
+                const double f = m[k] * ip;
+                const bool own = r == k;
+#pragma unroll
+                for (int j = 0; j < KP; ++j) {
+                    if (j == k) continue;
+                    const double bj = bc[h][j];
+                    m[j] = own ? bj * ip : m[j] - f * bj;
                 }
+                m[k] = own ? -ip : f;
             }
         }
-        __syncthreads();
-        for (int j = 0; j < K; ++j) {
-            const int off = j * K - j * (j - 1) / 2;
-            for (int r = lane; r < K - j; r += 64) pfo[off + r] = (float)inv[(r + j) * LD + r];
+        // Sigma = -m; its upper factor from the last pivot to the first
+#pragma unroll
+        for (int c = 0; c < KP; ++c) m[c] = -m[c];
+#pragma unroll
+        for (int k = KP - 1; k >= 0; --k) {
+            if (k < K) {
+                __syncthreads();
+                bc[h][r] = m[k];
+                __syncthreads();
+                const double d = bc[h][k];
+                bad |= !(d > 0.0);
+                const double u = d > 0.0 ? sqrt(d) : 1.0;
+                const double iu = 1.0 / u;
+                const double f = m[k] * iu;                 // U[r][k] for r <= k
+#pragma unroll
+                for (int j = 0; j < k; ++j) m[j] -= f * (bc[h][j] * iu);
+                m[k] = r <= k ? f : 0.0;
+            }
         }
-        if (lane == 0) pfo[kk2] = ok ? 1.0f : 0.0f;
+        // U[r][r + j] at j K - j (j - 1) / 2 + r, then the flag
+#pragma unroll
+        for (int c = 0; c < KP; ++c) {
+            const int j = c - r;
+            if (act && r < K && c < K && j >= 0) po[h][j * K - j * (j - 1) / 2 + r] = (float)m[c];
+        }
+        if (act && r == 0) po[h][kk2] = bad ? 0.0f : 1.0f;
         __syncthreads();
+        if (act)
+            for (int q = r; q <= kk2; q += KP) pfo[(int64_t)item.y * a.pfrow + q] = po[h][q];
     }
 }
+
 
 // --------------------------------------------------------------------------
 // k_agg: Algorithm 2 for one row of a row (or column) block (FP64), one
@@ -2716,6 +2900,243 @@ __global__ __launch_bounds__(64) void k_agg(const AggArgs a) {
         if (own) dg[lane] = sS[lane * LD + lane];
         __syncthreads();
         factor_solve_regs<KP, double>(sS, LD, sS, LD, rhs, zero, dg, sinv, 0.0, K, lane);
+        if (lane < K) out[lane] = rhs[lane];
+        __syncthreads();
+    }
+}
+
+// Positive-definiteness test of the symmetric K x K matrix whose row r the
+// group's lane r holds in d[] (destroyed; identity padding beyond K): the
+// symmetric elimination A <- A22 - a21 a21^T / a11, whose pivots are the
+// squares of the Cholesky pivots.  Column k of the trailing matrix is its row
+// k, so each step broadcasts the lanes' entries k through the group's LDS row
+// bc.  Returns false when a pivot is not positive, as the factorisation would.
+template <int KP>
+__device__ __forceinline__ bool grp_pd_test(double (&d)[KP], const int K, const int r, double *bc) {
+    int bad = 0;
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        if (k < K) {
+            __syncthreads();                        // the previous column is read
+            bc[r] = d[k];
+            __syncthreads();
+            const double p = bc[k];
+            bad |= !(p > 0.0);
+            const double f = d[k] / (p > 0.0 ? p : 1.0);
+#pragma unroll
+            for (int j = k + 1; j < KP; ++j) d[j] -= f * bc[j];
+        }
+    }
+    return bad == 0;
+}
+
+// Smallest eigenvalue of the symmetric K x K matrix whose row r the group's
+// lane r holds in a[] (destroyed).  Householder reduction to a tridiagonal T
+// (Golub and Van Loan, Sec. 8.3.1) with the rows in registers: step k
+// reflects column k below the diagonal onto its first entry and applies the
+// reflector from both sides as the rank-two update A - v w^T - w v^T.  Then
+// bisection on Sturm counts of T (the number of negative pivots of T - s I;
+// Golub and Van Loan, Sec. 8.4.1), KP shifts at a time, one per lane: each
+// round keeps the subinterval where the count first reaches one, until it is
+// within two units of roundoff of ||T||.  gl0 is the group's first lane; vb,
+// wb, td, te hold KP doubles of the group's LDS.
+template <int KP>
+__device__ double grp_min_eig(double (&a)[KP], const int K, const int r, const int gl0, double *vb, double *wb,
+                              double *td, double *te) {
+    const unsigned long long gmask = KP == 64 ? ~0ull : (((1ull << KP) - 1) << gl0);
+#pragma unroll
+    for (int k = 0; k < KP - 2; ++k) {
+        if (k < K - 2) {
+            const double x = r > k ? a[k] : 0.0;    // column k below the diagonal
+            const double x1 = __shfl(x, gl0 + k + 1, 64);
+            const double s2 = group_sum1(r > k + 1 ? x * x : 0.0, KP);
+            double alpha = x1, beta = 0.0, v = 0.0;
+            if (s2 > 0.0) {                          // otherwise column k is reduced already
+                const double mu = sqrt(x1 * x1 + s2);
+                alpha = x1 <= 0.0 ? mu : -mu;
+                const double v1 = x1 - alpha;
+                beta = 2.0 / (v1 * v1 + s2);
+                v = r == k + 1 ? v1 : x;
+            }
+            if (r == 0) te[k] = alpha;
+            __syncthreads();                         // the previous step's vb, wb are read
+            vb[r] = v;
+            __syncthreads();
+            double p = 0.0;
+#pragma unroll
+            for (int j = 0; j < KP; ++j) p += a[j] * vb[j];
+            p *= beta;
+            const double pv = group_sum1(p * v, KP);
+            const double w = r > k ? p - 0.5 * beta * pv * v : 0.0;
+            wb[r] = w;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < KP; ++j) a[j] -= v * wb[j] + w * vb[j];
+        }
+    }
+    // diagonal and last off-diagonal entry of T
+    double dr = 0.0, el = 0.0;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        dr = j == r ? a[j] : dr;
+        el = j == K - 2 ? a[j] : el;
+    }
+    if (r < K) td[r] = dr;
+    if (K >= 2 && r == K - 1) te[K - 2] = el;
+    __syncthreads();
+    // Gershgorin bounds: every eigenvalue lies above lo, and the smallest one
+    // lies below the smallest diagonal entry
+    double lo = 1e300, hi = 1e300, tn = 0.0, e2max = 0.0;
+    if (r < K) {
+        const double em = r > 0 ? fabs(te[r - 1]) : 0.0, ep = r < K - 1 ? fabs(te[r]) : 0.0;
+        lo = td[r] - em - ep;
+        hi = td[r];
+        tn = fabs(td[r]) + em + ep;
+        e2max = ep * ep;
+    }
+#pragma unroll
+    for (int o = 1; o < KP; o <<= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmin(hi, __shfl_xor(hi, o, 64));
+        tn = fmax(tn, __shfl_xor(tn, o, 64));
+        e2max = fmax(e2max, __shfl_xor(e2max, o, 64));
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, e2max);
+    const double tol = 4.440892098500626e-16 * tn;
+    // every group runs the same number of rounds; a finished group keeps its interval
+    for (int round = 0; round < 64; ++round) {
+        const bool open = hi - lo > tol;
+        if (__ballot(open) == 0) break;
+        const double width = hi - lo;
+        const double sg = lo + (double)(r + 1) * width / (double)(KP + 1);
+        int cnt = 0;
+        double q = 1.0;
+        for (int i = 0; i < K; ++i) {
+            double t = td[i] - sg;
+            if (i > 0) {
+                // e^2 / q through the reciprocal with one Newton step: the count
+                // only needs the sign of each pivot
+                const double rc0 = __builtin_amdgcn_rcp(q);
+                const double rc = fma(rc0, fma(-q, rc0, 1.0), rc0);
+                t -= te[i - 1] * te[i - 1] * rc;
+            }
+            q = fabs(t) < pivmin ? -pivmin : t;
+            cnt += q < 0.0;
+        }
+        const unsigned long long hit = __ballot(cnt > 0) & gmask;
+        const int first = hit ? (int)(__builtin_ctzll(hit) - gl0) : KP;
+        if (open) {
+            const double nhi = first < KP ? lo + (double)(first + 1) * width / (double)(KP + 1) : hi;
+            const double nlo = first > 0 ? lo + (double)first * width / (double)(KP + 1) : lo;
+            lo = nlo;
+            hi = nhi;
+        }
+    }
+    return 0.5 * (lo + hi);
+}
+
+// k_agg_rows: Algorithm 2 for one row per wavefront (K <= KP <= 32), the
+// siblings 64 / KP at a time, one per group of KP lanes (lane r of a group
+// holds row r).  A group stages D_j = Lambda_j - Lambda_b in its LDS block,
+// tests it (grp_pd_test) and, when the test fails, takes lambda_min(D_j) from
+// grp_min_eig; Lambda~_j and Lambda~_j mu_j then replace D_j there, and every
+// lane adds the groups' blocks into its row of Lambda* in sibling order, as
+// the sequential algorithm does.  mu* = Lambda*^-1 (Lambda* mu*) by
+// factor_solve_regs.
+template <int KP>
+__global__ __launch_bounds__(64) void k_agg_rows(const AggArgs a) {
+    constexpr int G = 64 / KP;
+    constexpr int LD = KP + 2;                      // doubles; 16-byte rows
+    __shared__ __align__(16) double sT[G][KP * LD];
+    __shared__ double vb[G][KP], wb[G][KP], td[G][KP], te[G][KP], rv[G][KP];
+    __shared__ double rhs[KP], dg[KP], sinv[KP], zero[KP];
+    int lane = threadIdx.x;
+    const int g = lane / KP, r = lane % KP, gl0 = g * KP;
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    for (int it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+        const int2 item = a.items[it];
+        const AggJob &jb = a.jobs[item.x];
+        const int n = item.y;
+        const double *brow = jb.base + (int64_t)n * a.prow;
+        double *out = a.out + (jb.out_off + n) * K;
+        if (jb.nsib == 0) {
+            if (lane < K) out[lane] = brow[kk2 + K + lane];
+            continue;
+        }
+        double tr = 0.0;
+        for (int k = 0; k < K; ++k) tr += brow[tri(k, k)];
+        const double eps = 1e-6 * tr / (double)K;
+        const double cb = 2.0 - (double)(jb.nsib + 1);
+        // row r of Lambda* = (2 - J) Lambda_b + ..., and of its right-hand side
+        double acc[KP];
+        double hr = 0.0;
+        {
+            double s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < KP; ++c) {
+                const double lb = (r < K && c < K) ? packed_sym(brow, r, c) : 0.0;
+                acc[c] = (r < K && c < K) ? cb * lb : (c == r ? 1.0 : 0.0);
+                if (c < K) s2 += lb * brow[kk2 + K + c];
+            }
+            hr = r < K ? cb * s2 : 0.0;
+        }
+        for (int s0 = 0; s0 < jb.nsib; s0 += G) {
+            const int s = s0 + g;
+            const bool act = s < jb.nsib;
+            const double *srow = jb.sib[act ? s : s0] + (int64_t)n * a.prow;
+            __syncthreads();                        // the previous siblings' blocks are read
+            for (int q = r; q < K * K; q += KP) {
+                const int rr = q / K, cc = q - rr * K;
+                sT[g][rr * LD + cc] = packed_sym(srow, rr, cc) - packed_sym(brow, rr, cc);
+            }
+            __syncthreads();
+            double d[KP];
+#pragma unroll
+            for (int c = 0; c < KP; ++c) d[c] = (r < K && c < K) ? sT[g][r * LD + c] : (c == r ? 1.0 : 0.0);
+            const bool pd = grp_pd_test<KP>(d, K, r, vb[g]);
+            double shift = 0.0;
+            if (__ballot(act && !pd) != 0) {
+#pragma unroll
+                for (int c = 0; c < KP; ++c) d[c] = (r < K && c < K) ? sT[g][r * LD + c] : (c == r ? 1.0 : 0.0);
+                const double lmin = grp_min_eig<KP>(d, K, r, gl0, vb[g], wb[g], td[g], te[g]);
+                shift = fabs(lmin) + eps;
+            }
+            if (act && !pd && r == 0) atomicAdd(a.corrections, 1);
+            // Lambda~_j (row r) over D_j, and Lambda~_j mu_j
+            double s2 = 0.0;
+            for (int c = 0; c < K; ++c) {
+                double v = packed_sym(srow, r < K ? r : 0, c);
+                if (!pd) v = (sT[g][r * LD + c] + (r == c ? shift : 0.0)) + packed_sym(brow, r < K ? r : 0, c);
+                s2 += v * srow[kk2 + K + c];
+                if (r < K) sT[g][r * LD + c] = v;
+            }
+            rv[g][r] = s2;
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                if (s0 + q < jb.nsib) {
+#pragma unroll
+                    for (int c = 0; c < KP; ++c)
+                        if (r < K && c < K) acc[c] += sT[q][r * LD + c];
+                    if (r < K) hr += rv[q][r];
+                }
+            }
+        }
+        // mu* = Lambda*^-1 (Lambda* mu*)
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+            for (int c = 0; c < KP; ++c) sT[0][r * LD + c] = acc[c];
+            rhs[r] = hr;
+            zero[r] = 0.0;
+            double dd = 0.0;
+#pragma unroll
+            for (int c = 0; c < KP; ++c) dd = c == r ? acc[c] : dd;
+            dg[r] = dd;
+        }
+        __syncthreads();
+        factor_solve_regs<KP, double>(sT[0], LD, sT[0], LD, rhs, zero, dg, sinv, 0.0, K, lane);
         if (lane < K) out[lane] = rhs[lane];
         __syncthreads();
     }
@@ -2980,8 +3401,9 @@ hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s) {
     if (a.nitems <= 0) return hipSuccess;
     const int g = grid_for(a.nitems, 1, 65536);
     if (a.K > kp) return hipErrorInvalidValue;
-    if (kp <= 32) hipLaunchKernelGGL((k_pfac<32>), dim3(g), dim3(64), 0, s, a);
-    else if (kp <= 64) hipLaunchKernelGGL((k_pfac<64>), dim3(g), dim3(64), 0, s, a);
+    if (kp <= 32) hipLaunchKernelGGL((k_pfac_rows<32>), dim3(grid_for((a.nitems + 1) / 2, 1, 65536)), dim3(64), 0,
+                                     s, a);
+    else if (kp <= 64) hipLaunchKernelGGL((k_pfac_rows<64>), dim3(g), dim3(64), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -2991,11 +3413,13 @@ hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s) {
     const int g = grid_for(a.nitems, 1, 65536);
     const bool d = prec == kP64;
     if (a.K <= 16) {
-        if (d) hipLaunchKernelGGL((k_mm<double, 16>), dim3(g), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_mm<float, 16>), dim3(g), dim3(64), 0, s, a);
+        const int g4 = grid_for((a.nitems + 3) / 4, 1, 65536);
+        if (d) hipLaunchKernelGGL((k_mm_rows<double, 16>), dim3(g4), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_mm_rows<float, 16>), dim3(g4), dim3(64), 0, s, a);
     } else if (a.K <= 32) {
-        if (d) hipLaunchKernelGGL((k_mm<double, 32>), dim3(g), dim3(64), 0, s, a);
-        else hipLaunchKernelGGL((k_mm<float, 32>), dim3(g), dim3(64), 0, s, a);
+        const int g2 = grid_for((a.nitems + 1) / 2, 1, 65536);
+        if (d) hipLaunchKernelGGL((k_mm_rows<double, 32>), dim3(g2), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_mm_rows<float, 32>), dim3(g2), dim3(64), 0, s, a);
     } else {
         if (d) hipLaunchKernelGGL((k_mm<double, 64>), dim3(g), dim3(64), 0, s, a);
         else hipLaunchKernelGGL((k_mm<float, 64>), dim3(g), dim3(64), 0, s, a);
@@ -3006,8 +3430,8 @@ hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s) {
 hipError_t launch_agg(const AggArgs &a, hipStream_t s) {
     if (a.nitems <= 0) return hipSuccess;
     const dim3 grid(grid_for(a.nitems, 1, 65536));
-    if (a.K <= 16) hipLaunchKernelGGL(k_agg<16>, grid, dim3(64), 0, s, a);
-    else if (a.K <= 32) hipLaunchKernelGGL(k_agg<32>, grid, dim3(64), 0, s, a);
+    if (a.K <= 16) hipLaunchKernelGGL(k_agg_rows<16>, grid, dim3(64), 0, s, a);
+    else if (a.K <= 32) hipLaunchKernelGGL(k_agg_rows<32>, grid, dim3(64), 0, s, a);
     else hipLaunchKernelGGL(k_agg<64>, grid, dim3(64), 0, s, a);
     return hipGetLastError();
 }
