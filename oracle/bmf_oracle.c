@@ -547,3 +547,183 @@ int64_t orc_mm(int64_t R, int32_t K, int32_t S, const double *samples, double *m
     free(Sig); free(L);
     return ridged;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Clustering of the kept samples for the dominant-mode (PP-DM) and mixture  */
+/* (PP-GMM) approximations (Sec. 4.1; Sec. 5.1, which clusters each          */
+/* parameter's samples with the nonparametric lambda-means algorithm).  The  */
+/* iteration is the hard-clustering one of DP-means (Kulis and Jordan, 2012): */
+/* in sample order, each sample joins the nearest centre unless that centre  */
+/* is farther than lambda, in which case it opens a new cluster on itself;   */
+/* then every centre moves to the mean of its members.  Readings (the paper  */
+/* gives no lambda or stopping rule): one initial cluster at the mean of all */
+/* samples; lambda^2 = c^2 sum_t |x_(t+1) - x_t|^2 / (2 (S - 1)), the mean   */
+/* squared step between successive kept samples over two, times the square  */
+/* of a scale c; at most cmax clusters (a sample that would open one more    */
+/* joins its nearest); clusters left without members are dropped, the others */
+/* keep their order; the iteration stops when the assignment repeats or      */
+/* after maxit rounds.  Distances and sums run in index order, unfused.      */
+/* ------------------------------------------------------------------------- */
+
+/* Squared distance of two K-vectors, components in order. */
+static double orc_dist2(int K, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double d = a[k] - b[k];
+        s = s + d * d;
+    }
+    return s;
+}
+
+/* One entity: xs[q] points at sample q (K values).  Writes labels[q] and
+ * returns the number of clusters. */
+static int orc_lmeans_one(int K, int S, const double *const *xs, double lam_scale, int cmax,
+                          int maxit, int32_t *labels, double *cent, int32_t *cnt, int32_t *prev)
+{
+    /* lambda from the successive steps */
+    double steps = 0.0;
+    for (int q = 0; q + 1 < S; ++q)
+        steps = steps + orc_dist2(K, xs[q + 1], xs[q]);
+    const double lam2 = S > 1 ? lam_scale * lam_scale * steps / (2.0 * (double)(S - 1)) : 0.0;
+    /* one cluster at the mean */
+    int C = 1;
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int q = 0; q < S; ++q)
+            s = s + xs[q][k];
+        cent[k] = s / (double)S;
+    }
+    for (int q = 0; q < S; ++q)
+        prev[q] = -1;
+    for (int it = 0; it < maxit; ++it) {
+        /* assignment, in sample order */
+        for (int q = 0; q < S; ++q) {
+            int best = 0;
+            double dbest = orc_dist2(K, xs[q], cent);
+            for (int c = 1; c < C; ++c) {
+                const double d = orc_dist2(K, xs[q], cent + (size_t)c * K);
+                if (d < dbest) {
+                    dbest = d;
+                    best = c;
+                }
+            }
+            if (dbest > lam2 && C < cmax) {
+                memcpy(cent + (size_t)C * K, xs[q], sizeof(double) * K);
+                best = C++;
+            }
+            labels[q] = best;
+        }
+        /* centres: member means (sums in sample order); drop empty clusters */
+        for (int c = 0; c < C; ++c) {
+            cnt[c] = 0;
+            for (int k = 0; k < K; ++k)
+                cent[(size_t)c * K + k] = 0.0;
+        }
+        for (int q = 0; q < S; ++q) {
+            double *m = cent + (size_t)labels[q] * K;
+            for (int k = 0; k < K; ++k)
+                m[k] = m[k] + xs[q][k];
+            cnt[labels[q]] += 1;
+        }
+        int Cn = 0;
+        for (int c = 0; c < C; ++c) {
+            if (cnt[c] == 0)
+                continue;
+            for (int k = 0; k < K; ++k)
+                cent[(size_t)Cn * K + k] = cent[(size_t)c * K + k] / (double)cnt[c];
+            cnt[Cn] = cnt[c];
+            for (int q = 0; q < S; ++q)
+                if (labels[q] == c)
+                    labels[q] = Cn;
+            ++Cn;
+        }
+        C = Cn;
+        int same = 1;
+        for (int q = 0; q < S; ++q) {
+            same &= labels[q] == prev[q];
+            prev[q] = labels[q];
+        }
+        if (same)
+            break;
+    }
+    return C;
+}
+
+/* Labels (R x S, row n = entity n) and cluster counts of every entity of one
+ * side of one block; samples are S x R x K as for orc_mm.  Returns the total
+ * number of clusters. */
+int64_t orc_lmeans(int64_t R, int32_t K, int32_t S, const double *samples, double lam_scale, int32_t cmax,
+                   int32_t maxit, int32_t *labels, int32_t *nclust)
+{
+    int64_t total = 0;
+    const double **xs = (const double **)malloc(sizeof(double *) * (size_t)S);
+    double *cent = (double *)malloc(sizeof(double) * (size_t)cmax * K);
+    int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * (size_t)cmax);
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)S);
+    for (int64_t n = 0; n < R; ++n) {
+        for (int q = 0; q < S; ++q)
+            xs[q] = samples + ((int64_t)q * R + n) * K;
+        nclust[n] = orc_lmeans_one(K, S, xs, lam_scale, cmax, maxit, labels + n * S, cent, cnt, prev);
+        total += nclust[n];
+    }
+    free(xs); free(cent); free(cnt); free(prev);
+    return total;
+}
+
+/* Moment matching (as orc_mm) of the samples q of entity n with
+ * labels[n * S + q] == which[n] (which[n] < 0: every sample), in sample
+ * order; at least two must be selected.  count[n] = selected samples, logdet[n]
+ * = log det Lambda_hat.  Returns the number of rows that took the ridge
+ * (selected count <= K, or the factorisation failed). */
+int64_t orc_mm_sel(int64_t R, int32_t K, int32_t S, const double *samples, const int32_t *labels,
+                   const int32_t *which, double *mu, double *Lam, double *logdet, int32_t *count)
+{
+    int64_t ridged = 0;
+    const size_t KK = (size_t)K * K;
+    double *Sig = (double *)malloc(sizeof(double) * KK);
+    double *L = (double *)malloc(sizeof(double) * KK);
+    for (int64_t n = 0; n < R; ++n) {
+        double *mn = mu + n * K;
+        int m = 0;
+        for (int q = 0; q < S; ++q)
+            m += which[n] < 0 || labels[n * S + q] == which[n];
+        count[n] = m;
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < S; ++q)
+                if (which[n] < 0 || labels[n * S + q] == which[n])
+                    s += samples[((int64_t)q * R + n) * K + k];
+            mn[k] = s / (double)m;
+        }
+        memset(Sig, 0, sizeof(double) * KK);
+        for (int q = 0; q < S; ++q) {
+            if (!(which[n] < 0 || labels[n * S + q] == which[n]))
+                continue;
+            const double *x = samples + ((int64_t)q * R + n) * K;
+            for (int a = 0; a < K; ++a)
+                for (int b = 0; b < K; ++b)
+                    Sig[a * K + b] += (x[a] - mn[a]) * (x[b] - mn[b]);
+        }
+        for (size_t p = 0; p < KK; ++p)
+            Sig[p] /= (double)(m - 1);
+        int need_ridge = (m <= K) || (orc_chol(K, Sig, L) != 0);
+        if (need_ridge) {
+            double tr = 0.0;
+            for (int k = 0; k < K; ++k)
+                tr += Sig[k * K + k];
+            const double delta = 1e-6 * tr / (double)K + 1e-300;
+            for (int k = 0; k < K; ++k)
+                Sig[k * K + k] += delta;
+            orc_chol(K, Sig, L);
+            ridged += 1;
+        }
+        double ld = 0.0;
+        for (int k = 0; k < K; ++k)
+            ld -= 2.0 * log(L[k * K + k]);
+        logdet[n] = ld;
+        orc_inverse_from_chol(K, L, Lam + n * KK);
+    }
+    free(Sig); free(L);
+    return ridged;
+}

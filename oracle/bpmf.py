@@ -19,6 +19,18 @@ TEST INFRASTRUCTURE ONLY (FP64).  Sweep order and readings:
   (t - burnin) % thin == 0.
 * Moment matching at the end of a stage (Sec. 4.1): per-row mean and inverse
   sample covariance (1/(S-1) normaliser, ridge when S <= K or not SPD).
+* Dominant mode and mixture approximations (Sec. 4.1; Sec. 5.1): each row's
+  kept samples are clustered by lambda-means (orc_lmeans, with its readings);
+  the dominant-mode fit is the moment matching of the largest cluster (lowest
+  index on ties; all samples when it has fewer than two); the mixture keeps the
+  `ncomp` largest clusters with at least two members (all samples as one
+  component when none has), weights proportional to their sizes, each
+  component moment-matched.  A mixture prior (Sec. 5.1, GMM prior Gibbs) is
+  applied per row and sweep as the component of largest pi_c N(x_n | mu_c,
+  Lambda_c^-1) at the row's current value (lowest index on ties); a side
+  propagated by a mixture starts at the mean of its largest component.  For
+  aggregation a mixture is pooled (Sec. 4.2, eq. marginal_mixture): mean
+  sum_c pi_c mu_c, covariance sum_c pi_c (Lambda_c^-1 + (mu_c - mu)(mu_c - mu)^T).
 * Aggregation (Sec. 4.2, eq. post_marg_aggregation and Algorithm 2): for the
   rows of row block i the base is block (i, 0) and the siblings are (i, j),
   j >= 1; for a column block j the base is (0, j) and the siblings (i, j),
@@ -45,7 +57,10 @@ def nw_scale_inverse(W0):
 class Oracle:
     def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
-                 seed=0, burnin=0, thin=1, nthreads=0):
+                 seed=0, burnin=0, thin=1, nthreads=0, approx="mm", lambda_scale=2.0, ncomp=3):
+        if approx not in ("mm", "dm", "gmm"):
+            raise ValueError("approx must be mm, dm or gmm")
+        self.approx, self.lambda_scale, self.ncomp = approx, float(lambda_scale), int(ncomp)
         self.N, self.D, self.K = int(N), int(D), int(K)
         self.I, self.J = int(I), int(J)
         self.seed = int(seed)
@@ -85,8 +100,12 @@ class Oracle:
             b, i, j = blk["b"], blk["i"], blk["j"]
             if blk["x_prop"]:
                 src = self.mm[i * self.J + 0]
-                blk["x_prior"] = (src["x_Lam"], src["x_mu"])
-                blk["X"] = src["x_mu"].copy()
+                if self.approx == "gmm":
+                    blk["x_prior"] = ("gmm", src["x_gmm"])
+                    blk["X"] = src["x_gmm"]["mu"][:, 0].copy()
+                else:
+                    blk["x_prior"] = (src["x_Lam"], src["x_mu"])
+                    blk["X"] = src["x_mu"].copy()
             else:
                 blk["x_prior"] = None
                 X = np.zeros((blk["R"], K))
@@ -94,8 +113,12 @@ class Oracle:
                 blk["X"] = X
             if blk["w_prop"]:
                 src = self.mm[0 * self.J + j]
-                blk["w_prior"] = (src["w_Lam"], src["w_mu"])
-                blk["W"] = src["w_mu"].copy()
+                if self.approx == "gmm":
+                    blk["w_prior"] = ("gmm", src["w_gmm"])
+                    blk["W"] = src["w_gmm"]["mu"][:, 0].copy()
+                else:
+                    blk["w_prior"] = (src["w_Lam"], src["w_mu"])
+                    blk["W"] = src["w_mu"].copy()
             else:
                 blk["w_prior"] = None
                 W = np.zeros((blk["C"], K))
@@ -126,7 +149,14 @@ class Oracle:
         else:
             n, ptr_, idx, val = blk["C"], blk["csc_ptr"], blk["csc_idx"], blk["csc_val"]
             other, prop, hyp, purpose, key = blk["X"], blk["w_prior"], blk["hw"], "COL", "W"
-        if prop is not None:
+        if prop is not None and isinstance(prop[0], str):
+            choice = gmm_choice(prop[1], blk[key])
+            blk[key + "_choice"] = choice
+            rows = np.arange(n)
+            P = np.ascontiguousarray(prop[1]["Lam"][rows, choice])
+            m = np.ascontiguousarray(prop[1]["mu"][rows, choice])
+            per_row = 1
+        elif prop is not None:
             P = np.ascontiguousarray(prop[0])
             m = np.ascontiguousarray(prop[1])
             per_row = 1
@@ -205,7 +235,14 @@ class Oracle:
             R = smp.shape[1]
             mu = np.zeros((R, self.K))
             Lam = np.zeros((R, self.K, self.K))
-            if S >= 2:
+            if S >= 2 and self.approx != "mm":
+                fit = self.cluster_fit(smp)
+                ridged += fit.pop("ridged")
+                mu, Lam = fit.pop("mu"), fit.pop("Lam")
+                out[side + "_labels"] = fit.pop("labels")
+                if self.approx == "gmm":
+                    out[side + "_gmm"] = dict(pi=fit["pi"], mu=fit["cmu"], Lam=fit["cLam"], logdet=fit["logdet"])
+            elif S >= 2:
                 ridged += native.lib().orc_mm(R, self.K, S, ptr(smp), ptr(mu), ptr(Lam))
             else:
                 mu[:] = smp[0]
@@ -214,6 +251,55 @@ class Oracle:
             out[side + "_Lam"] = Lam
         out["ridged"] = ridged
         return out
+
+    def cluster_fit(self, smp):
+        """Dominant-mode or mixture fit of one side from its samples (S, R, K)."""
+        S, R, K = smp.shape
+        lab = np.zeros((R, S), dtype=np.int32)
+        ncl = np.zeros(R, dtype=np.int32)
+        native.lib().orc_lmeans(R, K, S, ptr(smp), self.lambda_scale, LMEANS_CMAX, LMEANS_MAXIT,
+                                ptr(lab), ptr(ncl))
+        sizes = np.zeros((R, LMEANS_CMAX), dtype=np.int64)
+        for q in range(S):
+            sizes[np.arange(R), lab[:, q]] += 1
+        # clusters by decreasing size, lower index first on ties
+        order = np.argsort(-sizes, axis=1, kind="stable")
+        C = 1 if self.approx == "dm" else self.ncomp
+        which = np.full((R, C), -2, dtype=np.int32)          # -2: no component
+        for c in range(C):
+            cid = order[:, c]
+            ok = sizes[np.arange(R), cid] >= 2
+            which[ok, c] = cid[ok]
+        none = which[:, 0] == -2
+        which[none, 0] = -1                                  # every sample
+        cnt_sel = np.zeros((R, C), dtype=np.int32)
+        mu = np.zeros((R, C, K))
+        Lam = np.zeros((R, C, K, K))
+        logdet = np.zeros((R, C))
+        ridged = 0
+        for c in range(C):
+            has = which[:, c] != -2
+            w = np.where(has, which[:, c], -1).astype(np.int32)
+            m = np.zeros((R, K))
+            L = np.zeros((R, K, K))
+            ld = np.zeros(R)
+            cn = np.zeros(R, dtype=np.int32)
+            rid = native.lib().orc_mm_sel(R, K, S, ptr(smp), ptr(lab), ptr(w), ptr(m), ptr(L), ptr(ld), ptr(cn))
+            if c == 0:
+                ridged += rid
+            mu[:, c], Lam[:, c], logdet[:, c], cnt_sel[:, c] = m, L, ld, np.where(has, cn, 0)
+        if self.approx == "dm":
+            return dict(mu=mu[:, 0], Lam=Lam[:, 0], labels=lab, ridged=ridged)
+        pi = cnt_sel / cnt_sel.sum(1, keepdims=True)
+        # pooled moments for aggregation (eq. marginal_mixture)
+        mp = np.einsum("nc,nck->nk", pi, mu)
+        Sig = np.zeros((R, K, K))
+        for c in range(C):
+            dm = mu[:, c] - mp
+            Sc = np.linalg.inv(Lam[:, c])
+            Sig += pi[:, c, None, None] * (Sc + dm[:, :, None] * dm[:, None, :])
+        return dict(mu=mp, Lam=np.linalg.inv(Sig), labels=lab, ridged=ridged,
+                    pi=pi, cmu=mu, cLam=Lam, logdet=logdet)
 
     def run_stage(self, s, nsweeps):
         self.begin_stage(s)
@@ -269,6 +355,29 @@ class Oracle:
             b = min(row.size, a + step)
             out[a:b] = self.ybar + np.einsum("qk,qk->q", mx[row[a:b]], mw[col[a:b]])
         return out
+
+
+LMEANS_CMAX = 16      # clusters per row at most (lambda-means reading)
+LMEANS_MAXIT = 32     # lambda-means rounds at most
+
+
+def gmm_choice(g, X):
+    """Per row, the component c of largest log pi_c + log det(Lambda_c) / 2
+    - (x - mu_c)^T Lambda_c (x - mu_c) / 2 at the current value x (the common
+    constant of the Gaussian densities cancels); components with pi_c = 0 are
+    absent; the lowest index wins a tie."""
+    R, C, K = g["mu"].shape
+    best = np.zeros(R, dtype=np.int64)
+    bval = np.full(R, -np.inf)
+    for c in range(C):
+        d = X - g["mu"][:, c]
+        q = np.einsum("nk,nkl,nl->n", d, g["Lam"][:, c], d)
+        v = np.where(g["pi"][:, c] > 0, np.log(np.maximum(g["pi"][:, c], 1e-300)) + 0.5 * g["logdet"][:, c] - 0.5 * q,
+                     -np.inf)
+        take = v > bval
+        best[take] = c
+        bval[take] = v[take]
+    return best
 
 
 def aggregate_side(mu_b, Lam_b, mus, Lams, K, lam_out=None):

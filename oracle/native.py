@@ -69,6 +69,10 @@ def lib():
     L.orc_nw_draw.restype = ctypes.c_int
     L.orc_mm.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp]
     L.orc_mm.restype = _i64
+    L.orc_lmeans.argtypes = [_i64, _i32, _i32, _vp, _d, _i32, _i32, _vp, _vp]
+    L.orc_lmeans.restype = _i64
+    L.orc_mm_sel.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.orc_mm_sel.restype = _i64
     _lib = L
     return L
 
