@@ -18,6 +18,7 @@ Prints one JSON line.  `--gpus N` with N > 1 is not supported (one GPU).
 """
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import sys
@@ -380,41 +381,41 @@ TABLE4_SIM_SECONDS_1X1 = 118124.0      # the paper's 1x1 run (R, one node), decr
 
 def paper_sim():
     """Test RMSE and wall-clock of full PP chains on the paper's simulated data
-    (K = 5, tau = 1 fixed, 1200 sweeps, 800 burn-in, thin 2), batched BF16."""
+    (K = 5, tau = 1 fixed, 1200 sweeps, 800 burn-in, thin 2), batched BF16,
+    under each approximation (moment matching, dominant mode, mixture)."""
     import torch
     import synth
     from paper_1703_00734_amd import BMF
     out = {"metric": "test RMSE and chain wall-clock, paper's simulated workload", "runs": []}
-    for missing in ("mar", "structured"):
-        d = synth.simulated(1, missing)
-        for IJ in (1, 3, 5, 10, 30):
-            for order in ("decreasing", "random"):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                g = BMF(d["N"], d["D"], 5, d["row"], d["col"], d["val"], I=IJ, J=IJ, order=order,
-                        sample_tau=False, tau_fixed=1.0, seed=101, burnin=800, thin=2, max_kept=200,
-                        precision="bf16", batched=True)
-                stage_s = {}
-                for s in (1, 2, 3):
-                    ts = time.perf_counter()
-                    g.pp_stage(s, 1200)
-                    torch.cuda.synchronize()
-                    stage_s[s] = time.perf_counter() - ts
-                ta = time.perf_counter()
-                g.aggregate()
-                torch.cuda.synchronize()
-                agg_s = time.perf_counter() - ta
-                wall = time.perf_counter() - t0
-                p = g.predict(d["test_row"], d["test_col"])
-                g.close()
-                rmse = float(np.sqrt(np.mean((p.astype(np.float64) - d["test_val"]) ** 2)))
-                r = dict(missing=missing, partition="%dx%d" % (IJ, IJ), order=order, rmse=rmse,
-                         chain_wall_s=wall, stage_s=stage_s, aggregate_s=agg_s,
-                         train_entries=int(d["row"].size))
-                if missing == "mar":
-                    r["paper_rmse"] = TABLE4_SIM[IJ][0 if order == "decreasing" else 1]
-                out["runs"].append(r)
-                say("sim %s %dx%d %s: rmse %.5f, %.2f s" % (missing, IJ, IJ, order, rmse, wall))
+    data = {m: synth.simulated(1, m) for m in ("mar", "structured")}
+    for missing, IJ, order, approx in itertools.product(("mar", "structured"), (1, 3, 5, 10, 30),
+                                                        ("decreasing", "random"), ("mm", "dm", "gmm")):
+        d = data[missing]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = BMF(d["N"], d["D"], 5, d["row"], d["col"], d["val"], I=IJ, J=IJ, order=order,
+                sample_tau=False, tau_fixed=1.0, seed=101, burnin=800, thin=2, max_kept=200,
+                precision="bf16", batched=True, approx=approx)
+        stage_s = {}
+        for s in (1, 2, 3):
+            ts = time.perf_counter()
+            g.pp_stage(s, 1200)
+            torch.cuda.synchronize()
+            stage_s[s] = time.perf_counter() - ts
+        ta = time.perf_counter()
+        g.aggregate()
+        torch.cuda.synchronize()
+        agg_s = time.perf_counter() - ta
+        wall = time.perf_counter() - t0
+        p = g.predict(d["test_row"], d["test_col"])
+        g.close()
+        rmse = float(np.sqrt(np.mean((p.astype(np.float64) - d["test_val"]) ** 2)))
+        r = dict(missing=missing, partition="%dx%d" % (IJ, IJ), order=order, approx=approx, rmse=rmse,
+                 chain_wall_s=wall, stage_s=stage_s, aggregate_s=agg_s, train_entries=int(d["row"].size))
+        if missing == "mar":
+            r["paper_rmse"] = TABLE4_SIM[IJ][0 if order == "decreasing" else 1]
+        out["runs"].append(r)
+        say("sim %s %dx%d %s %s: rmse %.5f, %.2f s" % (missing, IJ, IJ, order, approx, rmse, wall))
     out["paper_1x1_seconds"] = TABLE4_SIM_SECONDS_1X1
     print(json.dumps(out))
 

@@ -89,6 +89,31 @@ typedef enum {
     BMF_ORDER_DECREASING = 2
 } bmf_order;
 
+/* Parametric approximation of each stage's subset posteriors, propagated as
+ * the next stages' priors and aggregated by Algorithm 2 (Sec. 4.1; Sec. 5.1):
+ *   MM  -- moment matching: per row the mean and inverse covariance of the
+ *          kept samples;
+ *   DM  -- dominant mode: the kept samples of each row are clustered by
+ *          lambda-means and the largest cluster is moment-matched;
+ *   GMM -- mixture: the ncomp largest clusters with at least two members, each
+ *          moment-matched, weights proportional to their sizes; a row under a
+ *          mixture prior takes, every sweep, the component of largest
+ *          responsibility pi_c N(x_n | mu_c, Lambda_c^-1) at its current value
+ *          as its prior (Sec. 5.1), and aggregation uses the pooled moments
+ *          (Sec. 4.2, eq. marginal_mixture).
+ * lambda-means is the DP-means iteration: in sample order each sample joins its
+ * nearest centre, or opens a new cluster when that centre is farther than
+ * lambda (at most 16 clusters); centres move to their members' means; until the
+ * assignment repeats (at most 32 rounds), starting from one cluster at the
+ * mean.  lambda^2 = lambda_scale^2 times half the mean squared step between
+ * successive kept samples of the row.  DM and GMM need K <= 32 and
+ * max_kept <= 256. */
+typedef enum {
+    BMF_APPROX_MM = 0,
+    BMF_APPROX_DM = 1,
+    BMF_APPROX_GMM = 2
+} bmf_approx;
+
 typedef struct {
     /* data: COO training set, host memory, 0-based, no duplicate (row, col).
      * The largest row or column part times the factor row stride in bytes
@@ -132,11 +157,16 @@ typedef struct {
     void *workspace;             /* device memory owned by the caller, or NULL */
     size_t workspace_bytes;      /* its size; see bmf_workspace_size */
     void *stream;                /* hipStream_t, NULL = default stream */
+    int32_t approx;              /* bmf_approx (0 = moment matching) */
+    double lambda_scale;         /* lambda-means scale, > 0 (0 => 2) */
+    int32_t ncomp;               /* mixture components, 1..4 (0 => 3) */
 } bmf_config;
 
 /* Fill *cfg with defaults: K = 10, I = J = 1, beta0 = 2, nu0 = K, tau Gamma(1,1)
  * sampled, tau_fixed = 1, burnin = 0, thin = 1, max_kept = 1, FP32, batched,
- * lane_nnz = 0 (autotuned), pivot_theta = 2^-10.  Data pointers are NULL. */
+ * lane_nnz = 0 (autotuned), pivot_theta = 2^-10, moment matching
+ * (lambda_scale = 2, ncomp = 3 for the other approximations).  Data pointers
+ * are NULL. */
 bmf_status bmf_config_defaults(bmf_config *cfg);
 
 /* Bytes of device workspace bmf_init needs for cfg (host only, touches no
@@ -249,6 +279,20 @@ bmf_status bmf_get_draw(bmf_ctx *c, int32_t b, int32_t side, double *x);
  * after its stage has been finalised: mu (n x K) and Lambda (n x K x K, full
  * symmetric).  Either output may be NULL. */
 bmf_status bmf_get_mm(bmf_ctx *c, int32_t b, int32_t side, double *mu, double *Lam);
+
+/* Cluster label of every kept sample of every row of block b (side 0 = X rows,
+ * 1 = W columns) after its stage has been finalised under the dominant-mode or
+ * mixture approximation (Sec. 5.1, lambda-means): labels (n x S, host), S the
+ * number of samples the stage kept; labels are 0-based in the order the
+ * clusters were opened.  BMF_ESTATE under moment matching. */
+bmf_status bmf_get_clusters(bmf_ctx *c, int32_t b, int32_t side, int32_t *labels);
+
+/* Component comp (0-based, by decreasing size) of the per-row fit of block b
+ * under the dominant-mode (comp 0 only) or mixture approximation: weights pi
+ * (n; 0 for a row with fewer components), means mu (n x K), precisions Lambda
+ * (n x K x K), log det Lambda (n).  Any output may be NULL. */
+bmf_status bmf_get_component(bmf_ctx *c, int32_t b, int32_t side, int32_t comp, double *pi, double *mu,
+                             double *Lam, double *logdet);
 
 /* Aggregated per-row posterior means (after bmf_predict or bmf_aggregate):
  * side 0: mu_x (N x K) in original row ids; side 1: mu_w (D x K). */

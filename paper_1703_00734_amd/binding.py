@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libbmf.so")
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 ORDER = {"given": 0, "random": 1, "decreasing": 2}
 STEP = {"rows": 0, "cols": 1, "hyper_x": 2, "hyper_w": 3, "tau": 4}
+APPROX = {"mm": 0, "dm": 1, "gmm": 2}
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -37,6 +38,7 @@ class bmf_config(ctypes.Structure):
         ("lane_nnz", _i32),
         ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
         ("stream", _vp),
+        ("approx", _i32), ("lambda_scale", _d), ("ncomp", _i32),
     ]
 
 
@@ -79,6 +81,8 @@ def load():
         "bmf_set_state": [_vp, _i32, _vp, _vp, _vp, _vp],
         "bmf_step": [_vp, _i32, _i32, _i64],
         "bmf_get_mm": [_vp, _i32, _i32, _vp, _vp],
+        "bmf_get_clusters": [_vp, _i32, _i32, _vp],
+        "bmf_get_component": [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
         "bmf_get_draw": [_vp, _i32, _i32, _vp],
         "bmf_aggregate": [_vp],
         "bmf_get_aggregate": [_vp, _i32, _vp],
@@ -116,7 +120,8 @@ def exported_symbols():
             "bmf_get_block_csr", "bmf_get_state", "bmf_set_state", "bmf_step", "bmf_get_draw", "bmf_get_mm",
             "bmf_aggregate", "bmf_get_aggregate", "bmf_get_stats", "bmf_enable_timing",
             "bmf_kernel_times", "bmf_get_schedule", "bmf_stage_work", "bmf_get_sample",
-            "bmf_set_progress", "bmf_save_state", "bmf_load_state", "bmf_predict_noalloc"]
+            "bmf_set_progress", "bmf_save_state", "bmf_load_state", "bmf_predict_noalloc", "bmf_get_clusters",
+            "bmf_get_component"]
 
 
 # int32_t (*bmf_progress_fn)(void *user, int32_t stage, int64_t sweep)
@@ -134,7 +139,7 @@ class BMF:
     def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
                  seed=0, burnin=0, thin=1, max_kept=1, precision="fp32", pivot_theta=0.0,
-                 batched=True, lane_nnz=0, device=True, stream=None):
+                 batched=True, lane_nnz=0, device=True, stream=None, approx="mm", lambda_scale=2.0, ncomp=3):
         if device:
             # torch's HIP runtime is initialised before the library's is loaded
             import torch
@@ -167,6 +172,9 @@ class BMF:
         c.pivot_theta = float(pivot_theta)
         c.batched = 1 if batched else 0
         c.lane_nnz = int(lane_nnz)
+        c.approx = APPROX[approx] if isinstance(approx, str) else int(approx)
+        c.lambda_scale = float(lambda_scale)
+        c.ncomp = int(ncomp)
         self.cfg = c
         self.ctx = _vp()
         self.workspace = None
@@ -303,6 +311,24 @@ class BMF:
         Lam = np.empty((n, self.K, self.K))
         self._check(self.L.bmf_get_mm(self.ctx, b, side, _ptr(mu), _ptr(Lam)))
         return mu, Lam
+
+    def get_clusters(self, b, side, S):
+        """Cluster labels (n x S) of the S samples the block's stage kept."""
+        info = self.block_info(b)
+        n = info["R"] if side == 0 else info["C"]
+        lab = np.empty((n, S), dtype=np.int32)
+        self._check(self.L.bmf_get_clusters(self.ctx, b, side, _ptr(lab)))
+        return lab
+
+    def get_component(self, b, side, comp):
+        info = self.block_info(b)
+        n = info["R"] if side == 0 else info["C"]
+        pi = np.empty(n)
+        mu = np.empty((n, self.K))
+        Lam = np.empty((n, self.K, self.K))
+        ld = np.empty(n)
+        self._check(self.L.bmf_get_component(self.ctx, b, side, comp, _ptr(pi), _ptr(mu), _ptr(Lam), _ptr(ld)))
+        return dict(pi=pi, mu=mu, Lam=Lam, logdet=ld)
 
     def aggregate(self):
         self._check(self.L.bmf_aggregate(self.ctx))

@@ -35,9 +35,10 @@ enum Counter { kFbRow = 0, kFbCol = 1, kFbTotal = 2, kNonPD = 3, kRidged = 4, kC
                kNumCounters = 16 };
 
 // Kernel classes for the optional per-launch timing.
-enum KClass { kKRows = 0, kKCols, kKGram, kKFallback, kKSse, kKStats, kKReduce, kKHyper, kKInit, kKMM, kKAgg, kKPredict, kKFill, kNumK };
+enum KClass { kKRows = 0, kKCols, kKGram, kKFallback, kKSse, kKStats, kKReduce, kKHyper, kKInit, kKMM, kKAgg, kKPredict, kKFill, kKPick, kNumK };
 const char *kKNames[kNumK] = {"update_rows", "update_cols", "gram_segments", "update_fallback_fp64", "sse", "nw_stats", "reduce",
-                              "hyper_draws", "init", "moment_match", "aggregate", "predict", "bookkeeping"};
+                              "hyper_draws", "init", "moment_match", "aggregate", "predict", "bookkeeping",
+                              "mixture_pick"};
 
 int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -54,13 +55,18 @@ struct Layout {
         W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
         m_items, m_items2, m_stats, m_hyper, m_mmout, pfac, m_pfout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
-        p_out, rowpos, colpos, m_gitems, m_gstart, total;
+        p_out, rowpos, colpos, m_gitems, m_gstart, lab, which, aux, gmm, m_labptr, m_auxptr, m_gmmout, m_gsides,
+        m_pitems, total;
+    int32_t ncomp = 1;        // components per row of the propagated fit (mixture: ncomp, else 1)
     int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
     bool mfma = false;
 };
 
 // Offset (doubles) of the packed prior row inside a hyperparameter slot.
 int64_t kHyPacked(const Layout &L) { return (int64_t)L.K * L.K + 2 * L.K; }
+
+// Components kept per row: the mixture's ncomp (0 => 3), one otherwise.
+int32_t ncomp_of(const bmf_config &c) { return c.approx == BMF_APPROX_GMM ? (c.ncomp ? c.ncomp : 3) : 1; }
 
 bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L = Layout();
@@ -126,7 +132,9 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     // prior factors of the moment-matched rows that seed later stages (the rows
     // of blocks (i, 0) and the columns of blocks (0, j): N + D rows), for the
     // empty-entity path of FP32/BF16 passes on the wavefront kernels
-    if (!fp64 && L.kc >= 32 && L.nb > 1) L.pfrow = (int32_t)align_up(c.K * (c.K + 1) / 2 + 1, 4);
+    // (not under a mixture prior: a row's prior changes from sweep to sweep)
+    if (!fp64 && L.kc >= 32 && L.nb > 1 && c.approx != BMF_APPROX_GMM)
+        L.pfrow = (int32_t)align_up(c.K * (c.K + 1) / 2 + 1, 4);
     L.pfac = take(4 * ((int64_t)c.N + c.D) * L.pfrow);
     L.agg_x = take(8 * c.N * c.K);
     L.agg_w = take(8 * c.D * c.K);
@@ -165,6 +173,24 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.m_gstart = take(4 * (L.n_items_cap + 8));
     L.rowpos = take(8 * c.N);
     L.colpos = take(8 * c.D);
+    // dominant mode / mixture: cluster labels of every row's kept samples, the
+    // chosen clusters of the stage's items, per component plane the (weight,
+    // log det) pairs and (mixture) the component rows, plus the per-side
+    // pointer tables and the mixture-prior pick lists
+    {
+        const bool clus = c.approx != BMF_APPROX_MM;
+        const int64_t Etot = L.E_r + L.E_c;
+        L.ncomp = ncomp_of(c);
+        L.lab = take(clus ? Etot * c.max_kept : 0);
+        L.which = take(clus ? (L.Emax + 8) * kMaxComp : 0);
+        L.aux = take(clus ? 8 * 2 * (int64_t)L.ncomp * Etot : 0);
+        L.gmm = take(c.approx == BMF_APPROX_GMM ? 8 * (int64_t)L.ncomp * Etot * L.prow : 0);
+        L.m_labptr = take(sizeof(void *) * 2 * L.nb);
+        L.m_auxptr = take(sizeof(void *) * kMaxComp * 2 * L.nb);
+        L.m_gmmout = take(sizeof(void *) * kMaxComp * 2 * L.nb);
+        L.m_gsides = take(sizeof(GmmSide) * 2 * L.nb);
+        L.m_pitems = take(c.approx == BMF_APPROX_GMM ? sizeof(int2) * (L.Emax + 8) : 0);
+    }
     L.total = off;
     return true;
 }
@@ -218,6 +244,9 @@ struct StageLists {
     std::vector<int64_t> sse_tile_begin;            // SSE tiles per block (== row tiles grouped)
     int64_t row_ents = 0, col_ents = 0;
     int64_t row_updates = 0, ratings = 0;
+    // mixture priors: the propagated sides and their (side, entity) pick items
+    std::vector<GmmSide> gsides;
+    std::vector<int2> pitems;
 };
 
 }  // namespace
@@ -349,6 +378,7 @@ uint64_t data_fingerprint(const bmf_config &c) {
     m.val(c.N); m.val(c.D); m.val(c.K); m.val(c.nnz); m.val(c.I); m.val(c.J); m.val(c.order);
     m.val(c.beta0); m.val(c.nu0); m.val(c.sample_tau); m.val(c.tau_a0); m.val(c.tau_b0); m.val(c.tau_fixed);
     m.val(c.seed); m.val(c.burnin); m.val(c.thin); m.val(c.max_kept); m.val(c.precision); m.val(c.pivot_theta);
+    m.val(c.approx); m.val(c.lambda_scale); m.val(ncomp_of(c));
     if (c.mu0) m.bytes(c.mu0, 8 * (size_t)c.K);
     if (c.W0) m.bytes(c.W0, 8 * (size_t)c.K * c.K);
     if (c.nnz > 0) {
@@ -383,6 +413,14 @@ bmf_status validate(const bmf_config *cfg, std::string &err) {
     if (c.precision < BMF_PREC_FP64 || c.precision > BMF_PREC_BF16) { err = "bad precision"; return BMF_EINVAL; }
     if (c.pivot_theta < 0.0 || c.pivot_theta >= 1.0) { err = "pivot_theta must be in [0, 1)"; return BMF_EINVAL; }
     if (c.lane_nnz < 0) { err = "lane_nnz must be >= 0"; return BMF_EINVAL; }
+    if (c.approx < BMF_APPROX_MM || c.approx > BMF_APPROX_GMM) { err = "bad approx"; return BMF_EINVAL; }
+    if (!(c.lambda_scale >= 0.0) || !std::isfinite(c.lambda_scale)) { err = "lambda_scale must be >= 0"; return BMF_EINVAL; }
+    if (c.ncomp < 0 || c.ncomp > kMaxComp) { err = "ncomp must be in 0..4"; return BMF_EINVAL; }
+    if (c.approx != BMF_APPROX_MM && c.K > 32) { err = "dominant-mode and mixture fits need K <= 32"; return BMF_EUNSUPPORTED; }
+    if (c.approx != BMF_APPROX_MM && c.max_kept > kLmMaxS) {
+        err = "dominant-mode and mixture fits keep at most 256 samples per stage";
+        return BMF_EUNSUPPORTED;
+    }
     {
         // the gather kernels address a gathered row by a 32-bit byte offset from
         // its block's first row: the largest part times the row stride must fit
@@ -503,6 +541,29 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         q.c2 = counter_word(b, kCol);
         q.c2_init = counter_word(b, kInitW);
         q.block = b;
+        if (c->cfg.approx == BMF_APPROX_GMM) {
+            // a mixture prior: each sweep picks a component per row into the
+            // side's own rows, which the update kernels read
+            double *gm = c->dev<double>(L.gmm);
+            double *ax = c->dev<double>(L.aux);
+            char *Xb = c->base + L.X, *Wb = c->base + L.W;
+            if (xp) {
+                const int64_t src = c->x_off[B.i * J + 0];
+                r.prior = mm + c->x_off[b] * L.prow;
+                GmmSide g{gm + src * L.prow, ax + src * 2, const_cast<double *>(r.prior),
+                          Xb + c->x_off[b] * L.ks_m * L.ss, (int32_t)B.R, 0};
+                for (int32_t e = 0; e < (int32_t)B.R; ++e) S.pitems.push_back(make_int2((int32_t)S.gsides.size(), e));
+                S.gsides.push_back(g);
+            }
+            if (wp) {
+                const int64_t src = L.E_r + c->w_off[0 * J + B.j];
+                q.prior = mm + (L.E_r + c->w_off[b]) * L.prow;
+                GmmSide g{gm + src * L.prow, ax + src * 2, const_cast<double *>(q.prior),
+                          Wb + c->w_off[b] * L.ks_m * L.ss, (int32_t)B.C, 0};
+                for (int32_t e = 0; e < (int32_t)B.C; ++e) S.pitems.push_back(make_int2((int32_t)S.gsides.size(), e));
+                S.gsides.push_back(g);
+            }
+        }
         S.sides[k] = r;
         S.sides[nbs + k] = q;
         if (pf && s < 3 && B.j == 0) S.pfout[k] = pf + pfx[B.i] * L.pfrow;
@@ -788,6 +849,31 @@ static bmf_status upload_stage(bmf_ctx *c) {
         outs[nbs + k] = c->dev<double>(L.mm) + (L.E_r + c->w_off[b]) * L.prow;
     }
     if ((st = upload(c, L.m_mmout, outs.data(), outs.size() * sizeof(double *)))) return st;
+    if (c->cfg.approx != BMF_APPROX_MM) {
+        const int64_t Etot = L.E_r + L.E_c;
+        std::vector<uint8_t *> labp(2 * nbs);
+        std::vector<double *> auxp(kMaxComp * 2 * nbs, nullptr), gmp(kMaxComp * 2 * nbs, nullptr);
+        for (int32_t k = 0; k < nbs; ++k) {
+            const int32_t b = S.blocks[k];
+            const int64_t e[2] = {c->x_off[b], L.E_r + c->w_off[b]};
+            for (int sd = 0; sd < 2; ++sd) {
+                const int32_t i = sd * nbs + k;
+                labp[i] = c->dev<uint8_t>(L.lab) + e[sd] * c->cfg.max_kept;
+                for (int32_t cc = 0; cc < L.ncomp; ++cc) {
+                    auxp[cc * 2 * nbs + i] = c->dev<double>(L.aux) + (cc * Etot + e[sd]) * 2;
+                    if (c->cfg.approx == BMF_APPROX_GMM)
+                        gmp[cc * 2 * nbs + i] = c->dev<double>(L.gmm) + (cc * Etot + e[sd]) * L.prow;
+                }
+            }
+        }
+        if ((st = upload(c, L.m_labptr, labp.data(), labp.size() * sizeof(void *)))) return st;
+        if ((st = upload(c, L.m_auxptr, auxp.data(), auxp.size() * sizeof(void *)))) return st;
+        if ((st = upload(c, L.m_gmmout, gmp.data(), gmp.size() * sizeof(void *)))) return st;
+        if ((int64_t)S.pitems.size() > L.Emax + 8) return fail(c, BMF_ENOMEM, "mixture pick list exceeds its space");
+        if ((st = upload(c, L.m_gsides, S.gsides.data(), S.gsides.size() * sizeof(GmmSide)))) return st;
+        if ((st = upload(c, L.m_pitems, S.pitems.data(), S.pitems.size() * sizeof(int2)))) return st;
+        HIPCHK(c, hipStreamSynchronize(c->stream));     // the host tables above are released next
+    }
     if ((st = upload(c, L.m_pfout, S.pfout.data(), S.pfout.size() * sizeof(float *)))) return st;
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return BMF_OK;
@@ -1083,9 +1169,30 @@ static bmf_status run_hyper(bmf_ctx *c, int32_t j0, int32_t j1, uint32_t t, bool
 
 // Enqueue one sweep of the active stage on c->ls: rows, columns, SSE, NW
 // statistics, hyperparameter and tau draws, then the sweep-state advance.
+// Mixture priors (Sec. 5.1): every row under a propagated mixture takes the
+// component of largest responsibility at its current value (force0: the
+// largest component, for the initial state) into its side's prior rows.
+static bmf_status run_gmm_pick(bmf_ctx *c, bool force0) {
+    if (c->cfg.approx != BMF_APPROX_GMM || c->S.pitems.empty()) return BMF_OK;
+    const Layout &L = c->L;
+    GmmPickArgs a{};
+    a.items = c->dev<int2>(L.m_pitems);
+    a.nitems = (int32_t)c->S.pitems.size();
+    a.gsides = c->dev<GmmSide>(L.m_gsides);
+    a.plane = (L.E_r + L.E_c) * L.prow;
+    a.aux_plane = 2 * (L.E_r + L.E_c);
+    a.ks_state = L.ks_m;
+    a.K = c->cfg.K;
+    a.prow = L.prow;
+    a.ncomp = L.ncomp;
+    a.force0 = force0 ? 1 : 0;
+    return timed(c, kKPick, [&] { return launch_gmm_pick(c->prec(), a, c->ls); });
+}
+
 static bmf_status enqueue_sweep(bmf_ctx *c) {
     StageLists &S = c->S;
     bmf_status st;
+    if ((st = run_gmm_pick(c, false))) return st;
     const int32_t nbs = (int32_t)S.blocks.size();
     // the column pass always evaluates the residual SSE of every block (the tau
     // statistic when tau is sampled; the training fit, bmf_get_stats, always)
@@ -1302,6 +1409,7 @@ static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
         if ((st = upload(c, L.tau + 8 * (int64_t)b, &tau0, 8))) return st;
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    if ((st = run_gmm_pick(c, true))) return st;      // mixture priors: the largest component to start
     if ((st = init_factors(c))) return st;
     if (c->reg() && c->cfg.lane_nnz == 0 && c->cfg.batched) {
         if ((st = autotune(c))) return st;
@@ -1341,8 +1449,59 @@ static bmf_status finalize_stage(bmf_ctx *c) {
     a.prow = L.prow;
     a.out = c->dev<double *>(L.m_mmout);
     a.ridged = c->dev<int32_t>(L.counters) + kRidged;
-    bmf_status st = timed(c, kKMM, [&] { return launch_mm(c->fp64() ? kP64 : kP32, a, c->ls); });
-    if (st) return st;
+    const int32_t sprec = c->fp64() ? kP64 : kP32;
+    bmf_status st;
+    if (c->cfg.approx == BMF_APPROX_MM) {
+        if ((st = timed(c, kKMM, [&] { return launch_mm(sprec, a, c->ls); }))) return st;
+    } else {
+        // lambda-means per row, then the dominant cluster's or each
+        // component's moment matching, then (mixture) the pooled moments
+        const int32_t nbs2 = 2 * (int32_t)S.blocks.size();
+        const int64_t Etot = L.E_r + L.E_c;
+        LmeansArgs la{};
+        la.items = a.items;
+        la.nitems = a.nitems;
+        la.sides = a.sides;
+        la.sample = a.sample;
+        la.slot_elems = a.slot_elems;
+        la.ks = a.ks;
+        la.S = a.S;
+        la.K = a.K;
+        la.lam_scale = c->cfg.lambda_scale;
+        la.ncomp = L.ncomp;
+        la.labels = c->dev<uint8_t *>(L.m_labptr);
+        la.maxS = c->cfg.max_kept;
+        la.which = c->dev<int8_t>(L.which);
+        la.aux = c->dev<double *>(L.m_auxptr);
+        la.aux_plane = 2 * Etot;
+        if ((st = timed(c, kKMM, [&] { return launch_lmeans(sprec, la, c->ls); }))) return st;
+        a.labels = la.labels;
+        a.which = la.which;
+        a.maxS = la.maxS;
+        const bool gmm = c->cfg.approx == BMF_APPROX_GMM;
+        for (int32_t cc = 0; cc < L.ncomp; ++cc) {
+            MmArgs m = a;
+            m.comp = cc;
+            m.aux = c->dev<double *>(L.m_auxptr) + (int64_t)cc * nbs2;
+            if (gmm) m.out = c->dev<double *>(L.m_gmmout) + (int64_t)cc * nbs2;
+            if ((st = timed(c, kKMM, [&] { return launch_mm(sprec, m, c->ls); }))) return st;
+        }
+        if (gmm) {
+            GmmPoolArgs g{};
+            g.items = a.items;
+            g.nitems = a.nitems;
+            g.which = la.which;
+            g.comp = c->dev<double *>(L.m_gmmout);
+            g.aux = c->dev<double *>(L.m_auxptr);
+            g.plane = Etot * L.prow;
+            g.aux_plane = 2 * Etot;
+            g.out = c->dev<double *>(L.m_mmout);
+            g.K = a.K;
+            g.prow = L.prow;
+            g.ncomp = L.ncomp;
+            if ((st = timed(c, kKMM, [&] { return launch_gmm_pool(g, c->ls); }))) return st;
+        }
+    }
     if (L.pfrow && c->stage < 3) {
         PfacArgs f{};
         f.items = a.items;
@@ -1396,6 +1555,9 @@ bmf_status bmf_config_defaults(bmf_config *cfg) {
     cfg->precision = BMF_PREC_FP32;
     cfg->pivot_theta = std::ldexp(1.0, -10);
     cfg->batched = 1;
+    cfg->approx = BMF_APPROX_MM;
+    cfg->lambda_scale = 2.0;
+    cfg->ncomp = 3;
     return BMF_OK;
 }
 
@@ -1440,6 +1602,8 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
         return st;
     }
     c->cfg = *cfg;
+    if (c->cfg.lambda_scale == 0.0) c->cfg.lambda_scale = 2.0;
+    c->cfg.ncomp = ncomp_of(*cfg);
     c->cfg.row = nullptr;
     c->cfg.col = nullptr;
     c->cfg.val = nullptr;
@@ -1910,6 +2074,8 @@ bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
     StageLists &S = c->S;
     const int32_t nbs = (int32_t)S.blocks.size();
     bmf_status st;
+    // mixture priors follow the current state, as at the start of a sweep
+    if ((which == 0 || which == 1) && (st = run_gmm_pick(c, false))) return st;
     switch (which) {
     case 0: st = run_pass(c, true, tt, c->base + c->L.probe, k, false); break;
     case 1: st = run_pass(c, false, tt, c->base + c->L.probe, k, false); break;
@@ -1994,6 +2160,59 @@ bmf_status bmf_get_mm(bmf_ctx *c, int32_t b, int32_t side, double *mu, double *L
                     Lam[(r * K + bb) * K + a] = row[q];
                 }
         }
+    }
+    return BMF_OK;
+}
+
+bmf_status bmf_get_clusters(bmf_ctx *c, int32_t b, int32_t side, int32_t *labels) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (c->cfg.approx == BMF_APPROX_MM) return fail(c, BMF_ESTATE, "moment matching keeps no clusters");
+    if (b < 0 || b >= (int32_t)c->plan.blocks.size() || (side != 0 && side != 1) || !labels)
+        return fail(c, BMF_EINVAL, "bad block, side or output");
+    const PlanBlock &B = c->plan.blocks[b];
+    if (B.stage > c->finalized) return fail(c, BMF_ESTATE, "the block's stage is not finalised");
+    const int32_t S = c->done_stages[B.stage];
+    const int64_t n = side == 0 ? B.R : B.C;
+    const int64_t e = side == 0 ? c->x_off[b] : c->L.E_r + c->w_off[b];
+    std::vector<uint8_t> buf((size_t)(n * c->cfg.max_kept));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(buf.data(), c->base + c->L.lab + e * c->cfg.max_kept, buf.size(), hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < n; ++r)
+        for (int32_t q = 0; q < S; ++q) labels[r * S + q] = buf[(size_t)(r * c->cfg.max_kept + q)];
+    return BMF_OK;
+}
+
+bmf_status bmf_get_component(bmf_ctx *c, int32_t b, int32_t side, int32_t comp, double *pi, double *mu,
+                             double *Lam, double *logdet) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device) return fail(c, BMF_ESTATE, "context has no device state");
+    if (c->cfg.approx == BMF_APPROX_MM) return fail(c, BMF_ESTATE, "moment matching keeps no components");
+    const Layout &L = c->L;
+    if (b < 0 || b >= (int32_t)c->plan.blocks.size() || (side != 0 && side != 1) || comp < 0 || comp >= L.ncomp)
+        return fail(c, BMF_EINVAL, "bad block, side or component");
+    const PlanBlock &B = c->plan.blocks[b];
+    if (B.stage > c->finalized) return fail(c, BMF_ESTATE, "the block's stage is not finalised");
+    const int32_t K = c->cfg.K, kk2 = K * (K + 1) / 2;
+    const int64_t n = side == 0 ? B.R : B.C;
+    const int64_t e = side == 0 ? c->x_off[b] : L.E_r + c->w_off[b];
+    const int64_t Etot = L.E_r + L.E_c;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> ax((size_t)(2 * n));
+    HIPCHK(c, hipMemcpy(ax.data(), c->base + L.aux + (comp * Etot + e) * 2 * 8, ax.size() * 8, hipMemcpyDeviceToHost));
+    // the component's rows: the mixture planes, or (dominant mode) the fitted rows themselves
+    const int64_t roff = c->cfg.approx == BMF_APPROX_GMM ? L.gmm + (comp * Etot + e) * L.prow * 8 : L.mm + e * L.prow * 8;
+    std::vector<double> rows((size_t)(n * L.prow));
+    HIPCHK(c, hipMemcpy(rows.data(), c->base + roff, rows.size() * 8, hipMemcpyDeviceToHost));
+    for (int64_t r = 0; r < n; ++r) {
+        const double *row = rows.data() + r * L.prow;
+        if (pi) pi[r] = ax[(size_t)(2 * r)];
+        if (logdet) logdet[r] = ax[(size_t)(2 * r + 1)];
+        if (mu)
+            for (int k = 0; k < K; ++k) mu[r * K + k] = row[kk2 + K + k];
+        if (Lam)
+            for (int i = 0; i < K; ++i)
+                for (int j = 0; j < K; ++j) Lam[(r * K + i) * K + j] = row[i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i];
     }
     return BMF_OK;
 }
@@ -2197,6 +2416,23 @@ std::vector<Span> ckpt_spans(const bmf_ctx *c, int32_t stage, int32_t finalized,
         v.push_back({L.mm + (L.E_r + c->w_off[b]) * L.prow * 8, B.C * L.prow * 8});
     }
     if (L.pfrow) v.push_back({L.pfac, 4 * (P.N + P.D) * (int64_t)L.pfrow});
+    if (c->cfg.approx != BMF_APPROX_MM) {
+        // the fits of finalised blocks: labels, (weight, log det) planes, mixture components
+        const int64_t Etot = L.E_r + L.E_c;
+        for (int32_t b = 0; b < (int32_t)P.blocks.size(); ++b) {
+            const PlanBlock &B = P.blocks[b];
+            if (B.stage > finalized) continue;
+            const int64_t e[2] = {c->x_off[b], L.E_r + c->w_off[b]}, n[2] = {B.R, B.C};
+            for (int sd = 0; sd < 2; ++sd) {
+                v.push_back({L.lab + e[sd] * c->cfg.max_kept, n[sd] * c->cfg.max_kept});
+                for (int32_t cc = 0; cc < L.ncomp; ++cc) {
+                    v.push_back({L.aux + (cc * Etot + e[sd]) * 2 * 8, n[sd] * 2 * 8});
+                    if (c->cfg.approx == BMF_APPROX_GMM)
+                        v.push_back({L.gmm + (cc * Etot + e[sd]) * L.prow * 8, n[sd] * L.prow * 8});
+                }
+            }
+        }
+    }
     return v;
 }
 

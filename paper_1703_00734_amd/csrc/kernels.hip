@@ -1377,6 +1377,7 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         Tacc *hh = sh + h * KP, *hr = shraw + h * KP, *zz = sz + h * KP, *iv = sinv + h * KP;
 
         __syncthreads();                             // the previous pair is done with the LDS
+        Tacc hs = (Tacc)0;
         // the entity's rows (zero beyond K) and values, staged in its A
         for (int q = r; q < nc * KP; q += 32) {
             const int e = q / KP, k = q - e * KP;
@@ -1388,7 +1389,6 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         Tacc g[KP];
 #pragma unroll
         for (int c = 0; c < KP; ++c) g[c] = (Tacc)0;
-        Tacc hs = (Tacc)0;
         for (int e = 0; e < nc; ++e) {
             const Tacc *we = A + e * KP;
             const Tacc wr = we[r];
@@ -2492,29 +2492,46 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
     for (int pit = blockIdx.x; G * pit < a.nitems; pit += gridDim.x) {
         const int it = G * pit + h;
         const bool valid = it < a.nitems;           // uniform per entity
-        const int2 item = a.items[valid ? it : G * pit];
+        const int iq = valid ? it : G * pit;
+        const int2 item = a.items[iq];
         const SideDesc &sd = a.sides[item.x];
         const int n = item.y;
         const Ts *smp = reinterpret_cast<const Ts *>(a.sample) + (sd.sample_off + n) * a.ks;
-        double *out = a.out[item.x] + (int64_t)n * a.prow;
+        // the samples taken (every one, or one cluster's)
+        int w = -1;
+        const uint8_t *lab = nullptr;
+        if (a.labels) {
+            w = a.which[(int64_t)iq * kMaxComp + a.comp];
+            lab = a.labels[item.x] + (int64_t)n * a.maxS;
+        }
+        const bool has = w != -2;
+        int m = S;
+        if (w >= 0) {
+            m = 0;
+            for (int q = 0; q < S; ++q) m += lab[q] == w;
+        }
         double mu = 0.0;
-        if (r < K) {
+        if (r < K && has) {
             double s = 0.0;
-            for (int q = 0; q < S; ++q) s += (double)smp[(int64_t)q * a.slot_elems + r];
-            mu = s / (double)S;
+            for (int q = 0; q < S; ++q)
+                if (w < 0 || lab[q] == w) s += (double)smp[(int64_t)q * a.slot_elems + r];
+            mu = s / (double)m;
         }
         double row[KP];
 #pragma unroll
         for (int c = 0; c < KP; ++c) row[c] = 0.0;
-        bool ridge = S <= K;
+        bool ridge = m <= K;
+        double ld = 0.0;                            // log det Lambda_hat = -sum log pivots
         for (int pass = 0; pass < 2 && S >= 2; ++pass) {
 #pragma unroll
             for (int c = 0; c < KP; ++c) row[c] = 0.0;
             for (int t0 = 0; t0 < S; t0 += MC) {
                 const int nt = min(MC, S - t0);
                 __syncthreads();                    // the previous chunk is read
-                for (int t = 0; t < nt; ++t)
-                    xs[h][t * KP + r] = r < K ? (double)smp[(int64_t)(t0 + t) * a.slot_elems + r] - mu : 0.0;
+                for (int t = 0; t < nt; ++t) {
+                    const bool tk = r < K && has && (w < 0 || lab[t0 + t] == w);
+                    xs[h][t * KP + r] = tk ? (double)smp[(int64_t)(t0 + t) * a.slot_elems + r] - mu : 0.0;
+                }
                 __syncthreads();
                 for (int t = 0; t < nt; ++t) {
                     const double xr = xs[h][t * KP + r];
@@ -2522,7 +2539,7 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
                     for (int c = 0; c < KP; ++c) row[c] += xr * xs[h][t * KP + c];
                 }
             }
-            const double inv_s1 = 1.0 / (double)(S - 1);
+            const double inv_s1 = 1.0 / (double)(m >= 2 ? m - 1 : 1);
 #pragma unroll
             for (int c = 0; c < KP; ++c) row[c] = r < K ? row[c] * inv_s1 : (c == r ? 1.0 : 0.0);
             if (ridge) {
@@ -2537,6 +2554,7 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
             }
             // sweep pivots 0 .. K-1
             int bad = 0;
+            ld = 0.0;
 #pragma unroll
             for (int k = 0; k < KP; ++k) {
                 if (k < K) {
@@ -2545,6 +2563,7 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
                     __syncthreads();
                     const double p = bc[h][k];
                     bad |= !(p > 0.0);
+                    ld -= log(p > 0.0 ? p : 1.0);
                     const double ip = 1.0 / (p > 0.0 ? p : 1.0);
                     const double f = row[k] * ip;
                     const bool own = r == k;
@@ -2557,12 +2576,13 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
                     row[k] = own ? -ip : f;
                 }
             }
-            const bool again = !ridge && bad;       // the factorisation failed: take the ridge
-            if (valid && ridge && r == 0) atomicAdd(a.ridged, 1);
+            const bool again = !ridge && bad && has && m >= 2;   // the factorisation failed: take the ridge
             if (__ballot(valid && again) == 0) break;
             ridge = ridge || again;
             if (pass == 1) break;
         }
+        const bool fit = has && m >= 2 && S >= 2;
+        if (valid && fit && ridge && r == 0 && a.comp == 0) atomicAdd(a.ridged, 1);
         // Lambda_hat mu_hat, then the packed row through LDS
         __syncthreads();
         bc[h][r] = mu;
@@ -2575,13 +2595,310 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
             const int base = r * (r + 1) / 2;
 #pragma unroll
             for (int c = 0; c < KP; ++c)
-                if (c <= r) xs[h][base + c] = S >= 2 ? -row[c] : 0.0;
-            xs[h][kk2 + r] = S >= 2 ? eta : 0.0;
+                if (c <= r) xs[h][base + c] = fit ? -row[c] : 0.0;
+            xs[h][kk2 + r] = fit ? eta : 0.0;
             xs[h][kk2 + K + r] = mu;
         }
         __syncthreads();
-        if (valid)
+        if (valid && has) {
+            double *out = a.out[item.x] + (int64_t)n * a.prow;
             for (int q = r; q < a.prow; q += KP) out[q] = xs[h][q];
+            if (a.aux && r == 0) a.aux[item.x][(int64_t)n * 2 + 1] = ld;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_lmeans: clustering of each entity's kept samples for the dominant-mode and
+// mixture approximations (Sec. 4.1; Sec. 5.1, which clusters with
+// lambda-means), one lane per entity, by the hard-clustering DP-means
+// iteration (Kulis and Jordan, 2012): one initial cluster at the mean of the
+// samples; then rounds of (1) assignment in sample order -- the nearest centre
+// (squared distance, lowest index on ties), or a new cluster on the sample
+// itself when that centre is farther than lambda and fewer than kLmCmax
+// clusters exist -- and (2) centres moved to their members' means (sums in
+// sample order), clusters without members dropped with the others keeping
+// their order; until the assignment repeats, at most kLmMaxit rounds.
+// lambda^2 = c^2 sum_t |x_(t+1) - x_t|^2 / (2 (S - 1)), c = lam_scale.  Every
+// sum runs in index order without fused multiply-adds, so the labels are the
+// exact FP64 result of these steps.  Then the components: the ncomp largest
+// clusters with at least two members (decreasing size, lower index on ties),
+// or every sample as one component when none has two; weights proportional
+// to their sizes.  Centres, labels and counts live in the lane's private
+// memory; the samples are read from the sample store as needed.
+// --------------------------------------------------------------------------
+template <typename Ts, int KP>
+__global__ __launch_bounds__(64) void k_lmeans(const LmeansArgs a) {
+#pragma clang fp contract(off)
+    const int it = blockIdx.x * 64 + threadIdx.x;
+    if (it >= a.nitems) return;
+    const int K = a.K, S = a.S;
+    const int2 item = a.items[it];
+    const SideDesc &sd = a.sides[item.x];
+    const int n = item.y;
+    const Ts *smp = reinterpret_cast<const Ts *>(a.sample) + (sd.sample_off + n) * a.ks;
+    auto x = [&](int q, int k) { return (double)smp[(int64_t)q * a.slot_elems + k]; };
+    double cent[kLmCmax][KP];
+    int cnt[kLmCmax];
+    uint8_t lab[kLmMaxS], prev[kLmMaxS];
+    auto dist2 = [&](int q, int c) {
+        double t = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double d = x(q, k) - cent[c][k];
+            t = t + d * d;
+        }
+        return t;
+    };
+    double steps = 0.0;
+    for (int q = 0; q + 1 < S; ++q) {
+        double t = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const double d = x(q + 1, k) - x(q, k);
+            t = t + d * d;
+        }
+        steps = steps + t;
+    }
+    const double lam2 = S > 1 ? a.lam_scale * a.lam_scale * steps / (2.0 * (double)(S - 1)) : 0.0;
+    int C = 1;
+    for (int k = 0; k < K; ++k) {
+        double t = 0.0;
+        for (int q = 0; q < S; ++q) t = t + x(q, k);
+        cent[0][k] = t / (double)S;
+    }
+    for (int q = 0; q < S; ++q) prev[q] = 0xFF;
+    for (int round = 0; round < kLmMaxit; ++round) {
+        for (int q = 0; q < S; ++q) {
+            int best = 0;
+            double dbest = dist2(q, 0);
+            for (int c = 1; c < C; ++c) {
+                const double d = dist2(q, c);
+                if (d < dbest) {
+                    dbest = d;
+                    best = c;
+                }
+            }
+            if (dbest > lam2 && C < kLmCmax) {
+                for (int k = 0; k < K; ++k) cent[C][k] = x(q, k);
+                best = C++;
+            }
+            lab[q] = (uint8_t)best;
+        }
+        for (int c = 0; c < C; ++c) {
+            cnt[c] = 0;
+            for (int k = 0; k < K; ++k) cent[c][k] = 0.0;
+        }
+        for (int q = 0; q < S; ++q) {
+            const int c = lab[q];
+            for (int k = 0; k < K; ++k) cent[c][k] = cent[c][k] + x(q, k);
+            cnt[c] += 1;
+        }
+        int Cn = 0;
+        for (int c = 0; c < C; ++c) {
+            if (cnt[c] == 0) continue;
+            for (int k = 0; k < K; ++k) cent[Cn][k] = cent[c][k] / (double)cnt[c];
+            cnt[Cn] = cnt[c];
+            for (int q = 0; q < S; ++q)
+                if (lab[q] == c) lab[q] = (uint8_t)Cn;
+            ++Cn;
+        }
+        C = Cn;
+        bool same = true;
+        for (int q = 0; q < S; ++q) {
+            same = same && lab[q] == prev[q];
+            prev[q] = lab[q];
+        }
+        if (same) break;
+    }
+    uint8_t *lo = a.labels[item.x] + (int64_t)n * a.maxS;
+    for (int q = 0; q < S; ++q) lo[q] = lab[q];
+    // components
+    int chosen[kMaxComp];
+    int taken = 0, nch = 0;
+    for (int c = 0; c < a.ncomp; ++c) {
+        int best = -1;
+        for (int j = 0; j < C; ++j)
+            if (!((taken >> j) & 1) && cnt[j] >= 2 && (best < 0 || cnt[j] > cnt[best])) best = j;
+        if (best < 0) break;
+        taken |= 1 << best;
+        chosen[nch++] = best;
+    }
+    int total = 0;
+    for (int c = 0; c < nch; ++c) total += cnt[chosen[c]];
+    double *ax = a.aux[item.x] + (int64_t)n * 2;
+    for (int c = 0; c < kMaxComp; ++c) {
+        int8_t wv = -2;
+        double pi = 0.0;
+        if (nch == 0 && c == 0) {
+            wv = -1;
+            pi = 1.0;
+        } else if (c < nch) {
+            wv = (int8_t)chosen[c];
+            pi = (double)cnt[chosen[c]] / (double)total;
+        }
+        a.which[(int64_t)it * kMaxComp + c] = wv;
+        if (c < a.ncomp) ax[c * a.aux_plane] = pi;
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_gmm_pool: the pooled moments of each entity's mixture (eq.
+// marginal_mixture): mu = sum_c pi_c mu_c and Sigma = sum_c pi_c (Sigma_c +
+// (mu_c - mu)(mu_c - mu)^T) with Sigma_c = Lambda_c^-1, written as the
+// entity's moment-matched row [Lambda packed, Lambda mu, mu] with
+// Lambda = Sigma^-1.  64 / KP entities per wavefront, lane r of a group
+// holding row r; inverses by the symmetric sweep (sweep_inv).
+// --------------------------------------------------------------------------
+template <int KP>
+__device__ __forceinline__ void sweep_inv(double (&m)[KP], const int K, const int r, double *bc) {
+    // m (row r of a symmetric positive definite matrix, identity padding) <- row r of its inverse
+#pragma unroll
+    for (int k = 0; k < KP; ++k) {
+        if (k < K) {
+            __syncthreads();
+            bc[r] = m[k];
+            __syncthreads();
+            const double p = bc[k];
+            const double ip = 1.0 / (p > 0.0 ? p : 1.0);
+            const double f = m[k] * ip;
+            const bool own = r == k;
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                if (j == k) continue;
+                const double bj = bc[j];
+                m[j] = own ? bj * ip : m[j] - f * bj;
+            }
+            m[k] = own ? -ip : f;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < KP; ++c) m[c] = (r < K && c < K) ? -m[c] : (c == r ? 1.0 : 0.0);
+}
+
+template <int KP>
+__global__ __launch_bounds__(64) void k_gmm_pool(const GmmPoolArgs a) {
+    constexpr int G = 64 / KP;
+    constexpr int NP = KP * (KP + 1) / 2 + 2 * KP;
+    __shared__ __align__(16) double rowb[G][NP];
+    __shared__ double bc[G][KP];
+    const int lane = threadIdx.x;
+    const int h = lane / KP, r = lane % KP;
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    for (int pit = blockIdx.x; G * pit < a.nitems; pit += gridDim.x) {
+        const int it = G * pit + h;
+        const bool valid = it < a.nitems;
+        const int iq = valid ? it : G * pit;
+        const int2 item = a.items[iq];
+        const int n = item.y;
+        const double *ax = a.aux[item.x] + (int64_t)n * 2;
+        // pooled mean, components in order
+        double mu = 0.0;
+        for (int c = 0; c < a.ncomp; ++c) {
+            if (a.which[(int64_t)iq * kMaxComp + c] == -2) continue;
+            const double *cr = a.comp[item.x] + c * a.plane + (int64_t)n * a.prow;
+            mu += ax[c * a.aux_plane] * (r < K ? cr[kk2 + K + r] : 0.0);
+        }
+        double sig[KP];
+#pragma unroll
+        for (int j = 0; j < KP; ++j) sig[j] = 0.0;
+        for (int c = 0; c < a.ncomp; ++c) {
+            const bool pres = a.which[(int64_t)iq * kMaxComp + c] != -2;
+            if (__ballot(pres) == 0) continue;       // uniform over the wavefront
+            const double *cr = a.comp[item.x] + c * a.plane + (int64_t)n * a.prow;
+            const double pi = pres ? ax[c * a.aux_plane] : 0.0;
+            __syncthreads();
+            if (pres)
+                for (int q = r; q < kk2 + 2 * K; q += KP) rowb[h][q] = cr[q];
+            __syncthreads();
+            double m[KP];
+#pragma unroll
+            for (int j = 0; j < KP; ++j)
+                m[j] = (pres && r < K && j < K) ? rowb[h][r >= j ? tri(r, j) : tri(j, r)] : (j == r ? 1.0 : 0.0);
+            const double dr = (pres && r < K) ? rowb[h][kk2 + K + r] - mu : 0.0;
+            sweep_inv<KP>(m, K, r, bc[h]);
+            __syncthreads();
+            bc[h][r] = dr;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < KP; ++j)
+                if (r < K && j < K) sig[j] += pi * (m[j] + dr * bc[h][j]);
+        }
+#pragma unroll
+        for (int j = 0; j < KP; ++j) sig[j] = (r < K && j < K) ? sig[j] : (j == r ? 1.0 : 0.0);
+        sweep_inv<KP>(sig, K, r, bc[h]);
+        __syncthreads();
+        bc[h][r] = mu;
+        __syncthreads();
+        double eta = 0.0;
+#pragma unroll
+        for (int j = 0; j < KP; ++j)
+            if (j < K) eta += sig[j] * bc[h][j];
+        __syncthreads();
+        if (r < K) {
+#pragma unroll
+            for (int j = 0; j < KP; ++j)
+                if (j <= r) rowb[h][tri(r, j)] = sig[j];
+            rowb[h][kk2 + r] = eta;
+            rowb[h][kk2 + K + r] = mu;
+        }
+        __syncthreads();
+        if (valid) {
+            double *out = a.out[item.x] + (int64_t)n * a.prow;
+            for (int q = r; q < kk2 + 2 * K; q += KP) out[q] = rowb[h][q];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// k_gmm_pick: the mixture prior of a row for this sweep (Sec. 5.1): the
+// component c of largest log pi_c + log det(Lambda_c) / 2 - (x - mu_c)^T
+// Lambda_c (x - mu_c) / 2 at the row's current value x (the Gaussian
+// densities' common constant cancels; lowest index on ties; force0: the
+// largest component), copied into the side's own prior rows.  64 / KP rows
+// per wavefront, lane r of a group computing entry r of Lambda_c (x - mu_c).
+// --------------------------------------------------------------------------
+template <typename Ts, int KP>
+__global__ __launch_bounds__(64) void k_gmm_pick(const GmmPickArgs a) {
+    constexpr int G = 64 / KP;
+    __shared__ double bc[G][KP];
+    const int lane = threadIdx.x;
+    const int h = lane / KP, r = lane % KP;
+    const int K = a.K;
+    const int kk2 = K * (K + 1) / 2;
+    for (int pit = blockIdx.x; G * pit < a.nitems; pit += gridDim.x) {
+        const int it = G * pit + h;
+        const bool valid = it < a.nitems;
+        const int2 item = a.items[valid ? it : G * pit];
+        const GmmSide &gs = a.gsides[item.x];
+        const int n = item.y;
+        const Ts *st = reinterpret_cast<const Ts *>(gs.state) + (int64_t)n * a.ks_state;
+        const double xr = r < K ? elem_to_d(st[r]) : 0.0;
+        int best = 0;
+        if (!a.force0) {
+            double bval = -INFINITY;
+            for (int c = 0; c < a.ncomp; ++c) {
+                const double pi = gs.aux[c * a.aux_plane + (int64_t)n * 2];
+                const double ldt = gs.aux[c * a.aux_plane + (int64_t)n * 2 + 1];
+                const double *cr = gs.src + c * a.plane + (int64_t)n * a.prow;
+                const double dr = r < K ? xr - cr[kk2 + K + r] : 0.0;
+                __syncthreads();
+                bc[h][r] = dr;
+                __syncthreads();
+                double t = 0.0;
+                for (int j = 0; j < K; ++j) t += (r < K ? cr[r >= j ? tri(r, j) : tri(j, r)] : 0.0) * bc[h][j];
+                const double qf = group_sum1(dr * t, KP);
+                const double v = log(pi > 0.0 ? pi : 1.0) + 0.5 * ldt - 0.5 * qf;
+                if (pi > 0.0 && v > bval) {
+                    bval = v;
+                    best = c;
+                }
+            }
+        }
+        if (valid) {
+            const double *cr = gs.src + best * a.plane + (int64_t)n * a.prow;
+            double *dst = gs.dst + (int64_t)n * a.prow;
+            for (int q = r; q < a.prow; q += KP) dst[q] = cr[q];
+        }
     }
 }
 
@@ -3405,6 +3722,48 @@ hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s) {
                                      s, a);
     else if (kp <= 64) hipLaunchKernelGGL((k_pfac_rows<64>), dim3(g), dim3(64), 0, s, a);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_lmeans(int32_t prec, const LmeansArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    if (a.K > 32 || a.S > kLmMaxS || a.ncomp < 1 || a.ncomp > kMaxComp) return hipErrorInvalidValue;
+    const dim3 grid((a.nitems + 63) / 64);
+    const bool d = prec == kP64;
+    if (a.K <= 8) {
+        if (d) hipLaunchKernelGGL((k_lmeans<double, 8>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_lmeans<float, 8>), grid, dim3(64), 0, s, a);
+    } else if (a.K <= 16) {
+        if (d) hipLaunchKernelGGL((k_lmeans<double, 16>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_lmeans<float, 16>), grid, dim3(64), 0, s, a);
+    } else {
+        if (d) hipLaunchKernelGGL((k_lmeans<double, 32>), grid, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_lmeans<float, 32>), grid, dim3(64), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gmm_pool(const GmmPoolArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    if (a.K > 32) return hipErrorInvalidValue;
+    if (a.K <= 16) hipLaunchKernelGGL(k_gmm_pool<16>, dim3(grid_for((a.nitems + 3) / 4, 1, 65536)), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL(k_gmm_pool<32>, dim3(grid_for((a.nitems + 1) / 2, 1, 65536)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmm_pick(int32_t prec, const GmmPickArgs &a, hipStream_t s) {
+    if (a.nitems <= 0) return hipSuccess;
+    if (a.K > 32) return hipErrorInvalidValue;
+    const dim3 g16(grid_for((a.nitems + 3) / 4, 1, 65536)), g32(grid_for((a.nitems + 1) / 2, 1, 65536));
+    if (a.K <= 16) {
+        if (prec == kP64) hipLaunchKernelGGL((k_gmm_pick<double, 16>), g16, dim3(64), 0, s, a);
+        else if (prec == kP32) hipLaunchKernelGGL((k_gmm_pick<float, 16>), g16, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_gmm_pick<uint16_t, 16>), g16, dim3(64), 0, s, a);
+    } else {
+        if (prec == kP64) hipLaunchKernelGGL((k_gmm_pick<double, 32>), g32, dim3(64), 0, s, a);
+        else if (prec == kP32) hipLaunchKernelGGL((k_gmm_pick<float, 32>), g32, dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_gmm_pick<uint16_t, 32>), g32, dim3(64), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -161,6 +161,75 @@ struct MmArgs {
     int32_t K, prow;
     double *const *out;       // per side: moment-matched rows
     int32_t *ridged;
+    // a subset of the samples per entity (dominant mode, mixture components),
+    // or every sample when `labels` is null: sample q of item it is taken
+    // when which[it * kMaxComp + comp] is -1 or equals its cluster label
+    // (labels[side] + entity * maxS + q); -2 means no component (no output)
+    const uint8_t *const *labels;
+    const int8_t *which;
+    int32_t comp, maxS;
+    double *const *aux;       // per side: (pi, log det Lambda) pairs of entity 0, or null
+};
+
+// Components kept per row by the mixture approximation, at most.
+constexpr int kMaxComp = 4;
+// lambda-means: clusters per row, rounds, kept samples per row, at most.
+constexpr int kLmCmax = 16;
+constexpr int kLmMaxit = 32;
+constexpr int kLmMaxS = 256;
+
+// lambda-means clustering of each item's kept samples and the choice of its
+// components: the largest cluster (ncomp = 1, dominant mode) or the ncomp
+// largest with at least two members (mixture), as cluster ids in which[]
+// (-1: every sample, -2: none) and size weights in the aux planes.
+struct LmeansArgs {
+    const int2 *items;        // (side, entity)
+    int32_t nitems;
+    const SideDesc *sides;
+    const void *sample;
+    int64_t slot_elems;
+    int32_t ks, S, K;
+    double lam_scale;
+    int32_t ncomp;
+    uint8_t *const *labels;   // per side: entity 0's labels (maxS per entity)
+    int32_t maxS;
+    int8_t *which;            // per item, kMaxComp
+    double *const *aux;       // per side: plane 0 (pi, log det) of entity 0
+    int64_t aux_plane;        // doubles between component planes
+};
+
+// Pooled moments of each item's mixture (eq. marginal_mixture) into its
+// moment-matched row.
+struct GmmPoolArgs {
+    const int2 *items;
+    int32_t nitems;
+    const int8_t *which;      // per item, kMaxComp
+    const double *const *comp;// per side: plane 0 row of entity 0
+    const double *const *aux; // per side: plane 0 (pi, log det) of entity 0
+    int64_t plane, aux_plane; // doubles between component planes
+    double *const *out;       // per side: moment-matched rows
+    int32_t K, prow, ncomp;
+};
+
+// A side whose prior is a propagated mixture: each sweep every row takes the
+// component of largest responsibility at its current value, copied into the
+// side's own prior rows (which the update kernels read).
+struct GmmSide {
+    const double *src;        // plane 0 row of entity 0 of the source block
+    const double *aux;        // plane 0 (pi, log det) of entity 0 of the source
+    double *dst;              // this side's prior rows (entity 0)
+    const void *state;        // this side's state rows (entity 0)
+    int32_t n;
+    int32_t pad_;
+};
+
+struct GmmPickArgs {
+    const int2 *items;        // (gmm side, entity)
+    int32_t nitems;
+    const GmmSide *gsides;
+    int64_t plane, aux_plane;
+    int32_t ks_state, K, prow, ncomp;
+    int32_t force0;           // 1: the largest component (stage begin)
 };
 
 // Prior factors of moment-matched rows: for each (side, entity) item the row
@@ -241,6 +310,9 @@ hipError_t launch_reduce(const ReduceJob *jobs, int32_t njobs, int32_t max_width
 hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
 hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s);
 hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
+hipError_t launch_lmeans(int32_t prec, const LmeansArgs &a, hipStream_t s);
+hipError_t launch_gmm_pool(const GmmPoolArgs &a, hipStream_t s);
+hipError_t launch_gmm_pick(int32_t prec, const GmmPickArgs &a, hipStream_t s);
 hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s);
 hipError_t launch_agg(const AggArgs &a, hipStream_t s);
 hipError_t launch_predict(const PredictArgs &a, hipStream_t s);

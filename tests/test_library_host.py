@@ -122,12 +122,26 @@ def test_validation_errors():
     _expect("BMF_EINVAL", nu0=2.0)                                                # nu0 <= K-1
     _expect("BMF_EINVAL", W0=np.array([[1, 2, 0, 0], [2, 1, 0, 0], [0, 0, 1, 0], [0, 0, 0, 1.0]]))
     _expect("BMF_EINVAL", thin=0)
+    _expect("BMF_EINVAL", approx=3)                                               # no such approximation
+    _expect("BMF_EINVAL", approx="gmm", ncomp=5)                                  # at most 4 components
+    _expect("BMF_EINVAL", approx="dm", lambda_scale=-1.0)
+    _expect("BMF_EUNSUPPORTED", approx="dm", K=33, nu0=33.0)                      # clustering needs K <= 32
+    _expect("BMF_EUNSUPPORTED", approx="gmm", max_kept=257)                       # labels of 256 samples at most
     # ceil partition that leaves the last part empty: N=10, I=6 -> parts of 2
     rng = np.random.default_rng(1)
     cells = rng.choice(100, size=30, replace=False)
     with pytest.raises(BMFError) as e:
         BMF(10, 10, 2, cells // 10, cells % 10, np.ones(30), I=6, device=False)
     assert e.value.status == "BMF_EINVAL"
+
+
+def test_mixture_introspection_refused_without_device_or_clusters():
+    N, D, row, col, val = _data(seed=7)
+    m = BMF(N, D, 4, row, col, val, approx="gmm", device=False)
+    for f in (lambda: m.get_clusters(0, 0, 2), lambda: m.get_component(0, 0, 0)):
+        with pytest.raises(BMFError) as e:
+            f()
+        assert e.value.status == "BMF_ESTATE"
 
 
 def test_device_calls_refused_on_host_context():
