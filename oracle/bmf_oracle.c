@@ -258,20 +258,24 @@ void orc_init_side(int64_t R, int32_t K, uint64_t seed, uint32_t c2, double *out
 /* The conditional system of one entity: with G = sum_{d in Omega_n} w_d w_d^T
  * and s = sum_{d in Omega_n} r_nd w_d (entries ptr[n] .. ptr[n+1] of idx/val),
  *     A = P_n + tau G,   h = P_n m_n + tau s.
- * G and hs are scratch (K x K and K). */
+ * With per-column noise precisions (the tau_d variant of Sec. 2.1) the row
+ * update weights each entry by its column's tau_d: wt (indexed like `other`,
+ * or NULL for 1) gives G = sum tau_d w_d w_d^T and s = sum tau_d r_nd w_d,
+ * with tau = 1.  G and hs are scratch (K x K and K). */
 static void orc_cond_system(int32_t K, int64_t e0, int64_t e1, const int32_t *idx, const double *val,
-                            const double *other, const double *Pn, const double *mn, double tau,
-                            double *G, double *hs, double *A, double *h)
+                            const double *other, const double *wt, const double *Pn, const double *mn,
+                            double tau, double *G, double *hs, double *A, double *h)
 {
     memset(G, 0, sizeof(double) * (size_t)K * K);
     memset(hs, 0, sizeof(double) * (size_t)K);
     for (int64_t e = e0; e < e1; ++e) {
         const double *w = other + (int64_t)idx[e] * K;
         const double r = val[e];
+        const double we = wt ? wt[idx[e]] : 1.0;
         for (int a = 0; a < K; ++a) {
             for (int b = 0; b < K; ++b)
-                G[a * K + b] += w[a] * w[b];
-            hs[a] += r * w[a];
+                G[a * K + b] += we * w[a] * w[b];
+            hs[a] += we * r * w[a];
         }
     }
     for (int a = 0; a < K; ++a) {
@@ -303,17 +307,35 @@ void orc_cond_precision(int64_t R, int32_t K, const int64_t *ptr, const int32_t 
         for (int64_t n = 0; n < R; ++n) {
             const double *Pn = per_row ? P + n * K * K : P;
             const double *mn = per_row ? m + n * K : m;
-            orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, Pn, mn, tau, G, hs,
+            orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, NULL, Pn, mn, tau, G, hs,
                             A + n * (int64_t)K * K, h);
         }
         free(G); free(hs); free(h);
     }
 }
 
+/* orc_update_side with per-column noise precisions (the tau_d variant of
+ * Sec. 2.1): wt (per entity of the other side, the row update's entry weights
+ * tau_d) and taus (per entity of this side, the column update's tau_d); either
+ * NULL for the scalar tau. */
+int64_t orc_update_side_w(int64_t R, int32_t K, const int64_t *ptr, const int32_t *idx,
+                          const double *val, const double *other, const double *wt, const double *taus,
+                          int32_t per_row, const double *P, const double *m, double tau, uint64_t seed,
+                          uint32_t t, uint32_t c2, double *out, int32_t nthreads);
+
 int64_t orc_update_side(int64_t R, int32_t K, const int64_t *ptr, const int32_t *idx,
                         const double *val, const double *other, int32_t per_row,
                         const double *P, const double *m, double tau, uint64_t seed,
                         uint32_t t, uint32_t c2, double *out, int32_t nthreads)
+{
+    return orc_update_side_w(R, K, ptr, idx, val, other, NULL, NULL, per_row, P, m, tau, seed, t, c2, out,
+                             nthreads);
+}
+
+int64_t orc_update_side_w(int64_t R, int32_t K, const int64_t *ptr, const int32_t *idx,
+                          const double *val, const double *other, const double *wt, const double *taus,
+                          int32_t per_row, const double *P, const double *m, double tau, uint64_t seed,
+                          uint32_t t, uint32_t c2, double *out, int32_t nthreads)
 {
     int64_t failures = 0;
 #ifdef _OPENMP
@@ -337,7 +359,8 @@ int64_t orc_update_side(int64_t R, int32_t K, const int64_t *ptr, const int32_t 
         for (int64_t n = 0; n < R; ++n) {
             const double *Pn = per_row ? P + n * K * K : P;
             const double *mn = per_row ? m + n * K : m;
-            orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, Pn, mn, tau, G, hs, A, h);
+            orc_cond_system(K, ptr[n], ptr[n + 1], idx, val, other, wt, Pn, mn, taus ? taus[n] : tau, G, hs,
+                            A, h);
             if (orc_chol(K, A, L) != 0) {
                 failures += 1;
                 continue;
@@ -380,6 +403,20 @@ double orc_tau_draw(double sse, int64_t M, double a0, double b0, uint64_t seed, 
     const double shape = a0 + 0.5 * (double)M;
     const double rate = b0 + 0.5 * sse;
     return orc_gamma(seed, 0u, t, c2, shape) / rate;
+}
+
+/* Per-column noise precisions (the tau_d variant of Sec. 2.1): for column d
+ * of a block with M_d entries and residual SSE_d, tau_d ~ Gamma(shape
+ * a0 + M_d/2, rate b0 + SSE_d/2), the attempts on counter (d, t, c2, k).
+ * C columns; sse and cnt per column. */
+void orc_tau_cols(int64_t C, const double *sse, const int64_t *cnt, double a0, double b0, uint64_t seed,
+                  uint32_t t, uint32_t c2, double *tau)
+{
+    for (int64_t d = 0; d < C; ++d) {
+        const double shape = a0 + 0.5 * (double)cnt[d];
+        const double rate = b0 + 0.5 * sse[d];
+        tau[d] = orc_gamma(seed, (uint32_t)d, t, c2, shape) / rate;
+    }
 }
 
 /* Normal-Wishart hyperparameter draw for one side of one block, given its Nb

@@ -38,6 +38,11 @@ TEST INFRASTRUCTURE ONLY (FP64).  Sweep order and readings:
   (|lambda_min| + eps) I with eps = 1e-6 tr(Lambda_base) / K (the "small
   constant" is a reading).  With no siblings, mu* is the base mean itself.
 * Prediction (Sec. 5.2): y_hat = y_bar + mu*_x^T mu*_w with posterior means.
+* Per-column noise precisions (the tau_d variant of Sec. 2.1, tau_per_column):
+  y_nd ~ N(x_n^T w_d, 1/tau_d) with tau_d ~ Gamma(a0, b0) per column of each
+  block; the row update weights each entry by its column's tau_d, the column
+  update uses its own tau_d, and the draw is tau_d ~ Gamma(a0 + M_d/2,
+  b0 + SSE_d/2) over the column's M_d entries, on counter (d, t, TAU, k).
 """
 import numpy as np
 
@@ -57,7 +62,9 @@ def nw_scale_inverse(W0):
 class Oracle:
     def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
-                 seed=0, burnin=0, thin=1, nthreads=0, approx="mm", lambda_scale=2.0, ncomp=3):
+                 seed=0, burnin=0, thin=1, nthreads=0, approx="mm", lambda_scale=2.0, ncomp=3,
+                 tau_per_column=False):
+        self.tau_per_column = bool(tau_per_column)
         if approx not in ("mm", "dm", "gmm"):
             raise ValueError("approx must be mm, dm or gmm")
         self.approx, self.lambda_scale, self.ncomp = approx, float(lambda_scale), int(ncomp)
@@ -127,6 +134,8 @@ class Oracle:
             blk["hx"] = (np.eye(K), np.zeros(K))      # (Lambda_X, mu_X)
             blk["hw"] = (np.eye(K), np.zeros(K))
             blk["tau"] = self.a0 / self.b0 if self.sample_tau else self.tau_fixed
+            if self.tau_per_column:
+                blk["tau"] = np.full(blk["C"], blk["tau"])
             blk["t"] = 0
             blk["samples_x"] = []
             blk["samples_w"] = []
@@ -166,10 +175,18 @@ class Oracle:
             per_row = 0
         out = blk[key].copy()
         other = np.ascontiguousarray(other)
-        fails = native.lib().orc_update_side(
-            n, K, ptr(ptr_), ptr(idx), ptr(val), ptr(other), per_row, ptr(P), ptr(m),
-            float(blk["tau"]), self.seed, t & 0xFFFFFFFF, counter_c2(blk["b"], purpose),
-            ptr(out), self.nthreads)
+        if self.tau_per_column:
+            # rows: entry weights tau_d of the gathered columns; columns: their own tau_d
+            tcol = np.ascontiguousarray(blk["tau"], dtype=np.float64)
+            wt, taus = (tcol, None) if which == "rows" else (None, tcol)
+            fails = native.lib().orc_update_side_w(
+                n, K, ptr(ptr_), ptr(idx), ptr(val), ptr(other), ptr(wt), ptr(taus), per_row, ptr(P),
+                ptr(m), 1.0, self.seed, t & 0xFFFFFFFF, counter_c2(blk["b"], purpose), ptr(out), self.nthreads)
+        else:
+            fails = native.lib().orc_update_side(
+                n, K, ptr(ptr_), ptr(idx), ptr(val), ptr(other), per_row, ptr(P), ptr(m),
+                float(blk["tau"]), self.seed, t & 0xFFFFFFFF, counter_c2(blk["b"], purpose),
+                ptr(out), self.nthreads)
         if fails:
             raise FloatingPointError("oracle: %d non-SPD conditional precisions" % fails)
         blk[key] = out
@@ -193,8 +210,23 @@ class Oracle:
                                     ptr(blk["csr_val"]), ptr(np.ascontiguousarray(blk["X"])),
                                     ptr(np.ascontiguousarray(blk["W"])))
 
+    def col_sse(self, blk):
+        """Residual SSE of every column of a block (entries in CSC order)."""
+        X, W = blk["X"], blk["W"]
+        cols = np.repeat(np.arange(blk["C"]), np.diff(blk["csc_ptr"]))
+        res = blk["csc_val"] - np.einsum("ek,ek->e", X[blk["csc_idx"]], W[cols])
+        return np.bincount(cols, weights=res * res, minlength=blk["C"])
+
     def tau_draw(self, blk, t=None):
         t = blk["t"] if t is None else t
+        if self.tau_per_column:
+            sse = np.ascontiguousarray(self.col_sse(blk))
+            cnt = np.ascontiguousarray(np.diff(blk["csc_ptr"]).astype(np.int64))
+            tau = np.zeros(blk["C"])
+            native.lib().orc_tau_cols(blk["C"], ptr(sse), ptr(cnt), self.a0, self.b0, self.seed, t & 0xFFFFFFFF,
+                                      counter_c2(blk["b"], "TAU"), ptr(tau))
+            blk["tau"] = tau
+            return
         s = self.sse(blk)
         blk["tau"] = native.lib().orc_tau_draw(s, blk["M"], self.a0, self.b0, self.seed,
                                                t & 0xFFFFFFFF, counter_c2(blk["b"], "TAU"))

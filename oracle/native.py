@@ -69,6 +69,11 @@ def lib():
     L.orc_nw_draw.restype = ctypes.c_int
     L.orc_mm.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp]
     L.orc_mm.restype = _i64
+    L.orc_update_side_w.argtypes = [_i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _d, _u64,
+                                    _u32, _u32, _vp, _i32]
+    L.orc_update_side_w.restype = _i64
+    L.orc_tau_cols.argtypes = [_i64, _vp, _vp, _d, _d, _u64, _u32, _u32, _vp]
+    L.orc_tau_cols.restype = None
     L.orc_lmeans.argtypes = [_i64, _i32, _i32, _vp, _d, _i32, _i32, _vp, _vp]
     L.orc_lmeans.restype = _i64
     L.orc_mm_sel.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -78,7 +83,9 @@ def lib():
 
 
 def ptr(a):
-    """Raw data pointer of a C-contiguous numpy array."""
+    """Raw data pointer of a C-contiguous numpy array (None: a null pointer)."""
+    if a is None:
+        return None
     assert a.flags["C_CONTIGUOUS"], "oracle arrays must be C-contiguous"
     return a.ctypes.data_as(ctypes.c_void_p)
 
