@@ -160,6 +160,15 @@ typedef struct {
     int32_t approx;              /* bmf_approx (0 = moment matching) */
     double lambda_scale;         /* lambda-means scale, > 0 (0 => 2) */
     int32_t ncomp;               /* mixture components, 1..4 (0 => 3) */
+    /* per-column noise precisions (Sec. 2.1, the tau_d variant of eq.
+     * BMF_likelihood_normal): y_nd ~ N(x_n^T w_d, 1/tau_d), one tau_d per
+     * column of each block, each with the Gamma(tau_a0, tau_b0) prior (or
+     * tau_fixed when tau is not sampled) and drawn every sweep from
+     * Gamma(tau_a0 + M_d/2, tau_b0 + SSE_d/2) over its M_d entries.  The row
+     * update then weights each entry by its column's tau_d (the library forms
+     * sqrt(tau_d) w_d and sqrt(tau_d) r_nd at the start of each sweep), the
+     * column update uses its own.  FP32 and FP64 precision only. */
+    int32_t tau_per_column;
 } bmf_config;
 
 /* Fill *cfg with defaults: K = 10, I = J = 1, beta0 = 2, nu0 = K, tau Gamma(1,1)
@@ -293,6 +302,11 @@ bmf_status bmf_get_clusters(bmf_ctx *c, int32_t b, int32_t side, int32_t *labels
  * (n x K x K), log det Lambda (n).  Any output may be NULL. */
 bmf_status bmf_get_component(bmf_ctx *c, int32_t b, int32_t side, int32_t comp, double *pi, double *mu,
                              double *Lam, double *logdet);
+
+/* Per-column noise precisions tau_d of block b (C values, host) when
+ * bmf_config.tau_per_column is set and b is in the active stage
+ * (BMF_ESTATE otherwise). */
+bmf_status bmf_get_tau_cols(bmf_ctx *c, int32_t b, double *tau);
 
 /* Aggregated per-row posterior means (after bmf_predict or bmf_aggregate):
  * side 0: mu_x (N x K) in original row ids; side 1: mu_w (D x K). */

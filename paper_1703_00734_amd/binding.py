@@ -39,6 +39,7 @@ class bmf_config(ctypes.Structure):
         ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
         ("stream", _vp),
         ("approx", _i32), ("lambda_scale", _d), ("ncomp", _i32),
+        ("tau_per_column", _i32),
     ]
 
 
@@ -83,6 +84,7 @@ def load():
         "bmf_get_mm": [_vp, _i32, _i32, _vp, _vp],
         "bmf_get_clusters": [_vp, _i32, _i32, _vp],
         "bmf_get_component": [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
+        "bmf_get_tau_cols": [_vp, _i32, _vp],
         "bmf_get_draw": [_vp, _i32, _i32, _vp],
         "bmf_aggregate": [_vp],
         "bmf_get_aggregate": [_vp, _i32, _vp],
@@ -121,7 +123,7 @@ def exported_symbols():
             "bmf_aggregate", "bmf_get_aggregate", "bmf_get_stats", "bmf_enable_timing",
             "bmf_kernel_times", "bmf_get_schedule", "bmf_stage_work", "bmf_get_sample",
             "bmf_set_progress", "bmf_save_state", "bmf_load_state", "bmf_predict_noalloc", "bmf_get_clusters",
-            "bmf_get_component"]
+            "bmf_get_component", "bmf_get_tau_cols"]
 
 
 # int32_t (*bmf_progress_fn)(void *user, int32_t stage, int64_t sweep)
@@ -139,7 +141,8 @@ class BMF:
     def __init__(self, N, D, K, row, col, val, I=1, J=1, order="given", mu0=None, beta0=2.0,
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
                  seed=0, burnin=0, thin=1, max_kept=1, precision="fp32", pivot_theta=0.0,
-                 batched=True, lane_nnz=0, device=True, stream=None, approx="mm", lambda_scale=2.0, ncomp=3):
+                 batched=True, lane_nnz=0, device=True, stream=None, approx="mm", lambda_scale=2.0, ncomp=3,
+                 tau_per_column=False):
         if device:
             # torch's HIP runtime is initialised before the library's is loaded
             import torch
@@ -175,6 +178,7 @@ class BMF:
         c.approx = APPROX[approx] if isinstance(approx, str) else int(approx)
         c.lambda_scale = float(lambda_scale)
         c.ncomp = int(ncomp)
+        c.tau_per_column = 1 if tau_per_column else 0
         self.cfg = c
         self.ctx = _vp()
         self.workspace = None
@@ -319,6 +323,11 @@ class BMF:
         lab = np.empty((n, S), dtype=np.int32)
         self._check(self.L.bmf_get_clusters(self.ctx, b, side, _ptr(lab)))
         return lab
+
+    def get_tau_cols(self, b):
+        tau = np.empty(self.block_info(b)["C"])
+        self._check(self.L.bmf_get_tau_cols(self.ctx, b, _ptr(tau)))
+        return tau
 
     def get_component(self, b, side, comp):
         info = self.block_info(b)

@@ -56,7 +56,7 @@ struct Layout {
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
         m_items, m_items2, m_stats, m_hyper, m_mmout, pfac, m_pfout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
         p_out, rowpos, colpos, m_gitems, m_gstart, lab, which, aux, gmm, m_labptr, m_auxptr, m_gmmout, m_gsides,
-        m_pitems, total;
+        m_pitems, tau_col, Wt, vt, one, m_taujobs, total;
     int32_t ncomp = 1;        // components per row of the propagated fit (mixture: ncomp, else 1)
     int64_t n_tiles_cap, n_items_cap, n_stats_cap, n_sse_cap, n_seg_cap;
     bool mfma = false;
@@ -191,6 +191,17 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
         L.m_gsides = take(sizeof(GmmSide) * 2 * L.nb);
         L.m_pitems = take(c.approx == BMF_APPROX_GMM ? sizeof(int2) * (L.Emax + 8) : 0);
     }
+    // per-column noise precisions: tau_d of every block column, the row pass's
+    // scaled copies of W and of the CSR values, and a constant 1 (the row
+    // pass's tau then)
+    {
+        const bool tc = c.tau_per_column != 0;
+        L.tau_col = take(tc ? 8 * L.E_c : 0);
+        L.Wt = take(tc ? L.ss * L.E_c * L.ks_m : 0);
+        L.vt = take(tc ? L.vs * nnz : 0);
+        L.one = take(8);
+        L.m_taujobs = take(sizeof(TauColJob) * L.nb);
+    }
     L.total = off;
     return true;
 }
@@ -244,6 +255,8 @@ struct StageLists {
     std::vector<int64_t> sse_tile_begin;            // SSE tiles per block (== row tiles grouped)
     int64_t row_ents = 0, col_ents = 0;
     int64_t row_updates = 0, ratings = 0;
+    // per-column noise precisions: one job per block
+    std::vector<TauColJob> taujobs;
     // mixture priors: the propagated sides and their (side, entity) pick items
     std::vector<GmmSide> gsides;
     std::vector<int2> pitems;
@@ -378,7 +391,7 @@ uint64_t data_fingerprint(const bmf_config &c) {
     m.val(c.N); m.val(c.D); m.val(c.K); m.val(c.nnz); m.val(c.I); m.val(c.J); m.val(c.order);
     m.val(c.beta0); m.val(c.nu0); m.val(c.sample_tau); m.val(c.tau_a0); m.val(c.tau_b0); m.val(c.tau_fixed);
     m.val(c.seed); m.val(c.burnin); m.val(c.thin); m.val(c.max_kept); m.val(c.precision); m.val(c.pivot_theta);
-    m.val(c.approx); m.val(c.lambda_scale); m.val(ncomp_of(c));
+    m.val(c.approx); m.val(c.lambda_scale); m.val(ncomp_of(c)); m.val(c.tau_per_column);
     if (c.mu0) m.bytes(c.mu0, 8 * (size_t)c.K);
     if (c.W0) m.bytes(c.W0, 8 * (size_t)c.K * c.K);
     if (c.nnz > 0) {
@@ -416,6 +429,10 @@ bmf_status validate(const bmf_config *cfg, std::string &err) {
     if (c.approx < BMF_APPROX_MM || c.approx > BMF_APPROX_GMM) { err = "bad approx"; return BMF_EINVAL; }
     if (!(c.lambda_scale >= 0.0) || !std::isfinite(c.lambda_scale)) { err = "lambda_scale must be >= 0"; return BMF_EINVAL; }
     if (c.ncomp < 0 || c.ncomp > kMaxComp) { err = "ncomp must be in 0..4"; return BMF_EINVAL; }
+    if (c.tau_per_column && c.precision == BMF_PREC_BF16) {
+        err = "per-column noise precisions need FP32 or FP64 precision";
+        return BMF_EUNSUPPORTED;
+    }
     if (c.approx != BMF_APPROX_MM && c.K > 32) { err = "dominant-mode and mixture fits need K <= 32"; return BMF_EUNSUPPORTED; }
     if (c.approx != BMF_APPROX_MM && c.max_kept > kLmMaxS) {
         err = "dominant-mode and mixture fits keep at most 256 samples per stage";
@@ -521,7 +538,8 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         r.sample_off = soff;
         soff += B.R;
         r.prior = xp ? mm + c->x_off[B.i * J + 0] * L.prow : hyper + ((int64_t)b * 2 + 0) * L.hy + kHyPacked(L);
-        r.tau = tau + b;
+        r.tau = c->cfg.tau_per_column ? c->dev<double>(L.one) : tau + b;
+        r.tau_stride = 0;
         r.pfac = xp && pf ? pf + pfx[B.i] * L.pfrow : nullptr;
         r.n = (int32_t)B.R;
         r.per_row = xp;
@@ -534,7 +552,10 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
         q.sample_off = soff;
         soff += B.C;
         q.prior = wp ? mm + (L.E_r + c->w_off[0 * J + B.j]) * L.prow : hyper + ((int64_t)b * 2 + 1) * L.hy + kHyPacked(L);
-        q.tau = tau + b;
+        q.tau = c->cfg.tau_per_column ? c->dev<double>(L.tau_col) + c->w_off[b] : tau + b;
+        q.tau_stride = c->cfg.tau_per_column ? 1 : 0;
+        if (c->cfg.tau_per_column)
+            S.taujobs.push_back(TauColJob{b, (int32_t)B.C, c->w_off[b], c->csc_ptr_off[b], c->nz_off[0][b], B.M});
         q.pfac = wp && pf ? pf + pfw[B.j] * L.pfrow : nullptr;
         q.n = (int32_t)B.C;
         q.per_row = wp;
@@ -746,7 +767,7 @@ static void build_stage_lists(bmf_ctx *c, int32_t s) {
             S.hyper.push_back(h);
             S.hyper_kind.push_back(1);
         }
-        if (c->cfg.sample_tau) {
+        if (c->cfg.sample_tau && !c->cfg.tau_per_column) {
             HyperJob h{2, b, k, k + 1, B.M, tau + b};
             S.hyper.push_back(h);
             S.hyper_kind.push_back(2);
@@ -849,6 +870,7 @@ static bmf_status upload_stage(bmf_ctx *c) {
         outs[nbs + k] = c->dev<double>(L.mm) + (L.E_r + c->w_off[b]) * L.prow;
     }
     if ((st = upload(c, L.m_mmout, outs.data(), outs.size() * sizeof(double *)))) return st;
+    if ((st = upload(c, L.m_taujobs, S.taujobs.data(), S.taujobs.size() * sizeof(TauColJob)))) return st;
     if (c->cfg.approx != BMF_APPROX_MM) {
         const int64_t Etot = L.E_r + L.E_c;
         std::vector<uint8_t *> labp(2 * nbs);
@@ -894,6 +916,11 @@ static UpdArgs upd_args(bmf_ctx *c, bool rows, uint32_t t, void *sample, bool us
     a.idx = c->dev<int32_t>(rows ? L.csr_idx : L.csc_idx);
     a.val = c->dev<void>(rows ? L.csr_val : L.csc_val);
     a.other = c->dev<void>(rows ? L.W : L.X);
+    if (rows && c->cfg.tau_per_column) {
+        // the row pass reads sqrt(tau_d) w_d and sqrt(tau_d) r_nd (tau = 1)
+        a.val = c->dev<void>(L.vt);
+        a.other = c->dev<void>(L.Wt);
+    }
     a.ks_other = L.ks_m;
     a.self = c->dev<void>(rows ? L.X : L.W);
     a.ks_self = L.ks_m;
@@ -1189,10 +1216,50 @@ static bmf_status run_gmm_pick(bmf_ctx *c, bool force0) {
     return timed(c, kKPick, [&] { return launch_gmm_pick(c->prec(), a, c->ls); });
 }
 
+// Per-column noise precisions: the row pass's scaled factors and values from
+// the current W and tau_d (every block of the stage, or block k), and the
+// tau_d draws after the column pass.
+static TauColArgs tau_args(bmf_ctx *c, int32_t k, uint32_t t, bool use_ss) {
+    const Layout &L = c->L;
+    TauColArgs a{};
+    a.jobs = c->dev<TauColJob>(L.m_taujobs) + (k < 0 ? 0 : k);
+    a.njobs = k < 0 ? (int32_t)c->S.taujobs.size() : 1;
+    a.tau = c->dev<double>(L.tau_col);
+    a.W = c->dev<void>(L.W);
+    a.Wt = c->dev<void>(L.Wt);
+    a.ks = L.ks_m;
+    a.K = c->cfg.K;
+    a.val = c->dev<void>(L.csr_val);
+    a.vt = c->dev<void>(L.vt);
+    a.idx = c->dev<int32_t>(L.csr_idx);
+    a.cptr = c->dev<int64_t>(L.csc_ptr);
+    a.sse_col = c->dev<double>(L.sse_col);
+    a.a0 = c->cfg.tau_a0;
+    a.b0 = c->cfg.tau_b0;
+    a.ss = use_ss ? c->dev<SweepState>(L.sweep) : nullptr;
+    a.t = t;
+    a.k0 = (uint32_t)(c->cfg.seed & 0xFFFFFFFFu);
+    a.k1 = (uint32_t)(c->cfg.seed >> 32);
+    return a;
+}
+
+static bmf_status run_tau_scale(bmf_ctx *c, int32_t k) {
+    if (!c->cfg.tau_per_column) return BMF_OK;
+    const TauColArgs a = tau_args(c, k, 0, false);
+    return timed(c, kKFill, [&] { return launch_tau_scale(c->prec(), a, c->ls); });
+}
+
+static bmf_status run_tau_cols(bmf_ctx *c, int32_t k, uint32_t t, bool use_ss) {
+    if (!c->cfg.tau_per_column || !c->cfg.sample_tau) return BMF_OK;
+    const TauColArgs a = tau_args(c, k, t, use_ss);
+    return timed(c, kKHyper, [&] { return launch_tau_cols(a, c->ls); });
+}
+
 static bmf_status enqueue_sweep(bmf_ctx *c) {
     StageLists &S = c->S;
     bmf_status st;
     if ((st = run_gmm_pick(c, false))) return st;
+    if ((st = run_tau_scale(c, -1))) return st;
     const int32_t nbs = (int32_t)S.blocks.size();
     // the column pass always evaluates the residual SSE of every block (the tau
     // statistic when tau is sampled; the training fit, bmf_get_stats, always)
@@ -1217,6 +1284,7 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
         na.k1 = (uint32_t)(c->cfg.seed >> 32);
         na.noise = c->dev<double>(c->L.nw_noise);
         if ((st = timed(c, kKReduce, [&] { return launch_reduce(rj, nr, c->L.npair, c->ls, &na); }))) return st;
+        if ((st = run_tau_cols(c, -1, 0, true))) return st;
         if (S.hyper_begin[nbs] > 0) return run_hyper(c, 0, S.hyper_begin[nbs], 0, true, true, true);
     } else {
         for (int32_t k = 0; k < nbs; ++k) {
@@ -1225,6 +1293,7 @@ static bmf_status enqueue_sweep(bmf_ctx *c) {
             if ((st = reduce_sse(c, k))) return st;
             if ((st = run_stats(c, k, k + 1))) return st;
             if ((st = run_stats(c, nbs + k, nbs + k + 1))) return st;
+            if ((st = run_tau_cols(c, k, 0, true))) return st;
             if ((st = run_hyper(c, S.hyper_begin[k], S.hyper_begin[k + 1], 0, true))) return st;
         }
     }
@@ -1408,6 +1477,15 @@ static bmf_status begin_stage(bmf_ctx *c, int32_t s) {
         if ((st = upload(c, L.hyper + ((int64_t)b * 2 + 1) * L.hy * 8, hy.data(), 8 * L.hy))) return st;
         if ((st = upload(c, L.tau + 8 * (int64_t)b, &tau0, 8))) return st;
         HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (c->cfg.tau_per_column) {
+        const double one = 1.0;
+        if ((st = upload(c, L.one, &one, 8))) return st;
+        for (const TauColJob &j : S.taujobs) {
+            std::vector<double> tv((size_t)j.C, tau0);
+            if ((st = upload(c, L.tau_col + 8 * j.w_off, tv.data(), 8 * tv.size()))) return st;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
     }
     if ((st = run_gmm_pick(c, true))) return st;      // mixture priors: the largest component to start
     if ((st = init_factors(c))) return st;
@@ -2074,8 +2152,10 @@ bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
     StageLists &S = c->S;
     const int32_t nbs = (int32_t)S.blocks.size();
     bmf_status st;
-    // mixture priors follow the current state, as at the start of a sweep
+    // mixture priors follow the current state, as at the start of a sweep;
+    // per-column precisions: the row pass's scaled copies of W and the values
     if ((which == 0 || which == 1) && (st = run_gmm_pick(c, false))) return st;
+    if (which == 0 && (st = run_tau_scale(c, k))) return st;
     switch (which) {
     case 0: st = run_pass(c, true, tt, c->base + c->L.probe, k, false); break;
     case 1: st = run_pass(c, false, tt, c->base + c->L.probe, k, false); break;
@@ -2093,6 +2173,10 @@ bmf_status bmf_step(bmf_ctx *c, int32_t b, int32_t which, int64_t t) {
     case 4: {
         if (!c->cfg.sample_tau) return fail(c, BMF_ESTATE, "tau is fixed");
         if ((st = run_sse(c, k))) return st;
+        if (c->cfg.tau_per_column) {
+            st = run_tau_cols(c, k, tt, false);
+            break;
+        }
         int32_t j = -1;
         for (int32_t q = S.hyper_begin[k]; q < S.hyper_begin[k + 1]; ++q)
             if (S.hyper_kind[q] == 2) j = q;
@@ -2214,6 +2298,18 @@ bmf_status bmf_get_component(bmf_ctx *c, int32_t b, int32_t side, int32_t comp, 
             for (int i = 0; i < K; ++i)
                 for (int j = 0; j < K; ++j) Lam[(r * K + i) * K + j] = row[i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i];
     }
+    return BMF_OK;
+}
+
+bmf_status bmf_get_tau_cols(bmf_ctx *c, int32_t b, double *tau) {
+    if (!c) return BMF_EINVAL;
+    if (!c->device || c->stage == 0) return fail(c, BMF_ESTATE, "no active stage");
+    if (!c->cfg.tau_per_column) return fail(c, BMF_ESTATE, "the noise precision is one per block");
+    if (stage_index(c, b) < 0) return fail(c, BMF_EINVAL, "block is not in the active stage");
+    if (!tau) return fail(c, BMF_EINVAL, "null output");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(tau, c->base + c->L.tau_col + 8 * c->w_off[b], 8 * (size_t)c->plan.blocks[b].C,
+                        hipMemcpyDeviceToHost));
     return BMF_OK;
 }
 
@@ -2402,6 +2498,7 @@ std::vector<Span> ckpt_spans(const bmf_ctx *c, int32_t stage, int32_t finalized,
             v.push_back({L.W + c->w_off[b] * L.ks_m * L.ss, B.C * L.ks_m * L.ss});
             v.push_back({L.hyper + (int64_t)b * 2 * L.hy * 8, 16 * (int64_t)L.hy});
             v.push_back({L.tau + 8 * (int64_t)b, 8});
+            if (c->cfg.tau_per_column) v.push_back({L.tau_col + 8 * c->w_off[b], 8 * B.C});
             v.push_back({L.sse_final + 8 * (int64_t)k, 8});
             ents += B.R + B.C;
             ++k;

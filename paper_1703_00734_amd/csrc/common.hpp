@@ -46,7 +46,7 @@ struct SideDesc {
     int64_t sample_off;  // entity 0 in one slot of the sample store
     const double *prior; // shared: [Lambda (K*K), mu (K), Lambda*mu (K)];
                          // per-row: moment-matched rows [Lambda packed, eta, mu]
-    const double *tau;   // this block's noise precision
+    const double *tau;   // this block's noise precision, or (tau_stride 1) one per entity
     const float *pfac;   // per-row priors of FP32/BF16 passes: per entity the inverse
                          // factor of its prior precision (rows of stride pfrow), else null
     int32_t n;           // number of entities
@@ -54,7 +54,17 @@ struct SideDesc {
     uint32_t c2;         // Philox counter word of the conditional draws
     uint32_t c2_init;    // Philox counter word of the initial draws
     int32_t block;       // global block id b = i * J + j
-    int32_t pad_;
+    int32_t tau_stride;  // 0: tau[0] for every entity; 1: tau[n] (per-column precisions, column side)
+};
+
+// Per-column noise precisions of one block of a stage: the columns' tau_d,
+// the row pass's scaled factors sqrt(tau_d) w_d and values sqrt(tau_d) r_nd.
+struct TauColJob {
+    int32_t block;
+    int32_t C;           // columns
+    int64_t w_off;       // first column in the W arrays (and in tau_col)
+    int64_t cptr_off;    // first column in the global CSC pointer array
+    int64_t e0, M;       // the block's CSR entries
 };
 
 // Device-side sweep bookkeeping read by every kernel of a sweep, so one

@@ -546,7 +546,7 @@ __global__ __launch_bounds__(256) void k_update_reg(const UpdArgs a) {
     // A = P + tau G, h = P m + tau hs (identity padding beyond K); the prior is
     // a packed row [P lower (row-major), P m, m]: the side's own row when
     // propagated, the shared Normal-Wishart prior otherwise
-    const Tacc tau = (Tacc)(*sd.tau);
+    const Tacc tau = (Tacc)sd.tau[(int64_t)sd.tau_stride * n];
     const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
     Tacc hraw[SSE ? KC : 1];                // sum r w of the column, for its SSE
     if constexpr (SSE) {
@@ -1214,7 +1214,7 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             }
         }
         __syncthreads();
-        const Tacc tau = (Tacc)(*sd.tau);
+        const Tacc tau = (Tacc)sd.tau[(int64_t)sd.tau_stride * n];
         const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
         const double *pv = pr + K * (K + 1) / 2;
         // packed lower prior, lanes over consecutive entries (coalesced), all
@@ -1290,7 +1290,7 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
             __syncthreads();
             if (lane < KP) sz[lane] = lane < K ? (Tacc)elem_to_d(elem_from<Ts>((double)xv)) : (Tacc)0;
             __syncthreads();
-            const double tauv = (double)(Tacc)(*sd.tau);     // the tau that scaled A
+            const double tauv = (double)tau;                 // the tau that scaled A
             double acc = 0.0;
             if (lane < KP) {
                 // (L^T w)_lane = sum_{p >= lane} L_p,lane w_p (L in sA, row stride LDL)
@@ -1403,7 +1403,7 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         __syncthreads();
         // A = P + tau G, h = P m + tau hs: the packed prior, coalesced over the
         // half's lanes (row of entry q as in the wave kernel)
-        const Tacc tau = (Tacc)(*sd.tau);
+        const Tacc tau = (Tacc)sd.tau[(int64_t)sd.tau_stride * n];
         const double *pr = sd.prior + (sd.per_row ? (int64_t)n * a.prow : 0);
         const int npk = K * (K + 1) / 2;
         constexpr int NQ = (KP * (KP + 1) / 2 + 31) / 32;
@@ -1659,7 +1659,7 @@ __device__ __forceinline__ void group_lowrank_copy(
     const int64_t p0 = a.ptr[sd.ptr_off + n];
     const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
     const int nc = valid && deg <= NC ? deg : 0;
-    const float tau = (float)(*sd.tau);
+    const float tau = (float)sd.tau[(int64_t)sd.tau_stride * n];
     const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * a.ks_other;
     const Tv *val = reinterpret_cast<const Tv *>(a.val);
     __syncthreads();                                 // the previous copies' LDS is read
@@ -2605,6 +2605,47 @@ __global__ __launch_bounds__(64) void k_mm_rows(const MmArgs a) {
             for (int q = r; q < a.prow; q += KP) out[q] = xs[h][q];
             if (a.aux && r == 0) a.aux[item.x][(int64_t)n * 2 + 1] = ld;
         }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Per-column noise precisions (the tau_d variant of Sec. 2.1).  The row
+// conditional with entry weights tau_d, A = P + sum tau_d w_d w_d^T and
+// h = P m + sum tau_d r_nd w_d, is the unweighted one of w~_d = sqrt(tau_d) w_d
+// and r~_nd = sqrt(tau_d) r_nd; k_tau_scale forms both (rounded once to the
+// state and value precision) for the row pass, from the current W and tau.
+// k_tau_cols draws tau_d ~ Gamma(a0 + M_d / 2, b0 + SSE_d / 2) per column, on
+// counter (d, t, (block << 8) | TAU, attempt), with SSE_d the column's
+// residual SSE of this sweep's column pass.
+// --------------------------------------------------------------------------
+template <typename Ts, typename Tv>
+__global__ __launch_bounds__(256) void k_tau_scale(const TauColArgs a) {
+    const TauColJob jb = a.jobs[blockIdx.y];
+    const Ts *W = reinterpret_cast<const Ts *>(a.W) + jb.w_off * a.ks;
+    Ts *Wt = reinterpret_cast<Ts *>(a.Wt) + jb.w_off * a.ks;
+    const double *tau = a.tau + jb.w_off;
+    const int64_t nw = (int64_t)jb.C * a.ks;
+    for (int64_t q = blockIdx.x * 256 + threadIdx.x; q < nw; q += (int64_t)gridDim.x * 256) {
+        const int64_t d = q / a.ks;
+        Wt[q] = (Ts)(sqrt(tau[d]) * (double)W[q]);
+    }
+    const Tv *val = reinterpret_cast<const Tv *>(a.val) + jb.e0;
+    Tv *vt = reinterpret_cast<Tv *>(a.vt) + jb.e0;
+    const int32_t *idx = a.idx + jb.e0;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < jb.M; e += (int64_t)gridDim.x * 256)
+        vt[e] = (Tv)(sqrt(tau[idx[e]]) * (double)val[e]);
+}
+
+__global__ __launch_bounds__(256) void k_tau_cols(const TauColArgs a) {
+    const TauColJob jb = a.jobs[blockIdx.y];
+    const uint32_t t = a.ss ? a.ss->t : a.t;
+    for (int d = blockIdx.x * 256 + threadIdx.x; d < jb.C; d += gridDim.x * 256) {
+        const int64_t m = a.cptr[jb.cptr_off + d + 1] - a.cptr[jb.cptr_off + d];
+        const double *sp = a.sse_col + 4 * (jb.w_off + d);
+        const double sse = ((sp[0] + sp[1]) + sp[2]) + sp[3];
+        const double shape = a.a0 + 0.5 * (double)m;
+        const double rate = a.b0 + 0.5 * sse;
+        a.tau[jb.w_off + d] = gamma_draw(a.k0, a.k1, (uint32_t)d, t, counter_word(jb.block, kTau), shape) / rate;
     }
 }
 
@@ -3722,6 +3763,21 @@ hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s) {
                                      s, a);
     else if (kp <= 64) hipLaunchKernelGGL((k_pfac_rows<64>), dim3(g), dim3(64), 0, s, a);
     else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_tau_scale(int32_t prec, const TauColArgs &a, hipStream_t s) {
+    if (a.njobs <= 0) return hipSuccess;
+    const dim3 grid(256, a.njobs);
+    if (prec == kP64) hipLaunchKernelGGL((k_tau_scale<double, double>), grid, dim3(256), 0, s, a);
+    else if (prec == kP32) hipLaunchKernelGGL((k_tau_scale<float, float>), grid, dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_tau_cols(const TauColArgs &a, hipStream_t s) {
+    if (a.njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tau_cols, dim3(16, a.njobs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

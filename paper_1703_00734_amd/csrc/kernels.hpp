@@ -171,6 +171,26 @@ struct MmArgs {
     double *const *aux;       // per side: (pi, log det Lambda) pairs of entity 0, or null
 };
 
+// Per-column noise precisions: the row pass's scaled copies (sqrt(tau_d) w_d
+// into Wt, sqrt(tau_d) r_nd into vt, in the state / value precision) and the
+// per-column Gamma draws, for the blocks of a stage (grid y = job).
+struct TauColArgs {
+    const TauColJob *jobs;
+    int32_t njobs;
+    double *tau;              // per column (W-array order)
+    const void *W;            // state rows (stride ks)
+    void *Wt;
+    int32_t ks, K;
+    const void *val;          // CSR values
+    void *vt;
+    const int32_t *idx;       // CSR local column ids
+    const int64_t *cptr;      // CSC pointers (global entry offsets)
+    const double *sse_col;    // per column 4 partial sums of its residual SSE
+    double a0, b0;
+    const SweepState *ss;     // sweep index from here when set, else t
+    uint32_t t, k0, k1;
+};
+
 // Components kept per row by the mixture approximation, at most.
 constexpr int kMaxComp = 4;
 // lambda-means: clusters per row, rounds, kept samples per row, at most.
@@ -311,6 +331,8 @@ hipError_t launch_hyper(const HyperArgs &a, int32_t njobs, hipStream_t s);
 hipError_t launch_init(int32_t prec, const InitArgs &a, hipStream_t s);
 hipError_t launch_mm(int32_t prec, const MmArgs &a, hipStream_t s);
 hipError_t launch_lmeans(int32_t prec, const LmeansArgs &a, hipStream_t s);
+hipError_t launch_tau_scale(int32_t prec, const TauColArgs &a, hipStream_t s);
+hipError_t launch_tau_cols(const TauColArgs &a, hipStream_t s);
 hipError_t launch_gmm_pool(const GmmPoolArgs &a, hipStream_t s);
 hipError_t launch_gmm_pick(int32_t prec, const GmmPickArgs &a, hipStream_t s);
 hipError_t launch_pfac(int32_t kp, const PfacArgs &a, hipStream_t s);

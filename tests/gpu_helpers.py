@@ -22,14 +22,15 @@ def small_data(K, seed=1, N=600, D=300, nnz=20000, empty_rows=7, kind="ratings")
 
 def pair(d, K, precision="fp64", I=1, J=1, order="given", seed=11, burnin=0, thin=1, max_kept=4,
          sample_tau=True, tau_fixed=1.0, batched=True, pivot_theta=0.0, lane_nnz=0, approx="mm",
-         lambda_scale=2.0, ncomp=3):
+         lambda_scale=2.0, ncomp=3, tau_per_column=False):
     g = BMF(d["N"], d["D"], K, d["row"], d["col"], d["val"], I=I, J=J, order=order, seed=seed,
             burnin=burnin, thin=thin, max_kept=max_kept, precision=precision,
             sample_tau=sample_tau, tau_fixed=tau_fixed, batched=batched, pivot_theta=pivot_theta,
-            lane_nnz=lane_nnz, approx=approx, lambda_scale=lambda_scale, ncomp=ncomp)
+            lane_nnz=lane_nnz, approx=approx, lambda_scale=lambda_scale, ncomp=ncomp,
+            tau_per_column=tau_per_column)
     o = Oracle(d["N"], d["D"], K, d["row"], d["col"], d["val"], I=I, J=J, order=order, seed=seed,
                burnin=burnin, thin=thin, sample_tau=sample_tau, tau_fixed=tau_fixed, approx=approx,
-               lambda_scale=lambda_scale, ncomp=ncomp)
+               lambda_scale=lambda_scale, ncomp=ncomp, tau_per_column=tau_per_column)
     return g, o
 
 

@@ -127,6 +127,7 @@ def test_validation_errors():
     _expect("BMF_EINVAL", approx="dm", lambda_scale=-1.0)
     _expect("BMF_EUNSUPPORTED", approx="dm", K=33, nu0=33.0)                      # clustering needs K <= 32
     _expect("BMF_EUNSUPPORTED", approx="gmm", max_kept=257)                       # labels of 256 samples at most
+    _expect("BMF_EUNSUPPORTED", tau_per_column=True, precision="bf16")           # tau_d: FP32 and FP64 only
     # ceil partition that leaves the last part empty: N=10, I=6 -> parts of 2
     rng = np.random.default_rng(1)
     cells = rng.choice(100, size=30, replace=False)
