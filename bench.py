@@ -148,7 +148,10 @@ def time_stages(d, cfg, precision, batched, steps, warmup):
     # next stage top up their samples with untimed sweeps
     need = 2 * d["K"] + 2
     extra = max(0, need - (warmup + 2 * steps))
+    t_init = time.perf_counter()
     g = _ctx(d, cfg, precision, batched, CHAIN_SEEDS[0], 0, warmup + 2 * steps + extra)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t_init       # validation, ordering, partition, CSR/CSC, upload
     per_stage = {}
     stages = stages_of(cfg)
     for s in stages:
@@ -208,7 +211,7 @@ def time_stages(d, cfg, precision, batched, steps, warmup):
                             ktimes=ktimes, row_updates=row_updates, ratings=ratings,
                             schedule=g.schedule(), prop_copies=copies, prior_rows=prop,
                             factor_rows=pfac, ents=ents)
-    out = dict(per_stage=per_stage, stats=g.stats())
+    out = dict(per_stage=per_stage, stats=g.stats(), init_s=init_s)
     g.close()
     return out
 
@@ -500,7 +503,7 @@ def main():
         t_arm = sum(v["per_stage"][s]["ms_per_step"] for s in stages)
         arm = {"ms_per_step": t_arm, "ratings_per_s": ratings / (t_arm / 1000.0),
                "row_updates_per_s": row_updates / (t_arm / 1000.0),
-               "fallback_rows": v["stats"]["fallback_rows"], "stages": {}}
+               "fallback_rows": v["stats"]["fallback_rows"], "init_s": v["init_s"], "stages": {}}
         for s_, ps in v["per_stage"].items():
             arm["stages"][str(s_)] = {
                 "ms_per_step": ps["ms_per_step"], "ratings": ps["ratings"], "row_updates": ps["row_updates"],

@@ -169,6 +169,13 @@ typedef struct {
      * sqrt(tau_d) w_d and sqrt(tau_d) r_nd at the start of each sweep), the
      * column update uses its own.  FP32 and FP64 precision only. */
     int32_t tau_per_column;
+    /* bmf_init lays out the ordering, partition and per-block CSR/CSC
+     * (Sec. 5.2) on the GPU by default: a radix sort of one unique key per
+     * entry and order, the same plan as the host planner's; it allocates and
+     * frees its own temporary device memory (about 40 bytes per entry) during
+     * the call.  plan_on_host != 0 keeps the whole plan on the host
+     * (bmf_init_host always does). */
+    int32_t plan_on_host;
 } bmf_config;
 
 /* Fill *cfg with defaults: K = 10, I = J = 1, beta0 = 2, nu0 = K, tau Gamma(1,1)

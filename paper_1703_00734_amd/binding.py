@@ -39,7 +39,7 @@ class bmf_config(ctypes.Structure):
         ("workspace", _vp), ("workspace_bytes", ctypes.c_size_t),
         ("stream", _vp),
         ("approx", _i32), ("lambda_scale", _d), ("ncomp", _i32),
-        ("tau_per_column", _i32),
+        ("tau_per_column", _i32), ("plan_on_host", _i32),
     ]
 
 
@@ -142,7 +142,7 @@ class BMF:
                  nu0=None, W0=None, sample_tau=True, tau_a0=1.0, tau_b0=1.0, tau_fixed=1.0,
                  seed=0, burnin=0, thin=1, max_kept=1, precision="fp32", pivot_theta=0.0,
                  batched=True, lane_nnz=0, device=True, stream=None, approx="mm", lambda_scale=2.0, ncomp=3,
-                 tau_per_column=False):
+                 tau_per_column=False, plan_on_host=False):
         if device:
             # torch's HIP runtime is initialised before the library's is loaded
             import torch
@@ -179,6 +179,7 @@ class BMF:
         c.lambda_scale = float(lambda_scale)
         c.ncomp = int(ncomp)
         c.tau_per_column = 1 if tau_per_column else 0
+        c.plan_on_host = 1 if plan_on_host else 0
         self.cfg = c
         self.ctx = _vp()
         self.workspace = None

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libbmf.so")
-SOURCES = ["kernels.hip", "api.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "planner.cpp", "planner_gpu.hip"]
 ARCH = os.environ.get("BMF_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions stay off in every HIP compile.

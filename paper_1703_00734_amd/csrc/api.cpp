@@ -51,7 +51,7 @@ struct Layout {
     int64_t nb = 0, E_r = 0, E_c = 0, Emax = 0, Pmax = 0;
     int64_t vs = 0, ss = 0, sp = 0;  // value / state / sample element bytes
     // byte offsets
-    int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, ord, X, W, hyper, tau, mu0,
+    int64_t csr_ptr, csr_idx, csr_val, csc_ptr, csc_idx, csc_val, csr_ent, csc_ent, ord, X, W, hyper, tau, mu0,
         W0inv, mm, agg_x, agg_w, sample, probe, sse_col, colsq, sse_final, stats_part, stats_final,
         counters, sweep, fb_list, m_sides, m_tiles, m_reduce, gpart, m_segs, m_splits, nw_noise,
         m_items, m_items2, m_stats, m_hyper, m_mmout, pfac, m_pfout, m_agg_jobs, m_agg_items, p_xslot, p_wslot,
@@ -121,6 +121,9 @@ bool layout_for(const bmf_config &c, Layout &L, std::string &err) {
     L.csc_ptr = take(8 * (L.E_c + L.nb));
     L.csc_idx = take(4 * nnz);
     L.csc_val = take(L.vs * nnz);
+    // COO entry of every CSR / CSC position (device planner: the host keeps none)
+    L.csr_ent = take(c.plan_on_host ? 0 : 4 * nnz);
+    L.csc_ent = take(c.plan_on_host ? 0 : 4 * nnz);
     L.ord = take(4 * (L.E_r + L.E_c));
     L.X = take(L.ss * L.E_r * L.ks_m);
     L.W = take(L.ss * L.E_c * L.ks_m);
@@ -1666,6 +1669,26 @@ bmf_status bmf_workspace_size(const bmf_config *cfg, size_t *bytes) {
     return BMF_OK;
 }
 
+// Per-block offsets into the pointer, factor and entry arrays.
+static void block_offsets(bmf_ctx *c) {
+    int64_t pr = 0, pc = 0, xr = 0, wc = 0, nzb = 0;
+    for (const PlanBlock &B : c->plan.blocks) {
+        c->nz_off[0].push_back(nzb);
+        c->nz_off[1].push_back(nzb);
+        nzb += B.M;
+        c->csr_ptr_off.push_back(pr);
+        c->csc_ptr_off.push_back(pc);
+        c->x_off.push_back(xr);
+        c->w_off.push_back(wc);
+        c->ord_row_off.push_back(xr);
+        c->ord_col_off.push_back(c->L.E_r + wc);
+        pr += B.R + 1;
+        pc += B.C + 1;
+        xr += B.R;
+        wc += B.C;
+    }
+}
+
 static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device) {
     if (!out) return BMF_EINVAL;
     *out = nullptr;
@@ -1718,30 +1741,15 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     for (int64_t e = 0; e < cfg->nnz; ++e) s += (double)cfg->val[e];
     c->ybar = cfg->nnz > 0 ? s / (double)cfg->nnz : 0.0;
     c->fingerprint = data_fingerprint(*cfg);
-    st = build_plan(*cfg, c->plan, err);
-    if (st) {
-        *out = c;
-        c->err = err;
-        return st;
-    }
-    const Plan &P = c->plan;
-    const int64_t nb = (int64_t)P.blocks.size();
-    int64_t pr = 0, pc = 0, xr = 0, wc = 0, nzb = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-        const PlanBlock &B = P.blocks[b];
-        c->nz_off[0].push_back(nzb);
-        c->nz_off[1].push_back(nzb);
-        nzb += B.M;
-        c->csr_ptr_off.push_back(pr);
-        c->csc_ptr_off.push_back(pc);
-        c->x_off.push_back(xr);
-        c->w_off.push_back(wc);
-        c->ord_row_off.push_back(xr);
-        c->ord_col_off.push_back(c->L.E_r + wc);
-        pr += B.R + 1;
-        pc += B.C + 1;
-        xr += B.R;
-        wc += B.C;
+    const bool host_plan = !device || cfg->plan_on_host;
+    if (host_plan) {
+        st = build_plan(*cfg, c->plan, err);
+        if (st) {
+            *out = c;
+            c->err = err;
+            return st;
+        }
+        block_offsets(c);
     }
     *out = c;
     if (!device) return BMF_OK;
@@ -1765,8 +1773,38 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     }
     c->device = true;
     HIPCHK(c, hipMemsetAsync(c->base, 0, (size_t)L.total, c->stream));
-    // CSR / CSC with centred values, degree orders
     const bool fp64 = cfg->precision == BMF_PREC_FP64;
+    if (!host_plan) {
+        // the per-entry half of the plan on the GPU, straight into the workspace
+        GpuPlanDst dst{};
+        dst.csr_ptr = c->dev<int64_t>(L.csr_ptr);
+        dst.csc_ptr = c->dev<int64_t>(L.csc_ptr);
+        dst.csr_idx = c->dev<int32_t>(L.csr_idx);
+        dst.csc_idx = c->dev<int32_t>(L.csc_idx);
+        dst.csr_val = c->dev<void>(L.csr_val);
+        dst.csc_val = c->dev<void>(L.csc_val);
+        dst.csr_ent = c->dev<int32_t>(L.csr_ent);
+        dst.csc_ent = c->dev<int32_t>(L.csc_ent);
+        dst.colsq = c->dev<double>(L.colsq);
+        dst.rowpos = c->dev<int64_t>(L.rowpos);
+        dst.colpos = c->dev<int64_t>(L.colpos);
+        if ((st = gpu_build_plan(*cfg, c->ybar, fp64, c->plan, dst, c->stream, err))) return fail(c, st, err);
+        block_offsets(c);
+        std::vector<int32_t> hord;
+        for (int pass = 0; pass < 2; ++pass) {
+            hord.clear();
+            for (const PlanBlock &B : c->plan.blocks) {
+                std::vector<int32_t> o = degree_order(pass == 0 ? B.csr_ptr : B.csc_ptr);
+                hord.insert(hord.end(), o.begin(), o.end());
+            }
+            if ((st = upload(c, L.ord + (pass == 0 ? 0 : 4 * L.E_r), hord.data(), hord.size() * 4))) return st;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    const Plan &P = c->plan;
+    const int64_t nb = (int64_t)P.blocks.size();
+    // CSR / CSC with centred values, degree orders (host plan)
+    if (host_plan) {
     std::vector<int64_t> hptr;
     std::vector<int32_t> hidx;
     std::vector<double> vd;
@@ -1825,6 +1863,8 @@ static bmf_status init_common(const bmf_config *cfg, bmf_ctx **out, bool device)
     if ((st = upload(c, L.colsq, colsq.data(), colsq.size() * 8))) return st;
     if ((st = upload(c, L.rowpos, P.row_pos.data(), 8 * P.row_pos.size()))) return st;
     if ((st = upload(c, L.colpos, P.col_pos.data(), 8 * P.col_pos.size()))) return st;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     {
         void *sp = nullptr;
         HIPCHK(c, scratch_address(&sp));
@@ -2028,9 +2068,25 @@ bmf_status bmf_get_block_csr(const bmf_ctx *c, int32_t b, int32_t which, int64_t
     if (!c || b < 0 || b >= (int32_t)c->plan.blocks.size() || which < 0 || which > 1) return BMF_EINVAL;
     const PlanBlock &B = c->plan.blocks[b];
     const std::vector<int64_t> &p = which == 0 ? B.csr_ptr : B.csc_ptr;
+    if (ptr) std::copy(p.begin(), p.end(), ptr);
+    if (c->device && !c->cfg.plan_on_host) {
+        // the device planner keeps the local ids and entries on the device only
+        const Layout &L = c->L;
+        const int64_t e0 = c->nz_off[which][b];
+        if (idx && B.M > 0 && hipMemcpy(idx, c->base + (which == 0 ? L.csr_idx : L.csc_idx) + 4 * e0, 4 * B.M,
+                                        hipMemcpyDeviceToHost) != hipSuccess)
+            return BMF_EDEVICE;
+        if (entry && B.M > 0) {
+            std::vector<int32_t> ent((size_t)B.M);
+            if (hipMemcpy(ent.data(), c->base + (which == 0 ? L.csr_ent : L.csc_ent) + 4 * e0, 4 * B.M,
+                          hipMemcpyDeviceToHost) != hipSuccess)
+                return BMF_EDEVICE;
+            std::copy(ent.begin(), ent.end(), entry);
+        }
+        return BMF_OK;
+    }
     const std::vector<int32_t> &i = which == 0 ? B.csr_idx : B.csc_idx;
     const std::vector<int64_t> &e = which == 0 ? B.csr_entry : B.csc_entry;
-    if (ptr) std::copy(p.begin(), p.end(), ptr);
     if (idx) std::copy(i.begin(), i.end(), idx);
     if (entry) std::copy(e.begin(), e.end(), entry);
     return BMF_OK;

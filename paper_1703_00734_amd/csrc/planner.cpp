@@ -10,8 +10,6 @@
 
 namespace bmf {
 
-namespace {
-
 // pos[e] for every entity: its position in the chosen order.
 std::vector<int64_t> make_positions(int64_t n, const std::vector<int64_t> &count, int32_t order,
                                     uint64_t seed, uint32_t purpose) {
@@ -39,6 +37,8 @@ std::vector<int64_t> make_positions(int64_t n, const std::vector<int64_t> &count
     return pos;
 }
 
+namespace {
+
 // One stable counting-sort pass of `perm` by key[perm[k]] in [0, range).
 void counting_pass(std::vector<int64_t> &perm, const std::vector<int64_t> &key, int64_t range) {
     std::vector<int64_t> start(range + 1, 0);
@@ -61,6 +61,23 @@ std::vector<int32_t> degree_order(const std::vector<int64_t> &ptr) {
     return ord;
 }
 
+bmf_status plan_partition(const bmf_config &cfg, Plan &p, std::string &err) {
+    p = Plan();
+    p.N = cfg.N;
+    p.D = cfg.D;
+    p.I = cfg.I;
+    p.J = cfg.J;
+    p.bs_r = (p.N + p.I - 1) / p.I;
+    p.bs_c = (p.D + p.J - 1) / p.J;
+    for (int32_t i = 0; i < p.I; ++i) p.R.push_back(std::min(p.bs_r, p.N - i * p.bs_r));
+    for (int32_t j = 0; j < p.J; ++j) p.C.push_back(std::min(p.bs_c, p.D - j * p.bs_c));
+    if (p.R.back() <= 0 || p.C.back() <= 0) {
+        err = "partition leaves an empty part";
+        return BMF_EINVAL;
+    }
+    return BMF_OK;
+}
+
 bmf_status build_plan(const bmf_config &cfg, Plan &p, std::string &err) {
     p = Plan();
     p.N = cfg.N;
@@ -78,17 +95,17 @@ bmf_status build_plan(const bmf_config &cfg, Plan &p, std::string &err) {
         rc[r] += 1;
         cc[c] += 1;
     }
+    {
+        Plan q;
+        const bmf_status st = plan_partition(cfg, q, err);
+        if (st) return st;
+        p.bs_r = q.bs_r;
+        p.bs_c = q.bs_c;
+        p.R = q.R;
+        p.C = q.C;
+    }
     p.row_pos = make_positions(p.N, rc, cfg.order, cfg.seed, kPermRow);
     p.col_pos = make_positions(p.D, cc, cfg.order, cfg.seed, kPermCol);
-
-    p.bs_r = (p.N + p.I - 1) / p.I;
-    p.bs_c = (p.D + p.J - 1) / p.J;
-    for (int32_t i = 0; i < p.I; ++i) p.R.push_back(std::min(p.bs_r, p.N - i * p.bs_r));
-    for (int32_t j = 0; j < p.J; ++j) p.C.push_back(std::min(p.bs_c, p.D - j * p.bs_c));
-    if (p.R.back() <= 0 || p.C.back() <= 0) {
-        err = "partition leaves an empty part";
-        return BMF_EINVAL;
-    }
 
     // keys of every entry: block, local row, local column
     std::vector<int64_t> blk(nnz), lr(nnz), lc(nnz);

@@ -42,10 +42,13 @@ def test_library_host_half_under_sanitizers():
         pytest.skip("hipcc not available")
     from paper_1703_00734_amd import build as B
     os.makedirs(OUT, exist_ok=True)
-    kobj = os.path.join(B.BUILD, "kernels.o")
-    if not os.path.exists(kobj):
-        os.makedirs(B.BUILD, exist_ok=True)
-        kobj = B._compile("kernels.hip")                   # device code, no sanitizer
+    dev_objs = []
+    for src in ("kernels.hip", "planner_gpu.hip"):         # device code, no sanitizer
+        obj = os.path.join(B.BUILD, os.path.splitext(src)[0] + ".o")
+        if not os.path.exists(obj):
+            os.makedirs(B.BUILD, exist_ok=True)
+            obj = B._compile(src)
+        dev_objs.append(obj)
     host = ["-O1", "-g", "-std=c++17", "--offload-arch=gfx950", "-I" + os.path.join(ROOT, "include"),
             "-I" + B.CSRC, "-Wno-unused-value", "-Wno-unused-result"]
     for f in SAN:
@@ -57,6 +60,6 @@ def test_library_host_half_under_sanitizers():
         _run([hipcc, "-c"] + host + [src, "-o", obj])
         objs.append(obj)
     exe = os.path.join(OUT, "host_driver")
-    _run([hipcc, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address,undefined"] + objs + [kobj, "-o", exe])
+    _run([hipcc, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address,undefined"] + objs + dev_objs + ["-o", exe])
     r = _run([exe], env=ENV, timeout=300)
     assert "host driver done, 0 failures" in r.stdout
