@@ -1662,11 +1662,23 @@ __device__ __forceinline__ void group_lowrank_copy(
     const float tau = (float)sd.tau[(int64_t)sd.tau_stride * n];
     const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * a.ks_other;
     const Tv *val = reinterpret_cast<const Tv *>(a.val);
+    // the entries' rows and values: loads from clamped (valid) positions, the
+    // ones beyond the copy's entries masked, so that only one branch (on a
+    // copy having entries at all) remains
+    float wv[NC], yv = 0.0f;
+#pragma unroll
+    for (int e = 0; e < NC; ++e) wv[e] = 0.0f;
+    if (nc > 0) {
+        const int rr = min(r, K - 1);
+#pragma unroll
+        for (int e = 0; e < NC; ++e)
+            wv[e] = to_acc<float>(other[(int64_t)a.idx[p0 + min(e, nc - 1)] * a.ks_other + rr]);
+        yv = (float)val[p0 + min(r, nc - 1)];
+    }
     __syncthreads();                                 // the previous copies' LDS is read
 #pragma unroll
-    for (int e = 0; e < NC; ++e)
-        sw[e][r] = (e < nc && r < K) ? to_acc<float>(other[(int64_t)a.idx[p0 + e] * a.ks_other + r]) : 0.0f;
-    if (r < NC) sy[r] = r < nc ? (float)val[p0 + r] : 0.0f;
+    for (int e = 0; e < NC; ++e) sw[e][r] = (e < nc && r < K) ? wv[e] : 0.0f;
+    if (r < NC) sy[r] = r < nc ? yv : 0.0f;
     __syncthreads();
     // h = Lambda mu + tau sum_e y_e w_e
     float hs = 0.0f;
@@ -1679,16 +1691,16 @@ __device__ __forceinline__ void group_lowrank_copy(
 #pragma unroll
     for (int e = 0; e < NC; ++e) v[e] = 0.0f;
     {
+        // masked rather than branched: lanes outside row j's range add zeros
         int off = 0;
 #pragma unroll 4
         for (int j = 0; j < K; ++j) {
-            if (j <= r && r < K) {
-                const int q = r - j;
-                const float u = su[off + q];
-                y += u * sb[q];
+            const bool on = j <= r && r < K;
+            const int q = min(max(r - j, 0), K - 1 - j);
+            const float u = on ? su[off + q] : 0.0f;
+            y += u * sb[q];
 #pragma unroll
-                for (int e = 0; e < NC; ++e) v[e] += u * sw[e][q];
-            }
+            for (int e = 0; e < NC; ++e) v[e] += u * sw[e][q];
             off += K - j;
         }
     }
@@ -1734,13 +1746,15 @@ __device__ __forceinline__ void group_lowrank_copy(
     __syncthreads();                                 // h is read
     sb[r] = r < K ? y : 0.0f;
     __syncthreads();
-    // x = U y: U[r][r + j] is entry r of stored row j
+    // x = U y: U[r][r + j] is entry r of stored row j (masked lanes add zeros)
     float acc = 0.0f;
     {
         int off = 0;
 #pragma unroll 8
         for (int j = 0; j < K; ++j) {
-            if (r + j < K) acc += su[off + r] * sb[r + j];
+            const bool on = r + j < K;
+            const int q = min(r, K - 1 - j);
+            acc += (on ? su[off + q] : 0.0f) * sb[q + j];
             off += K - j;
         }
     }
@@ -1844,7 +1858,9 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
                 int off = 0;
 #pragma unroll 8
                 for (int j = 0; j < K; ++j) {
-                    if (r + j < K) acc += su[off + r] * zc[r + j];
+                    const bool on = r + j < K;
+                    const int q = min(r, K - 1 - j);
+                    acc += (on ? su[off + q] : 0.0f) * zc[q + j];
                     off += K - j;
                 }
                 const double *mu = pr + kk2 + K;
