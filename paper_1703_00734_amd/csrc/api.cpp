@@ -30,6 +30,7 @@ constexpr int32_t kFallbackGrid = 128;      // workgroups of the FP64 redo pass
 constexpr int64_t kLightNnz = 16;           // light entities: VALU-Gram or two-per-wavefront kernels
 constexpr int64_t kSegNnz = 2048;           // MFMA path: entities with more entries are split
 constexpr int32_t kWaveGridCap = 1 << 20;
+constexpr int64_t kMfDuoMin = 32768;            // heavy entities of a stage side for the MFMA duo kernel
 
 enum Counter { kFbRow = 0, kFbCol = 1, kFbTotal = 2, kNonPD = 3, kRidged = 4, kCorr = 5, kHyperDone = 6,
                kNumCounters = 16 };
@@ -1022,6 +1023,12 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         // the empty-entity kernel.
         const bool duo = L.kc == 32 && (c->prec() == kP32 || c->prec() == kPBF);
         const bool lsplit = L.mfma || duo;
+        // heavy entities two per wavefront (MFMA Grams) when the stage's side
+        // has enough of them to fill the chip at half as many wavefronts; the
+        // count is the stage's, so batched, per-block and single-step passes
+        // choose alike (the two kernels' arithmetic is the same)
+        const int64_t nheavy = rows ? S.i_row_light - S.i_row_heavy : S.i_col_light - S.i_col_heavy;
+        const bool mf_duo = nheavy >= kMfDuoMin;
         enum { kWave = 0, kLight = 1, kGroup = 2 };
         std::vector<std::pair<int64_t, int64_t>> split;
         std::vector<int> kind;
@@ -1077,9 +1084,12 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
                 b.splits = c->dev<int2>(L.m_splits) + r.first;
                 b.gpart = c->dev<float>(L.gpart);
             }
-            if (kind[ri] == kLight && duo) {
+            if (duo && (kind[ri] == kLight || (L.mfma && mf_duo))) {
+                // two entities per wavefront: light ones with the VALU Gram,
+                // with BF16 state the others with two MFMA Grams
+                const bool mf = kind[ri] != kLight;
                 const int32_t g = (int32_t)std::min<int64_t>((b.nitems + 1) / 2, kWaveGridCap);
-                if ((st = timed(c, kcls, [&] { return launch_update_duo(c->prec(), b, g, c->ls); }))) return st;
+                if ((st = timed(c, kcls, [&] { return launch_update_duo(c->prec(), b, g, c->ls, mf); }))) return st;
                 continue;
             }
             const bool vgram = kind[ri] == kLight;

@@ -1314,11 +1314,14 @@ __global__ __launch_bounds__(64) void k_update_wave(const UpdArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// k_update_duo: two light entities per wavefront (16 < K <= 32, FP32
-// arithmetic).  Lanes 32h .. 32h + 31 hold entity h: lane r owns row r of its
-// Gram, of its factor and of its solves, so the factorisation steps, which
-// leave half of a wavefront idle at one entity per wavefront, serve two.  For
-// entities with at most kDuoNnz entries (their rows are staged in LDS at once).
+// k_update_duo: two entities per wavefront (16 < K <= 32, FP32 arithmetic).
+// Lanes 32h .. 32h + 31 hold entity h: lane r owns row r of its factor and of
+// its solves, so the factorisation steps, which leave half of a wavefront
+// idle at one entity per wavefront, serve two.  The Gram: MF = false, lane r
+// forms row r of its entity's Gram on the VALU, for entities with at most
+// kDuoNnz entries (their rows are staged in LDS at once); MF = true (BF16
+// state), the whole wavefront forms the two Grams one after the other with
+// mfma_gram (or sums a heavy entity's partial Grams), any number of entries.
 // --------------------------------------------------------------------------
 constexpr int kDuoNnz = 16;
 
@@ -1328,7 +1331,7 @@ __device__ __forceinline__ float half_bcast(float v, int q, int hb) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(hb + 4 * q, __float_as_int(v)));
 }
 
-template <int P>
+template <int P, bool MF>
 __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
     using Tacc = typename PrecT<P>::acc;
     using Tw = typename PrecT<P>::w;
@@ -1340,6 +1343,8 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
     constexpr int LDL = KP + 4;                      // 16-byte rows for broadcast loads
     constexpr int CH = kDuoNnz;
     static_assert(CH * KP <= KP * LDL, "staged rows fit the Gram's LDS");
+    static_assert(!MF || P == kPBF, "the MFMA Gram reads BF16 factors");
+    static_assert(gram_stage_bytes<KP>() <= (int)sizeof(Tacc) * KP * LDL, "MFMA staging fits");
     __shared__ __align__(16) Tacc sA[2 * KP * LDL];  // per entity: staged rows, then A, then L
     __shared__ Tacc sr[2 * CH];
     __shared__ Tacc sh[2 * KP];
@@ -1369,7 +1374,7 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         const int n = item.y;
         const int64_t p0 = a.ptr[sd.ptr_off + n];
         const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
-        const bool fits = deg <= CH;                 // else: the FP64 redo takes it
+        const bool fits = MF || deg <= CH;           // else: the FP64 redo takes it
         const int nc = fits ? deg : 0;
         const Tw *other = otherb + sd.other_off * a.ks_other;
         Tacc *A = sA + h * (KP * LDL);
@@ -1378,6 +1383,43 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
 
         __syncthreads();                             // the previous pair is done with the LDS
         Tacc hs = (Tacc)0;
+        if constexpr (MF) {
+            // the two Grams, one after the other, by the whole wavefront (the
+            // chunks are staged in the second entity's A, which its own Gram
+            // overwrites only after its last chunk is read)
+            for (int hq = 0; hq < 2; ++hq) {
+                const int itq = 2 * pit + hq < nitems ? 2 * pit + hq : 2 * pit;
+                const int2 iq = a.items[itq];
+                const SideDesc &sq = a.sides[iq.x];
+                Tacc *Aq = sA + hq * (KP * LDL);
+                Tacc *hq_ = sh + hq * KP;
+                const int2 sp = a.splits ? a.splits[itq] : make_int2(0, 0);
+                if (sp.y > 0) {
+                    // heavy entity: sum its segments' partial Grams in segment order
+                    constexpr int PS = KP * KP + KP;
+                    const float *base = a.gpart + (int64_t)sp.x * PS;
+                    for (int q = lane; q < PS; q += 64) {
+                        const int ra = q / KP, cb = q - ra * KP;
+                        if (q < KP * KP && cb > ra) continue;
+                        float v = 0.0f;
+                        for (int g2 = 0; g2 < sp.y; ++g2) v += base[(int64_t)g2 * PS + q];
+                        if (q < KP * KP) Aq[ra * LDL + cb] = v;
+                        else hq_[q - KP * KP] = v;
+                    }
+                } else {
+                    const int64_t q0 = a.ptr[sq.ptr_off + iq.y], q1 = a.ptr[sq.ptr_off + iq.y + 1];
+                    f32x16_t c00 = {}, c10 = {}, c11 = {};
+                    float hlo = 0.0f, hhi = 0.0f;
+                    mfma_gram<KP>(reinterpret_cast<const uint16_t *>(otherb + sq.other_off * a.ks_other),
+                                  a.ks_other, a.idx, reinterpret_cast<const float *>(val), q0, q1, lane,
+                                  reinterpret_cast<uint16_t *>(sA + KP * LDL), c00, c10, c11, hlo, hhi);
+                    __builtin_amdgcn_wave_barrier();
+                    store_gram<KP, Tacc>(Aq, LDL, hq_, lane, c00, c10, c11, hlo, hhi);
+                }
+                __syncthreads();
+            }
+            hs = hh[r];
+        } else {
         // the entity's rows (zero beyond K) and values, staged in its A
         for (int q = r; q < nc * KP; q += 32) {
             const int e = q / KP, k = q - e * KP;
@@ -1401,6 +1443,7 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
         for (int c = 0; c < KP; ++c) A[r * LDL + c] = g[c];
         hh[r] = hs;
         __syncthreads();
+        }
         // A = P + tau G, h = P m + tau hs: the packed prior, coalesced over the
         // half's lanes (row of entry q as in the wave kernel)
         const Tacc tau = (Tacc)sd.tau[(int64_t)sd.tau_stride * n];
@@ -1643,11 +1686,50 @@ __device__ __forceinline__ float from_next(float x) { return dpp0<0x130>(x); }
 // copy runs beside it (a shorter partner applies identity factors), so
 // per-block launches, whose groups hold one copy, give the same draws.
 // --------------------------------------------------------------------------
+// Products with the dense LDS copy of U (row r at r (KP + 4), so that the
+// lanes' 16-byte row reads fall in distinct banks; zeros left of the
+// diagonal and past K) and vectors that every lane of a half-wave reads by
+// broadcast, four entries per read, summed in index order.  row_dot: lane r
+// forms (U b)_r from its row; col_dots: lane c forms (U^T b_e)_c for NV
+// vectors from its column, one read of U per entry for all of them.
+template <int KP>
+__device__ __forceinline__ float row_dot(const float *urow, const float *s) {
+    const float4 *u4 = reinterpret_cast<const float4 *>(urow);
+    const float4 *s4 = reinterpret_cast<const float4 *>(s);
+    float acc = 0.0f;
+#pragma unroll
+    for (int j = 0; j < KP / 4; ++j) {
+        const float4 u = u4[j], b = s4[j];
+        acc += u.x * b.x;
+        acc += u.y * b.y;
+        acc += u.z * b.z;
+        acc += u.w * b.w;
+    }
+    return acc;
+}
+template <int KP, int NV>
+__device__ __forceinline__ void col_dots(const float *ucol, const float *const (&s)[NV], float (&acc)[NV]) {
+    constexpr int UP = KP + 4;
+#pragma unroll
+    for (int j = 0; j < KP / 4; ++j) {
+        const float u0 = ucol[(4 * j) * UP], u1 = ucol[(4 * j + 1) * UP];
+        const float u2 = ucol[(4 * j + 2) * UP], u3 = ucol[(4 * j + 3) * UP];
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+            const float4 b = reinterpret_cast<const float4 *>(s[e])[j];
+            acc[e] += u0 * b.x;
+            acc[e] += u1 * b.y;
+            acc[e] += u2 * b.z;
+            acc[e] += u3 * b.w;
+        }
+    }
+}
+
 template <int P, int KP, int NC>
 __device__ __forceinline__ void group_lowrank_copy(
-    const UpdArgs &a, const int2 item, const bool valid, const int n, const float *su, const double *pr,
-    float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz], float (&sb)[KP], const float *sz,
-    void *sample, const bool ok, const int lane) {
+    const UpdArgs &a, const int2 item, const bool valid, const int n, const float *ucol,
+    const float *urow, const double *pr, float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz],
+    float (&sb)[KP], const float *sz, void *sample, const bool ok, const int lane) {
     using Tw = typename PrecT<P>::w;
     using Tv = typename PrecT<P>::v;
     using Ts = typename PrecT<P>::s;
@@ -1675,37 +1757,55 @@ __device__ __forceinline__ void group_lowrank_copy(
             wv[e] = to_acc<float>(other[(int64_t)a.idx[p0 + min(e, nc - 1)] * a.ks_other + rr]);
         yv = (float)val[p0 + min(r, nc - 1)];
     }
+#pragma unroll
+    for (int e = 0; e < NC; ++e) wv[e] = (e < nc && r < K) ? wv[e] : 0.0f;
     __syncthreads();                                 // the previous copies' LDS is read
 #pragma unroll
-    for (int e = 0; e < NC; ++e) sw[e][r] = (e < nc && r < K) ? wv[e] : 0.0f;
+    for (int e = 0; e < NC; ++e) sw[e][r] = wv[e];
     if (r < NC) sy[r] = r < nc ? yv : 0.0f;
     __syncthreads();
     // h = Lambda mu + tau sum_e y_e w_e
     float hs = 0.0f;
 #pragma unroll
-    for (int e = 0; e < NC; ++e) hs += sy[e] * sw[e][r];
+    for (int e = 0; e < NC; ++e) hs += sy[e] * wv[e];
     sb[r] = r < K ? (float)pr[kk2 + r] + tau * hs : 0.0f;
-    __syncthreads();
-    // y = U^T h and v_e = U^T w_e: lane c sums U[c - j][c] b[c - j] over j <= c
-    float y = 0.0f, v[NC];
-#pragma unroll
-    for (int e = 0; e < NC; ++e) v[e] = 0.0f;
-    {
-        // masked rather than branched: lanes outside row j's range add zeros
-        int off = 0;
-#pragma unroll 4
-        for (int j = 0; j < K; ++j) {
-            const bool on = j <= r && r < K;
-            const int q = min(max(r - j, 0), K - 1 - j);
-            const float u = on ? su[off + q] : 0.0f;
-            y += u * sb[q];
-#pragma unroll
-            for (int e = 0; e < NC; ++e) v[e] += u * sw[e][q];
-            off += K - j;
-        }
-    }
     int ncw = nc;
     if (64 / KP == 2) ncw = max(nc, __shfl_xor(nc, 32));
+    __syncthreads();
+    // y = U^T h and v_e = U^T w_e: lane c reads column c of U (zeros below
+    // the diagonal) from LDS, the vectors by broadcast; a v_e past both
+    // halves' entry counts is never used
+    float y, v[NC];
+    if (NC == kLowRankSmall || ncw > kLowRankNnz / 2) {
+        const float *vs[NC + 1];
+        float acc[NC + 1];
+        vs[0] = sb;
+        acc[0] = 0.0f;
+#pragma unroll
+        for (int e = 0; e < NC; ++e) {
+            vs[e + 1] = sw[e];
+            acc[e + 1] = 0.0f;
+        }
+        col_dots<KP, NC + 1>(ucol, vs, acc);
+        y = acc[0];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) v[e] = acc[e + 1];
+    } else {
+        constexpr int NH = NC > 1 ? NC / 2 : 1;
+        const float *vs[NH + 1];
+        float acc[NH + 1];
+        vs[0] = sb;
+        acc[0] = 0.0f;
+#pragma unroll
+        for (int e = 0; e < NH; ++e) {
+            vs[e + 1] = sw[e];
+            acc[e + 1] = 0.0f;
+        }
+        col_dots<KP, NH + 1>(ucol, vs, acc);
+        y = acc[0];
+#pragma unroll
+        for (int e = 0; e < NC; ++e) v[e] = e < NH ? acc[e + 1] : 0.0f;
+    }
     float fu[NC], ft[NC], fitm[NC], fid[NC];
 #pragma unroll
     for (int e = 0; e < NC; ++e) {
@@ -1746,18 +1846,8 @@ __device__ __forceinline__ void group_lowrank_copy(
     __syncthreads();                                 // h is read
     sb[r] = r < K ? y : 0.0f;
     __syncthreads();
-    // x = U y: U[r][r + j] is entry r of stored row j (masked lanes add zeros)
-    float acc = 0.0f;
-    {
-        int off = 0;
-#pragma unroll 8
-        for (int j = 0; j < K; ++j) {
-            const bool on = r + j < K;
-            const int q = min(r, K - 1 - j);
-            acc += (on ? su[off + q] : 0.0f) * sb[q + j];
-            off += K - j;
-        }
-    }
+    // x = U y: lane r holds row r of U (zeros left of the diagonal)
+    const float acc = row_dot<KP>(urow, sb);
     const float xv = r < K ? acc : 0.0f;
     const bool wr = valid && ok;
     Ts *self = reinterpret_cast<Ts *>(a.self);
@@ -1783,7 +1873,7 @@ __device__ __forceinline__ void group_lowrank_copy(
 }
 
 template <int P, int KP>
-__global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
+__global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const UpdArgs a) {
     using Ts = typename PrecT<P>::s;
     using Tp = typename PrecT<P>::p;
     constexpr int G = 64 / KP;
@@ -1791,11 +1881,13 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
     constexpr int LPC = KP / 4;                      // lanes per copy in a draw (4 normals each)
     constexpr int CPD = 64 / LPC;                    // copies per draw
     static_assert(WIN % G == 0 && WIN % CPD == 0, "whole copies per window");
-    __shared__ float su[KP * (KP + 1) / 2];          // the group's stored factor U
-    __shared__ float sw[G][kLowRankNnz][KP];         // a copy's entries' rows of the other side
+    constexpr int UP = KP + 4;                       // padded row stride of the dense copy of U
+    constexpr int NQ = (KP * (KP + 1) / 2 + 63) / 64;  // stored entries per lane
+    __shared__ __align__(16) float ud[KP * UP];      // ud[r][j] = U[r][j] (zero left of the diagonal)
+    __shared__ __align__(16) float sw[G][kLowRankNnz][KP];  // a copy's entries' rows of the other side
     __shared__ float sy[G][kLowRankNnz];             // their values
-    __shared__ float sb[G][KP];                      // right-hand side, then the solved vector
-    __shared__ float sz[WIN][KP];                    // noise of the window's copies
+    __shared__ __align__(16) float sb[G][KP];        // right-hand side, then the solved vector
+    __shared__ __align__(16) float sz[WIN][KP];      // noise of the window's copies
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
     uint32_t t_sw = a.t;
@@ -1807,6 +1899,21 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
     Ts *self = reinterpret_cast<Ts *>(a.self);
     const int lane = threadIdx.x;
     const int h = lane / KP, r = lane % KP;
+    for (int q = lane; q < KP * UP; q += 64) ud[q] = 0.0f;
+    // the stored factor holds diagonal d (entries U[p][p + d], p < K - d) from
+    // offset d K - d (d - 1) / 2: where each of this lane's entries goes in ud
+    int dst[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) {
+        const int q = lane + 64 * i;
+        const float fq = (float)(2 * K + 1);
+        int d = (int)((fq - sqrtf(fmaxf(fq * fq - 8.0f * (float)q, 0.0f))) * 0.5f);
+        d = max(0, min(d, K - 1));
+        if ((d + 1) * K - (d + 1) * d / 2 <= q) ++d;
+        if (d * K - d * (d - 1) / 2 > q) --d;
+        const int p = q - (d * K - d * (d - 1) / 2);
+        dst[i] = q < kk2 ? p * UP + p + d : -1;
+    }
     for (int g = blockIdx.x; g < a.ngroups; g += gridDim.x) {
         const int i0 = a.gstart[g];
         const int cnt = a.gstart[g + 1] - i0;        // copies in the group (at most 64)
@@ -1826,7 +1933,10 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
         const int n0 = __popcll(__ballot(lane < cnt && dl == 0));
         const int n2 = __popcll(__ballot(lane < cnt && dl >= 1 && dl <= kLowRankSmall));
         __syncthreads();                             // the previous group's factor is read
-        for (int q = lane; q < kk2; q += 64) su[q] = pf[q];
+        // the group's factor into the dense copy (its zeros were cleared at the start)
+#pragma unroll
+        for (int i = 0; i < NQ; ++i)
+            if (dst[i] >= 0) ud[dst[i]] = pf[lane + 64 * i];
         // windows of WIN copies: their noise in one draw per lane, then the
         // window's copies of each kind, G side by side (the kinds stay in order
         // inside a window, and a copy's draw does not depend on its partner)
@@ -1836,13 +1946,15 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
 #pragma unroll
             for (int d0 = 0; d0 < WIN; d0 += CPD) {
                 const int cw = d0 + lane / LPC, q = lane % LPC;
-                if (w0 + cw < w1 && 4 * q < K) {
-                    const int2 it = a.items[i0 + w0 + cw];
-                    float z[4];
-                    normals4((uint32_t)n, t_sw, a.sides[it.x].c2, (uint32_t)q, a.k0, a.k1, z);
+                if (w0 + cw < w1) {
+                    // entries K .. KP - 1 are zeros (the products read them)
+                    float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    if (4 * q < K) {
+                        const int2 it = a.items[i0 + w0 + cw];
+                        normals4((uint32_t)n, t_sw, a.sides[it.x].c2, (uint32_t)q, a.k0, a.k1, z);
+                    }
 #pragma unroll
-                    for (int e2 = 0; e2 < 4; ++e2)
-                        if (4 * q + e2 < K) sz[cw][4 * q + e2] = z[e2];
+                    for (int e2 = 0; e2 < 4; ++e2) sz[cw][4 * q + e2] = 4 * q + e2 < K ? z[e2] : 0.0f;
                 }
             }
             __syncthreads();
@@ -1853,16 +1965,7 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
                 const int ci = valid ? c + h : c;
                 const int2 item = a.items[i0 + ci];
                 const SideDesc &sd = a.sides[item.x];
-                const float *zc = sz[ci - w0];
-                float acc = 0.0f;
-                int off = 0;
-#pragma unroll 8
-                for (int j = 0; j < K; ++j) {
-                    const bool on = r + j < K;
-                    const int q = min(r, K - 1 - j);
-                    acc += (on ? su[off + q] : 0.0f) * zc[q + j];
-                    off += K - j;
-                }
+                const float acc = row_dot<KP>(ud + r * UP, sz[ci - w0]);
                 const double *mu = pr + kk2 + K;
                 const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
                 const bool wr = valid && ok;
@@ -1877,14 +1980,14 @@ __global__ __launch_bounds__(64) void k_update_group(const UpdArgs a) {
             for (int c = s0; c < s1; c += G) {
                 const bool valid = c + h < s1;
                 const int ci = valid ? c + h : c;
-                group_lowrank_copy<P, KP, kLowRankSmall>(a, a.items[i0 + ci], valid, n, su, pr, sw[h], sy[h], sb[h],
+                group_lowrank_copy<P, KP, kLowRankSmall>(a, a.items[i0 + ci], valid, n, ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
                                                          sz[ci - w0], sample, ok, lane);
             }
             const int b0 = max(n0 + n2, w0);
             for (int c = b0; c < w1; c += G) {
                 const bool valid = c + h < w1;
                 const int ci = valid ? c + h : c;
-                group_lowrank_copy<P, KP, kLowRankNnz>(a, a.items[i0 + ci], valid, n, su, pr, sw[h], sy[h], sb[h],
+                group_lowrank_copy<P, KP, kLowRankNnz>(a, a.items[i0 + ci], valid, n, ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
                                                        sz[ci - w0], sample, ok, lane);
             }
         }
@@ -3633,11 +3736,17 @@ static hipError_t upd_wave_kp(int32_t prec, const UpdArgs &a, int32_t grid, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
+hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s, bool mf) {
     if (grid <= 0) return hipSuccess;
     switch (prec) {
-    case kP32: hipLaunchKernelGGL((k_update_duo<kP32>), dim3(grid), dim3(64), 0, s, a); break;
-    case kPBF: hipLaunchKernelGGL((k_update_duo<kPBF>), dim3(grid), dim3(64), 0, s, a); break;
+    case kP32:
+        if (mf) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_update_duo<kP32, false>), dim3(grid), dim3(64), 0, s, a);
+        break;
+    case kPBF:
+        if (mf) hipLaunchKernelGGL((k_update_duo<kPBF, true>), dim3(grid), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((k_update_duo<kPBF, false>), dim3(grid), dim3(64), 0, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -3646,6 +3755,10 @@ hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipSt
 hipError_t launch_update_group(int32_t kp, int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s) {
     if (grid <= 0 || a.ngroups <= 0) return hipSuccess;
     if (a.K > kp || (kp != 32 && kp != 64)) return hipErrorInvalidValue;
+    // each workgroup clears its dense factor copy and maps the stored entries
+    // once, then strides over groups: about two rounds of resident
+    // workgroups (256 CUs, 16 at a time) spread that set-up over many groups
+    grid = std::min(grid, 8192);
     switch (prec) {
     case kP32:
         if (kp == 32) hipLaunchKernelGGL((k_update_group<kP32, 32>), dim3(grid), dim3(64), 0, s, a);

@@ -309,7 +309,7 @@ hipError_t launch_update_reg(int32_t kc, int32_t prec, const UpdArgs &a, int32_t
                              hipStream_t s);
 // Two entities with at most 16 entries per wavefront, 16 < K <= 32, FP32 or
 // BF16 state (items in pairs: grid counts pairs).
-hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s);
+hipError_t launch_update_duo(int32_t prec, const UpdArgs &a, int32_t grid, hipStream_t s, bool mf);
 // The copies of propagated rows in the sibling blocks of a stage that have at
 // most lowrank_max_nnz() entries, one prior group (copies sharing one stored
 // prior factor) per wavefront; a.items holds the copies grouped, sorted within
