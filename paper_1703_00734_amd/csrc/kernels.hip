@@ -1727,7 +1727,7 @@ __device__ __forceinline__ void col_dots(const float *ucol, const float *const (
 
 template <int P, int KP, int NC>
 __device__ __forceinline__ void group_lowrank_copy(
-    const UpdArgs &a, const int2 item, const bool valid, const int n, const float *ucol,
+    const UpdArgs &a, const int sx, const int64_t p0, const int deg, const bool valid, const int n, const float *ucol,
     const float *urow, const double *pr, float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz],
     float (&sb)[KP], const float *sz, void *sample, const bool ok, const int lane) {
     using Tw = typename PrecT<P>::w;
@@ -1737,9 +1737,7 @@ __device__ __forceinline__ void group_lowrank_copy(
     const int r = lane % KP;
     const int K = a.K;
     const int kk2 = K * (K + 1) / 2;
-    const SideDesc &sd = a.sides[item.x];
-    const int64_t p0 = a.ptr[sd.ptr_off + n];
-    const int deg = (int)(a.ptr[sd.ptr_off + n + 1] - p0);
+    const SideDesc &sd = a.sides[sx];
     const int nc = valid && deg <= NC ? deg : 0;
     const float tau = (float)sd.tau[(int64_t)sd.tau_stride * n];
     const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * a.ks_other;
@@ -1884,6 +1882,7 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
     constexpr int UP = KP + 4;                       // padded row stride of the dense copy of U
     constexpr int NQ = (KP * (KP + 1) / 2 + 63) / 64;  // stored entries per lane
     __shared__ __align__(16) float ud[KP * UP];      // ud[r][j] = U[r][j] (zero left of the diagonal)
+    __shared__ unsigned short dmap[NQ * 64];         // where stored entry q goes in ud (0xFFFF: none)
     __shared__ __align__(16) float sw[G][kLowRankNnz][KP];  // a copy's entries' rows of the other side
     __shared__ float sy[G][kLowRankNnz];             // their values
     __shared__ __align__(16) float sb[G][KP];        // right-hand side, then the solved vector
@@ -1902,7 +1901,6 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
     for (int q = lane; q < KP * UP; q += 64) ud[q] = 0.0f;
     // the stored factor holds diagonal d (entries U[p][p + d], p < K - d) from
     // offset d K - d (d - 1) / 2: where each of this lane's entries goes in ud
-    int dst[NQ];
 #pragma unroll
     for (int i = 0; i < NQ; ++i) {
         const int q = lane + 64 * i;
@@ -1912,7 +1910,7 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
         if ((d + 1) * K - (d + 1) * d / 2 <= q) ++d;
         if (d * K - d * (d - 1) / 2 > q) --d;
         const int p = q - (d * K - d * (d - 1) / 2);
-        dst[i] = q < kk2 ? p * UP + p + d : -1;
+        dmap[q] = q < kk2 ? (unsigned short)(p * UP + p + d) : (unsigned short)0xFFFF;
     }
     for (int g = blockIdx.x; g < a.ngroups; g += gridDim.x) {
         const int i0 = a.gstart[g];
@@ -1923,20 +1921,29 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
         const float *pf = sd0.pfac + (int64_t)n * a.pfrow;
         const double *pr = sd0.prior + (int64_t)n * a.prow;
         const bool ok = pf[kk2] > 0.0f;
-        // the copies' entry counts: none, one or two, three to eight (in that order)
-        int dl = 0;
+        // lane l < cnt holds copy l's side and entry count (none, one or two,
+        // three to eight, in that order; packed as side + count << 24) and its
+        // first entry (entry offsets fit 32 bits: the entry count does), handed
+        // to the lanes that update the copy by cross-lane reads instead of a
+        // chain of loads each
+        int dl = 0, ml = 0, pl = 0;
         if (lane < cnt) {
             const int2 it = a.items[i0 + lane];
             const int64_t po = a.sides[it.x].ptr_off + n;
-            dl = (int)(a.ptr[po + 1] - a.ptr[po]);
+            const int64_t q0 = a.ptr[po];
+            dl = (int)(a.ptr[po + 1] - q0);
+            pl = (int)q0;
+            ml = it.x | (dl << 24);
         }
         const int n0 = __popcll(__ballot(lane < cnt && dl == 0));
         const int n2 = __popcll(__ballot(lane < cnt && dl >= 1 && dl <= kLowRankSmall));
         __syncthreads();                             // the previous group's factor is read
         // the group's factor into the dense copy (its zeros were cleared at the start)
 #pragma unroll
-        for (int i = 0; i < NQ; ++i)
-            if (dst[i] >= 0) ud[dst[i]] = pf[lane + 64 * i];
+        for (int i = 0; i < NQ; ++i) {
+            const int q = lane + 64 * i, dq = dmap[q];
+            if (dq != 0xFFFF) ud[dq] = pf[q];
+        }
         // windows of WIN copies: their noise in one draw per lane, then the
         // window's copies of each kind, G side by side (the kinds stay in order
         // inside a window, and a copy's draw does not depend on its partner)
@@ -1946,13 +1953,11 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
 #pragma unroll
             for (int d0 = 0; d0 < WIN; d0 += CPD) {
                 const int cw = d0 + lane / LPC, q = lane % LPC;
+                const int sxw = __shfl(ml, min(w0 + cw, cnt - 1)) & 0xFFFFFF;
                 if (w0 + cw < w1) {
                     // entries K .. KP - 1 are zeros (the products read them)
                     float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                    if (4 * q < K) {
-                        const int2 it = a.items[i0 + w0 + cw];
-                        normals4((uint32_t)n, t_sw, a.sides[it.x].c2, (uint32_t)q, a.k0, a.k1, z);
-                    }
+                    if (4 * q < K) normals4((uint32_t)n, t_sw, a.sides[sxw].c2, (uint32_t)q, a.k0, a.k1, z);
 #pragma unroll
                     for (int e2 = 0; e2 < 4; ++e2) sz[cw][4 * q + e2] = 4 * q + e2 < K ? z[e2] : 0.0f;
                 }
@@ -1963,8 +1968,7 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
             for (int c = w0; c < e0; c += G) {
                 const bool valid = c + h < e0;
                 const int ci = valid ? c + h : c;
-                const int2 item = a.items[i0 + ci];
-                const SideDesc &sd = a.sides[item.x];
+                const SideDesc &sd = a.sides[__shfl(ml, ci) & 0xFFFFFF];
                 const float acc = row_dot<KP>(ud + r * UP, sz[ci - w0]);
                 const double *mu = pr + kk2 + K;
                 const float xv = r < K ? (float)(mu[r] + (double)acc) : 0.0f;
@@ -1980,14 +1984,18 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
             for (int c = s0; c < s1; c += G) {
                 const bool valid = c + h < s1;
                 const int ci = valid ? c + h : c;
-                group_lowrank_copy<P, KP, kLowRankSmall>(a, a.items[i0 + ci], valid, n, ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
+                const int mc = __shfl(ml, ci);
+                group_lowrank_copy<P, KP, kLowRankSmall>(a, mc & 0xFFFFFF, (int64_t)__shfl(pl, ci), mc >> 24, valid, n,
+                                                         ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
                                                          sz[ci - w0], sample, ok, lane);
             }
             const int b0 = max(n0 + n2, w0);
             for (int c = b0; c < w1; c += G) {
                 const bool valid = c + h < w1;
                 const int ci = valid ? c + h : c;
-                group_lowrank_copy<P, KP, kLowRankNnz>(a, a.items[i0 + ci], valid, n, ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
+                const int mc = __shfl(ml, ci);
+                group_lowrank_copy<P, KP, kLowRankNnz>(a, mc & 0xFFFFFF, (int64_t)__shfl(pl, ci), mc >> 24, valid, n,
+                                                       ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
                                                        sz[ci - w0], sample, ok, lane);
             }
         }
