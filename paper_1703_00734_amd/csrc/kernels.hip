@@ -1727,7 +1727,8 @@ __device__ __forceinline__ void col_dots(const float *ucol, const float *const (
 
 template <int P, int KP, int NC>
 __device__ __forceinline__ void group_lowrank_copy(
-    const UpdArgs &a, const int sx, const int64_t p0, const int deg, const bool valid, const int n, const float *ucol,
+    const UpdArgs &a, const int sx, const int64_t p0, const int deg, const float tau, const bool valid,
+    const int n, const float *ucol,
     const float *urow, const double *pr, float (&sw)[kLowRankNnz][KP], float (&sy)[kLowRankNnz],
     float (&sb)[KP], const float *sz, void *sample, const bool ok, const int lane) {
     using Tw = typename PrecT<P>::w;
@@ -1739,7 +1740,6 @@ __device__ __forceinline__ void group_lowrank_copy(
     const int kk2 = K * (K + 1) / 2;
     const SideDesc &sd = a.sides[sx];
     const int nc = valid && deg <= NC ? deg : 0;
-    const float tau = (float)sd.tau[(int64_t)sd.tau_stride * n];
     const Tw *other = reinterpret_cast<const Tw *>(a.other) + sd.other_off * a.ks_other;
     const Tv *val = reinterpret_cast<const Tv *>(a.val);
     // the entries' rows and values: loads from clamped (valid) positions, the
@@ -1927,10 +1927,13 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
         // to the lanes that update the copy by cross-lane reads instead of a
         // chain of loads each
         int dl = 0, ml = 0, pl = 0;
+        float tl = 0.0f;
         if (lane < cnt) {
             const int2 it = a.items[i0 + lane];
-            const int64_t po = a.sides[it.x].ptr_off + n;
+            const SideDesc &sl = a.sides[it.x];
+            const int64_t po = sl.ptr_off + n;
             const int64_t q0 = a.ptr[po];
+            tl = (float)sl.tau[(int64_t)sl.tau_stride * n];
             dl = (int)(a.ptr[po + 1] - q0);
             pl = (int)q0;
             ml = it.x | (dl << 24);
@@ -1985,7 +1988,8 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
                 const bool valid = c + h < s1;
                 const int ci = valid ? c + h : c;
                 const int mc = __shfl(ml, ci);
-                group_lowrank_copy<P, KP, kLowRankSmall>(a, mc & 0xFFFFFF, (int64_t)__shfl(pl, ci), mc >> 24, valid, n,
+                group_lowrank_copy<P, KP, kLowRankSmall>(a, mc & 0xFFFFFF, (int64_t)__shfl(pl, ci), mc >> 24,
+                                                         __shfl(tl, ci), valid, n,
                                                          ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
                                                          sz[ci - w0], sample, ok, lane);
             }
@@ -1994,7 +1998,8 @@ __global__ __launch_bounds__(64, KP <= 32 ? 4 : 2) void k_update_group(const Upd
                 const bool valid = c + h < w1;
                 const int ci = valid ? c + h : c;
                 const int mc = __shfl(ml, ci);
-                group_lowrank_copy<P, KP, kLowRankNnz>(a, mc & 0xFFFFFF, (int64_t)__shfl(pl, ci), mc >> 24, valid, n,
+                group_lowrank_copy<P, KP, kLowRankNnz>(a, mc & 0xFFFFFF, (int64_t)__shfl(pl, ci), mc >> 24,
+                                                       __shfl(tl, ci), valid, n,
                                                        ud + r, ud + r * UP, pr, sw[h], sy[h], sb[h],
                                                        sz[ci - w0], sample, ok, lane);
             }
