@@ -1387,13 +1387,25 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
             // the two Grams, one after the other, by the whole wavefront (the
             // chunks are staged in the second entity's A, which its own Gram
             // overwrites only after its last chunk is read)
+            // both entities' rows, entry ranges and segment splits first, so
+            // that the second's loads overlap the first's Gram
+            int2 sps[2];
+            int64_t q0s[2], q1s[2];
+            const Tw *oth[2];
+#pragma unroll
             for (int hq = 0; hq < 2; ++hq) {
                 const int itq = 2 * pit + hq < nitems ? 2 * pit + hq : 2 * pit;
                 const int2 iq = a.items[itq];
                 const SideDesc &sq = a.sides[iq.x];
+                sps[hq] = a.splits ? a.splits[itq] : make_int2(0, 0);
+                q0s[hq] = a.ptr[sq.ptr_off + iq.y];
+                q1s[hq] = a.ptr[sq.ptr_off + iq.y + 1];
+                oth[hq] = otherb + sq.other_off * a.ks_other;
+            }
+            for (int hq = 0; hq < 2; ++hq) {
                 Tacc *Aq = sA + hq * (KP * LDL);
                 Tacc *hq_ = sh + hq * KP;
-                const int2 sp = a.splits ? a.splits[itq] : make_int2(0, 0);
+                const int2 sp = sps[hq];
                 if (sp.y > 0) {
                     // heavy entity: sum its segments' partial Grams in segment order
                     constexpr int PS = KP * KP + KP;
@@ -1407,11 +1419,10 @@ __global__ __launch_bounds__(64) void k_update_duo(const UpdArgs a) {
                         else hq_[q - KP * KP] = v;
                     }
                 } else {
-                    const int64_t q0 = a.ptr[sq.ptr_off + iq.y], q1 = a.ptr[sq.ptr_off + iq.y + 1];
                     f32x16_t c00 = {}, c10 = {}, c11 = {};
                     float hlo = 0.0f, hhi = 0.0f;
-                    mfma_gram<KP>(reinterpret_cast<const uint16_t *>(otherb + sq.other_off * a.ks_other),
-                                  a.ks_other, a.idx, reinterpret_cast<const float *>(val), q0, q1, lane,
+                    mfma_gram<KP>(reinterpret_cast<const uint16_t *>(oth[hq]),
+                                  a.ks_other, a.idx, reinterpret_cast<const float *>(val), q0s[hq], q1s[hq], lane,
                                   reinterpret_cast<uint16_t *>(sA + KP * LDL), c00, c10, c11, hlo, hhi);
                     __builtin_amdgcn_wave_barrier();
                     store_gram<KP, Tacc>(Aq, LDL, hq_, lane, c00, c10, c11, hlo, hhi);
