@@ -765,3 +765,30 @@ def test_simulated_data_rmse_in_table4_band(golden_dir, IJ):
     assert abs(rmse - want) <= 0.01
     # the noise floor: no predictor beats the noise standard deviation by much
     assert rmse > 0.99
+
+
+def test_structured_missingness_recipe():
+    """The second simulated scenario of Sec. 5.3: row and column weights equally
+    spaced from 0.9 down to 0.005, cell (n, d) observed with probability
+    w_n w_d.  The paper states that this leaves about 80 % of the cells
+    missing, which fixes the reading of the product as the probability of
+    being observed (as the probability of being missing it would leave about
+    20 %).  Checked: the missing fraction, its closed-form expectation
+    1 - mean(w)^2, and the density falling with the row and column index as
+    the weights do."""
+    d = synth.simulated(3, "structured")
+    N, D = d["N"], d["D"]
+    frac_missing = d["test_row"].size / (N * D)
+    mean_w = np.linspace(0.9, 0.005, N).mean() * np.linspace(0.9, 0.005, D).mean()
+    print("structured: %.4f missing, expected %.4f" % (frac_missing, 1.0 - mean_w))
+    assert abs(frac_missing - 0.8) <= 0.01
+    assert abs(frac_missing - (1.0 - mean_w)) <= 1e-3
+    assert d["row"].size + d["test_row"].size == N * D
+    # observed density per row decile and per column decile decreases
+    rows = np.bincount(d["row"], minlength=N).astype(float)
+    cols = np.bincount(d["col"], minlength=D).astype(float)
+    rdec = np.array([c.mean() for c in np.array_split(rows, 10)])
+    cdec = np.array([c.mean() for c in np.array_split(cols, 10)])
+    assert np.all(np.diff(rdec) < 0) and np.all(np.diff(cdec) < 0)
+    # first row's expected count: w_1 sum_d w_d
+    assert abs(rows[0] / (0.9 * np.linspace(0.9, 0.005, D).sum()) - 1.0) <= 0.05
