@@ -3545,7 +3545,7 @@ __device__ double grp_min_eig(double (&a)[KP], const int K, const int r, const i
 // the sequential algorithm does.  mu* = Lambda*^-1 (Lambda* mu*) by
 // factor_solve_regs.
 template <int KP>
-__global__ __launch_bounds__(64) void k_agg_rows(const AggArgs a) {
+__global__ __launch_bounds__(64, 2) void k_agg_rows(const AggArgs a) {
     constexpr int G = 64 / KP;
     constexpr int LD = KP + 2;                      // doubles; 16-byte rows
     __shared__ __align__(16) double sT[G][KP * LD];
