@@ -1026,7 +1026,7 @@ static bmf_status run_pass(bmf_ctx *c, bool rows, uint32_t t, void *sample, int3
         // heavy entities two per wavefront (MFMA Grams) when the stage's side
         // has enough of them to fill the chip at half as many wavefronts; the
         // count is the stage's, so batched, per-block and single-step passes
-        // choose alike (the two kernels' arithmetic is the same)
+        // choose alike
         const int64_t nheavy = rows ? S.i_row_light - S.i_row_heavy : S.i_col_light - S.i_col_heavy;
         const bool mf_duo = nheavy >= kMfDuoMin;
         enum { kWave = 0, kLight = 1, kGroup = 2 };
