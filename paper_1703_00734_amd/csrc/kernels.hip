@@ -1687,15 +1687,17 @@ __device__ __forceinline__ float from_next(float x) { return dpp0<0x130>(x); }
 // moment-matched row of the same source block (X rows of blocks (i, j), j > 0,
 // from (i, 0); W columns of (i, j), i > 0, from (0, j)) -- that have at most
 // kLowRankNnz entries in their block.  They share the prior's stored factor
-// U = L^-T and its mean, so one wavefront stages U in LDS once and draws
-// every copy from it, 64 / KP copies at a time: copies without entries as
-// x = mu + U z, the others by the product-form rank-one update above.  The
-// host orders a group's copies by entry count (none, one or two, three to
-// eight), so the copies run side by side take the same number of scans, and
-// the two short kinds run a two-vector form.  A copy's arithmetic does not
-// depend on which
-// copy runs beside it (a shorter partner applies identity factors), so
-// per-block launches, whose groups hold one copy, give the same draws.
+// U = L^-T and its mean, so one wavefront expands U once into a dense LDS
+// matrix and draws every copy from it, 64 / KP copies at a time: copies
+// without entries as x = mu + U z, the others by the product-form rank-one
+// update above.  The host orders a group's copies by entry count (none, one
+// or two, three to eight), so the copies run side by side take the same
+// number of scans, and the two short kinds run a two-vector form.  Lane l
+// loads copy l's side, entry range and noise precision at the group's start;
+// the lanes that update a copy take them by cross-lane reads.  Workgroups
+// stride over the groups.  A copy's arithmetic does not depend on which copy
+// runs beside it (a shorter partner applies identity factors), so per-block
+// launches, whose groups hold one copy, give the same draws.
 // --------------------------------------------------------------------------
 // Products with the dense LDS copy of U (row r at r (KP + 4), so that the
 // lanes' 16-byte row reads fall in distinct banks; zeros left of the
